@@ -1,0 +1,107 @@
+/*
+ * qsgs_oracle.h -- CPU oracle for LIETS-QSGS (Wang & Al Kobaisi, "Ultra-Fast 3D
+ * Porous Media Generation: a GPU-Accelerated List-Indexed Explicit Time-Stepping
+ * QSGS Algorithm", arXiv 2602.11734).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, single-threaded reference
+ * that the GPU library is checked against.  Only the test-suite, the package's
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+ * code, header, table or constant with the GPU library, and the GPU library
+ * never calls it.
+ *
+ * Conventions (the integer definitions both sides implement independently):
+ *   grid      uint8 [nz][ny][nx], v = x + nx*(y + ny*z); 0 = pore, 1 = solid.
+ *             The domain is not periodic: off-grid neighbours do not exist.
+ *   direction d = 0..25 enumerates the 26-neighbourhood in the order of
+ *             k = (dx+1) + 3(dy+1) + 9(dz+1), k != 13, d = k - (k > 13);
+ *             class(d) = |dx|+|dy|+|dz|-1 (0 face, 1 edge, 2 corner).
+ *   draws     Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) keyed by the
+ *             64-bit realization key; counters are listed at each function.
+ *
+ * Parity status: every function here is pinned by the CPU tests (known-answer
+ * vectors, closed forms, brute force, scipy dilation, statistics), except where
+ * a function's comment says "parity unpinned".
+ */
+#ifndef QSGS_ORACLE_H
+#define QSGS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Counter tags (word 3 of the Philox counter) separating the draw streams. */
+#define ORC_TAG_SEED    1u
+#define ORC_TAG_GROW_HI 2u
+#define ORC_TAG_GROW_LO 3u
+
+#define ORC_DONE      1
+#define ORC_EXHAUSTED 2
+#define ORC_MAXSTEPS  3
+#define ORC_DEFAULT_MAX_STEPS (1 << 20)
+
+typedef struct {
+  double   solid_fraction; /* phi_s, target solid volume fraction (1 - porosity) */
+  double   seed_prob;      /* S_d, seed (core) probability                        */
+  double   g_ref[3];       /* G_ref for the face, edge, corner classes             */
+  int32_t  spacing;        /* s: minimum pairwise L1 seed distance; s <= 1 = none  */
+  int32_t  max_steps;      /* <= 0 selects ORC_DEFAULT_MAX_STEPS                    */
+  uint64_t key;            /* Philox key: k0 = low 32 bits, k1 = high 32 bits      */
+} orc_params;
+
+typedef struct {
+  int64_t n_candidates, n_seeds, solid_count, target_count, front_size;
+  int32_t steps, status;
+} orc_result;
+
+/* Philox4x32-10 block function. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Directions: offsets and class of direction d (0..25). */
+void orc_direction(int32_t d, int32_t* dx, int32_t* dy, int32_t* dz, int32_t* cls);
+
+/* Probability -> 32-bit threshold: min(2^32, floor(p * 2^32)); event iff w < T. */
+uint64_t orc_prob_threshold(double p);
+
+/* Target solid count S* = ceil(phi_s * N), the loop runs while count < S*. */
+int64_t orc_target_count(double phi_s, int64_t n);
+
+/* Eq. (1) at solid count cnt < S*: floor(T_ref * (20 S* - 19 cnt) / S*), capped at 2^32. */
+uint64_t orc_growth_threshold(uint64_t t_ref, int64_t cnt, int64_t s_star);
+
+/* Growth draw for the j-th void direction of source a at step t (32-bit value). */
+uint32_t orc_growth_draw(uint64_t key, int32_t a, uint32_t t, int32_t j);
+
+/* Seed candidates {v : w0(v) < t_seed} in ascending v, with 64-bit priorities. */
+int64_t orc_seed_candidates(int32_t nx, int32_t ny, int32_t nz, uint64_t key, uint64_t t_seed,
+                            int32_t* cand, uint64_t* prio, int64_t cap);
+
+/* Greedy seed acceptance in ascending (priority, v); writes 1 at seeds into a zeroed grid. */
+int64_t orc_seed_select(int32_t nx, int32_t ny, int32_t nz, int32_t spacing, int64_t n_cand,
+                        const int32_t* cand, const uint64_t* prio, uint8_t* grid);
+
+/* Interface: solid voxels with at least one in-domain void 26-neighbour, ascending v. */
+int64_t orc_interface(int32_t nx, int32_t ny, int32_t nz, const uint8_t* grid, int32_t* out);
+
+/* One growth step in the list-indexed form (Algorithm 3).  Returns |A_next|. */
+int64_t orc_step_liets(int32_t nx, int32_t ny, int32_t nz, uint8_t* grid, const int32_t* A,
+                       int64_t nA, uint32_t t, const uint64_t T[3], uint64_t key,
+                       int32_t* A_next, int64_t* n_new, uint32_t* mask_scratch,
+                       int32_t* new_scratch, uint64_t* attempts, uint64_t* successes);
+
+/* One growth step in the full-field form (Algorithm 2).  Returns the number grown. */
+int64_t orc_step_fullfield(int32_t nx, int32_t ny, int32_t nz, uint8_t* grid, uint32_t t,
+                           const uint64_t T[3], uint64_t key);
+
+/* Whole generation (seeding, then the list-indexed loop).  Optional outputs may be NULL:
+ * birth[v] = step at which v became solid (0 for seeds, -1 for pore), and per-step logs
+ * of |F_t|, |New_t| and the solid count at the start of step t (log_cap entries). */
+int32_t orc_generate(int32_t nx, int32_t ny, int32_t nz, const orc_params* p, uint8_t* grid,
+                     orc_result* res, int32_t* birth, int64_t* log_front, int64_t* log_new,
+                     int64_t* log_count, int32_t log_cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,117 @@
+"""Whole-run pins of the oracle's generation loop (Sec. 2.3 step 5, Algorithm 3)."""
+import numpy as np
+import pytest
+
+from tests import ref_tiny
+
+
+def _replay_check(orc, dims, run, key, g_ref, spacing):
+    """Reconstruct G_t from the birth map and check every step: a voxel born at
+    t+1 has a passing draw from a solid neighbour of G_t (reachability), and no
+    void voxel of G_{t+1} has one (completeness)."""
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    birth = run.birth.ravel()
+    s_star = run.target_count
+    t_ref = [orc.prob_threshold(g) for g in g_ref]
+    offs = ref_tiny.OFFSETS
+    for t in range(run.steps):
+        solid = (birth >= 0) & (birth <= t)
+        cnt = int(solid.sum())
+        assert cnt == run.log_count[t]
+        T = [orc.growth_threshold(tr, cnt, s_star) for tr in t_ref]
+        grown = set()
+        for a in np.flatnonzero(solid):
+            ax, ay, az = a % nx, (a // nx) % ny, a // (nx * ny)
+            j = 0
+            for d, (dx, dy, dz) in enumerate(offs):
+                qx, qy, qz = ax + dx, ay + dy, az + dz
+                if not (0 <= qx < nx and 0 <= qy < ny and 0 <= qz < nz):
+                    continue
+                q = qx + nx * (qy + ny * qz)
+                if solid[q]:
+                    continue
+                if orc.growth_draw(key, int(a), t, j) < T[ref_tiny.CLASSES[d]]:
+                    grown.add(int(q))
+                j += 1
+        born = set(int(v) for v in np.flatnonzero(birth == t + 1))
+        assert born == grown, t
+    assert int((birth >= 0).sum()) == run.solid_count
+    assert run.solid_count <= n
+
+
+def test_small_run_replays_exactly(orc):
+    dims = (14, 11, 9)
+    g_ref = (0.02, 0.008, 0.002)
+    run = orc.generate(dims, 0.6, 0.01, g_ref, 3, key=41, birth=True, log_cap=10000)
+    assert run.status == orc.DONE
+    _replay_check(orc, dims, run, 41, g_ref, 3)
+
+
+@pytest.mark.parametrize("key", [0, 1])
+def test_config_like_run_invariants(orc, key):
+    dims = (48, 40, 32)
+    g_ref = (0.02, 0.005, 0.00125)
+    run = orc.generate(dims, 0.7, 0.005, g_ref, 4, key=key, birth=True, log_cap=10000)
+    n = 48 * 40 * 32
+    assert run.status == orc.DONE
+    # overshoot: the last step starts below the target and ends at or above it
+    assert run.log_count[-1] < run.target_count <= run.solid_count
+    # monotone growth; counts follow the per-step new counts
+    counts = np.append(run.log_count, run.solid_count)
+    assert np.all(np.diff(counts) >= 0)
+    assert np.array_equal(np.diff(counts), run.log_new)
+    assert run.log_count[0] == run.n_seeds
+    # seeds are the birth-0 voxels, pairwise L1 >= s, and form the first front
+    seeds = np.flatnonzero(run.birth.ravel() == 0)
+    assert len(seeds) == run.n_seeds
+    c = np.stack([seeds % 48, (seeds // 48) % 40, seeds // (48 * 40)], -1)
+    dist = np.abs(c[:, None] - c[None]).sum(-1)
+    np.fill_diagonal(dist, 99)
+    assert dist.min() >= 4
+    assert run.log_front[0] == len(seeds)  # isolated seeds are all interface cells
+    # final grid equals the birth map, front equals the interface
+    assert np.array_equal(run.grid.ravel(), (run.birth.ravel() >= 0).astype(np.uint8))
+    assert run.front_size == len(orc.interface(run.grid))
+    assert run.solid_count == int(run.grid.sum()) < n
+
+
+def test_replay_with_overlapping_seeds(orc):
+    """s <= 1 allows adjacent seeds, so the first front can exclude buried seeds."""
+    dims = (10, 9, 8)
+    g_ref = (0.05, 0.02, 0.01)
+    run = orc.generate(dims, 0.9, 0.35, g_ref, 0, key=9, birth=True, log_cap=1000)
+    _replay_check(orc, dims, run, 9, g_ref, 0)
+    g0 = (run.birth >= 0) & (run.birth <= 0)
+    assert run.log_front[0] == len(orc.interface(g0.astype(np.uint8)))
+
+
+def test_status_exhausted_without_seeds(orc):
+    run = orc.generate((8, 8, 8), 0.5, 0.0, (0.1, 0.1, 0.1), 0, key=1, log_cap=10)
+    assert run.status == orc.EXHAUSTED and run.steps == 0 and run.solid_count == 0
+
+
+def test_status_max_steps_without_growth(orc):
+    run = orc.generate((8, 8, 8), 0.5, 0.01, (0.0, 0.0, 0.0), 0, key=1, max_steps=7,
+                       log_cap=10)
+    assert run.status == orc.MAXSTEPS and run.steps == 7
+    assert run.solid_count == run.n_seeds and run.n_seeds > 0
+
+
+def test_status_done_when_seeds_reach_target(orc):
+    run = orc.generate((6, 6, 6), 0.5, 1.0, (0.1, 0.1, 0.1), 0, key=1, log_cap=10)
+    assert run.status == orc.DONE and run.steps == 0 and run.solid_count == 216
+    assert run.front_size == 0
+
+
+def test_full_fill_terminates(orc):
+    """phi_s = 1 needs every voxel; growth with p = 1 fills the grid."""
+    run = orc.generate((7, 6, 5), 1.0, 0.02, (1.0, 1.0, 1.0), 2, key=3, log_cap=100)
+    assert run.status == orc.DONE and run.solid_count == 210 and run.front_size == 0
+
+
+def test_single_voxel_domain(orc):
+    run = orc.generate((1, 1, 1), 1.0, 1.0, (0.5, 0.5, 0.5), 5, key=0, log_cap=4)
+    assert run.status == orc.DONE and run.solid_count == 1 and run.steps == 0
+    run = orc.generate((1, 1, 1), 1.0, 0.0, (0.5, 0.5, 0.5), 5, key=0, log_cap=4)
+    assert run.status == orc.EXHAUSTED and run.solid_count == 0
