@@ -1,0 +1,169 @@
+/*
+ * qsgs.h -- C ABI of libqsgs: LIETS-QSGS porous-media generation on MI355X (gfx950).
+ *
+ * The method is the list-indexed explicit time-stepping (LIETS) formulation of QSGS
+ * (Wang & Al Kobaisi, arXiv 2602.11734): seeds are drawn with a seed probability
+ * (Sec. 2.1 step 2) and spaced by a diamond (L1) exclusion zone (Sec. 2.3, Fig. 1D);
+ * then, while the solid fraction is below its target and the active front is not
+ * empty, every front voxel tries each of its 26 neighbours with the directional
+ * growth probability of Eq. (1), and the front is rebuilt from the old front and
+ * the newly solid voxels (Sec. 2.3 steps 2-5, Algorithm 3).
+ *
+ * Integer definitions (bit-exact, shared by contract with the CPU oracle):
+ *   grid       uint8, voxel v = x + nx*(y + ny*z), 0 = pore, 1 = solid; not periodic.
+ *   directions d = 0..25: k = (dx+1) + 3(dy+1) + 9(dz+1), k != 13, d = k - (k > 13);
+ *              class = |dx|+|dy|+|dz|-1 (0 face, 1 edge, 2 corner).
+ *   draws      Philox4x32-10 (Salmon et al., SC'11), key = the 64-bit params.key
+ *              (word 0 = low 32 bits).  Seeding of v: counter (v, 0, 0, 1), v is a
+ *              candidate iff word0 < floor(S_d 2^32), its priority is (word1<<32|word2, v).
+ *              Growth at step t from solid a: the j-th in-domain void neighbour of a
+ *              (ascending d) draws (H<<16)|L, H and L being the 16-bit half (j&1) of word
+ *              (j>>1)&3 of the blocks at counters (a, t, j>>3, 2) and (a, t, j>>3, 3);
+ *              the neighbour grows iff the draw < T_class.
+ *   thresholds T_ref = min(2^32, floor(G_ref 2^32)); S* = ceil(phi_s N) in binary64;
+ *              Eq. (1) at solid count c < S*: T = min(2^32, floor(T_ref (20 S* - 19 c) / S*)).
+ *   spacing    candidates at L1 distance 1..s-1 conflict; seeds = greedy acceptance in
+ *              ascending priority (lexicographically-first maximal independent set).
+ *   front      F_t = solid voxels with an in-domain void 26-neighbour (a set; the order
+ *              of a front list is unspecified).
+ *   loop       while count < S* and F non-empty and step < max_steps.
+ *
+ * Conventions for every function:
+ *   - Functions never throw; they return a qsgs_status.  Values >= 0 are normal
+ *     outcomes, values < 0 are errors, and qsgs_last_error() describes the last error
+ *     raised on the calling thread.
+ *   - Device pointers are caller-owned device memory (hipMalloc or torch allocations);
+ *     the library never allocates or frees device memory on these paths.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it;
+ *     functions that return host-visible results (every qsgs_info output) synchronise it.
+ *   - Calls that share a workspace, grid or front buffer must not overlap in time.
+ */
+#ifndef QSGS_H
+#define QSGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QSGS_OK = 0,            /* a growth step ran; the loop may continue                    */
+  QSGS_DONE = 1,          /* solid count >= S* (target solid fraction reached)           */
+  QSGS_EXHAUSTED = 2,     /* the front is empty while the count is below the target      */
+  QSGS_MAXSTEPS = 3,      /* params.max_steps growth steps were taken                    */
+  QSGS_ERR_INVALID = -1,  /* bad argument; nothing was launched                          */
+  QSGS_ERR_CAPACITY = -2, /* a front list would exceed front_cap; state left unchanged   */
+  QSGS_ERR_WORKSPACE = -3,/* ws_bytes below the size the query functions return          */
+  QSGS_ERR_DEVICE = -4    /* a HIP runtime error; the message names the call             */
+} qsgs_status;
+
+typedef struct {
+  int32_t nx, ny, nz;     /* each >= 1 and nx*ny*nz < 2^31                                */
+} qsgs_dims;
+
+typedef struct {
+  double   solid_fraction;/* phi_s in (0, 1]: target solid volume fraction = 1 - porosity */
+  double   seed_prob;     /* S_d in [0, 1]: seed (core) probability, Sec. 2.1 step 2       */
+  double   g_ref[3];      /* G_ref of the face, edge and corner classes, each in [0, 1]    */
+  int32_t  spacing;       /* s >= 0: minimum pairwise L1 seed distance; s <= 1 = none       */
+  int32_t  max_steps;     /* growth step cap; <= 0 selects 2^20                             */
+  uint64_t key;           /* Philox key of the realization                                  */
+} qsgs_params;
+
+typedef struct {
+  int64_t n_candidates;   /* voxels whose seed draw passed                                 */
+  int64_t n_seeds;        /* accepted seeds (after spacing)                                 */
+  int64_t solid_count;    /* solid voxels now                                               */
+  int64_t target_count;   /* S* = ceil(phi_s N)                                             */
+  int64_t front_size;     /* |F_t| now                                                      */
+  int64_t grown_last_step;/* |New| of the last step taken                                   */
+  int32_t step;           /* growth steps taken so far (t)                                  */
+  int32_t status;         /* a qsgs_status value >= 0                                       */
+} qsgs_info;
+
+/* Bytes a grid buffer needs: N rounded up to a multiple of 4 (the growth step claims
+ * voxels with 32-bit atomics).  The voxels occupy the first N bytes; the rest is
+ * padding the library never changes.  0 for invalid dims. */
+size_t qsgs_grid_bytes(const qsgs_dims* dims);
+
+/* Workspace bytes for qsgs_seed and qsgs_generate with these dims and parameters
+ * (seed-candidate lists, spacing buckets, the two front lists used by qsgs_generate,
+ * loop control and the per-step log).  0 for invalid arguments. */
+size_t qsgs_workspace_bytes(const qsgs_dims* dims, const qsgs_params* params);
+
+/* Workspace bytes for qsgs_grow_step (loop control only; independent of the size). */
+size_t qsgs_step_workspace_bytes(void);
+
+/* Seeding (Sec. 2.1 step 2; spacing Sec. 2.3 / Fig. 1D) and the initial active front
+ * (Sec. 2.3 step 2).
+ *   d_grid   device, qsgs_grid_bytes(dims) bytes, 4-byte aligned; overwritten: 1 at seeds,
+ *            0 elsewhere.
+ *   d_front  device int32[front_cap]; receives F_0 (linear voxel indices, any order).
+ *   d_ws     device workspace of ws_bytes >= qsgs_workspace_bytes(dims, params).
+ *   info     host; on return: n_candidates, n_seeds, solid_count = n_seeds, target_count,
+ *            front_size = |F_0|, grown_last_step = 0, step = 0, status = the DEF-9 status
+ *            of the initial state (QSGS_OK if growth should run).
+ * Errors: QSGS_ERR_INVALID (bad dims/params/pointers), QSGS_ERR_WORKSPACE,
+ * QSGS_ERR_CAPACITY (|F_0| > front_cap; d_front untouched beyond front_cap),
+ * QSGS_ERR_DEVICE.  Synchronises `stream`. */
+qsgs_status qsgs_seed(const qsgs_dims* dims, const qsgs_params* params, uint8_t* d_grid,
+                      int32_t* d_front, int64_t front_cap, void* d_ws, size_t ws_bytes,
+                      qsgs_info* info, void* stream);
+
+/* One growth step t (Sec. 2.3 steps 3-4, Algorithm 3, Eq. (1)).
+ *   d_grid      device grid holding G_t (values 0/1); becomes G_{t+1}.
+ *   d_front_in  device int32[front_cap] holding F_t in its first info->front_size
+ *               entries (as written by qsgs_seed or a previous qsgs_grow_step).  The
+ *               step appends this step's new voxels after them (entries beyond
+ *               front_size are scratch); entries [0, front_size) are preserved.
+ *   d_front_out device int32[front_cap], must not overlap d_front_in; receives F_{t+1}.
+ *   d_ws        device workspace, ws_bytes >= qsgs_step_workspace_bytes().
+ *   info        host, in: step, solid_count, front_size (as returned by the previous call);
+ *               out: updated fields, grown_last_step = |New_t|, status per DEF-9.  When the
+ *               input status is already >= 1 (done, exhausted, max steps) nothing runs.
+ * Errors: QSGS_ERR_INVALID, QSGS_ERR_WORKSPACE, QSGS_ERR_DEVICE, and QSGS_ERR_CAPACITY
+ * when |F_t| + |New_t| > front_cap: the grid is restored to G_t, info is unchanged, and
+ * the call can be retried with larger buffers (front_cap >= N never overflows).
+ * Synchronises `stream`. */
+qsgs_status qsgs_grow_step(const qsgs_dims* dims, const qsgs_params* params, uint8_t* d_grid,
+                           int32_t* d_front_in, int32_t* d_front_out, int64_t front_cap,
+                           void* d_ws, size_t ws_bytes, qsgs_info* info, void* stream);
+
+/* Whole generation: qsgs_seed, then growth steps until DEF-9 stops (Sec. 2.3 step 5).
+ * The loop runs on the device; the host reads the loop status once per chunk of steps.
+ *   d_grid  device, qsgs_grid_bytes(dims) bytes, 4-byte aligned; receives the final grid.
+ *   d_ws    device workspace, ws_bytes >= qsgs_workspace_bytes(dims, params); on return it
+ *           holds the per-step log read by qsgs_read_step_log.
+ *   info    host; receives the final counts, steps and status (DONE/EXHAUSTED/MAXSTEPS).
+ * Errors: QSGS_ERR_INVALID, QSGS_ERR_WORKSPACE, QSGS_ERR_DEVICE.  Synchronises `stream`. */
+qsgs_status qsgs_generate(const qsgs_dims* dims, const qsgs_params* params, uint8_t* d_grid,
+                          void* d_ws, size_t ws_bytes, qsgs_info* info, void* stream);
+
+/* Copies the per-step log of the last qsgs_generate that used this workspace into host
+ * arrays (any may be NULL): front[t] = |F_t|, grown[t] = |New_t|, count[t] = solid count
+ * at the start of step t, for t < min(steps, max_entries, 65536).  Returns the number of
+ * entries written (>= 0) or a negative qsgs_status.  Synchronises `stream`. */
+int64_t qsgs_read_step_log(const void* d_ws, size_t ws_bytes, int64_t* front, int64_t* grown,
+                           int64_t* count, int64_t max_entries, void* stream);
+
+/* Kernel timing for measurement.  While enabled (enable != 0), qsgs_generate records HIP
+ * events around each growth-sweep and prune launch on its stream and accumulates their
+ * durations; qsgs_profile_read returns (and with reset != 0 clears) the totals:
+ * out[0] = grow launches, out[1] = grow milliseconds, out[2] = prune launches,
+ * out[3] = prune milliseconds, out[4] = seeding milliseconds (draw to first front). */
+void qsgs_profile_enable(int32_t enable);
+void qsgs_profile_read(double out[5], int32_t reset);
+
+/* Description of the last error on the calling thread ("" if none).  The pointer stays
+ * valid until the next library call on this thread. */
+const char* qsgs_last_error(void);
+
+/* Library version string, e.g. "qsgs 0.1.0 gfx950". */
+const char* qsgs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSGS_H */

@@ -1,0 +1,238 @@
+"""LIETS-QSGS porous-media generation on MI355X (gfx950).
+
+A thin ctypes binding of ``libqsgs.so`` (C ABI in ``include/qsgs.h``): every function
+below marshals arguments and calls the library of the same name.  Device memory and
+streams come from torch (``torch.empty(..., device="cuda")`` and
+``torch.cuda.current_stream()``); every step of the method runs in the HIP kernels.
+There is no CPU fallback: using the package without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libqsgs.so")
+
+OK, DONE, EXHAUSTED, MAXSTEPS = 0, 1, 2, 3
+ERR_INVALID, ERR_CAPACITY, ERR_WORKSPACE, ERR_DEVICE = -1, -2, -3, -4
+STATUS_NAMES = {OK: "ok", DONE: "done", EXHAUSTED: "exhausted", MAXSTEPS: "max_steps",
+                ERR_INVALID: "invalid", ERR_CAPACITY: "capacity", ERR_WORKSPACE: "workspace",
+                ERR_DEVICE: "device"}
+
+
+class QsgsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class qsgs_dims(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class qsgs_params(ctypes.Structure):
+    _fields_ = [("solid_fraction", ctypes.c_double), ("seed_prob", ctypes.c_double),
+                ("g_ref", ctypes.c_double * 3), ("spacing", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("key", ctypes.c_uint64)]
+
+
+class qsgs_info(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int64), ("n_seeds", ctypes.c_int64),
+                ("solid_count", ctypes.c_int64), ("target_count", ctypes.c_int64),
+                ("front_size", ctypes.c_int64), ("grown_last_step", ctypes.c_int64),
+                ("step", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+# Every symbol the header declares, with its ctypes signature.
+_P = ctypes.POINTER
+_VP, _SZ, _I64, _I32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int32
+SIGNATURES = {
+    "qsgs_grid_bytes": (_SZ, [_P(qsgs_dims)]),
+    "qsgs_workspace_bytes": (_SZ, [_P(qsgs_dims), _P(qsgs_params)]),
+    "qsgs_step_workspace_bytes": (_SZ, []),
+    "qsgs_seed": (ctypes.c_int, [_P(qsgs_dims), _P(qsgs_params), _VP, _VP, _I64, _VP, _SZ,
+                                 _P(qsgs_info), _VP]),
+    "qsgs_grow_step": (ctypes.c_int, [_P(qsgs_dims), _P(qsgs_params), _VP, _VP, _VP, _I64, _VP,
+                                      _SZ, _P(qsgs_info), _VP]),
+    "qsgs_generate": (ctypes.c_int, [_P(qsgs_dims), _P(qsgs_params), _VP, _VP, _SZ,
+                                     _P(qsgs_info), _VP]),
+    "qsgs_read_step_log": (_I64, [_VP, _SZ, _VP, _VP, _VP, _I64, _VP]),
+    "qsgs_profile_enable": (None, [_I32]),
+    "qsgs_profile_read": (None, [_VP, _I32]),
+    "qsgs_last_error": (ctypes.c_char_p, []),
+    "qsgs_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libqsgs.so (built by ``__graft_entry__.build()``); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+# ----- argument marshalling helpers -----
+
+def make_dims(dims) -> qsgs_dims:
+    if isinstance(dims, qsgs_dims):
+        return dims
+    nx, ny, nz = (int(v) for v in dims)
+    return qsgs_dims(nx, ny, nz)
+
+
+def make_params(solid_fraction: float, seed_prob: float, g_ref, spacing: int, key: int,
+                max_steps: int = 0) -> qsgs_params:
+    g = (ctypes.c_double * 3)(*[float(v) for v in g_ref])
+    return qsgs_params(float(solid_fraction), float(seed_prob), g, int(spacing), int(max_steps),
+                       int(key) & 0xFFFFFFFFFFFFFFFF)
+
+
+def params_of(case) -> qsgs_params:
+    return make_params(case.solid_fraction, case.seed_prob, case.g_ref, case.spacing, case.key,
+                       case.max_steps)
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise QsgsError(status, qsgs_last_error())
+    return status
+
+
+# ----- the C ABI, one function each -----
+
+def qsgs_grid_bytes(dims) -> int:
+    return int(load().qsgs_grid_bytes(ctypes.byref(make_dims(dims))))
+
+
+def qsgs_workspace_bytes(dims, params: qsgs_params) -> int:
+    return int(load().qsgs_workspace_bytes(ctypes.byref(make_dims(dims)), ctypes.byref(params)))
+
+
+def qsgs_step_workspace_bytes() -> int:
+    return int(load().qsgs_step_workspace_bytes())
+
+
+def qsgs_seed(dims, params, grid, front, front_cap: int, ws, ws_bytes: int,
+              info: qsgs_info | None = None, stream=None) -> tuple[int, qsgs_info]:
+    info = info if info is not None else qsgs_info()
+    st = load().qsgs_seed(ctypes.byref(make_dims(dims)), ctypes.byref(params), _ptr(grid),
+                          _ptr(front), int(front_cap), _ptr(ws), int(ws_bytes),
+                          ctypes.byref(info), _stream(stream))
+    return _check(st), info
+
+
+def qsgs_grow_step(dims, params, grid, front_in, front_out, front_cap: int, ws, ws_bytes: int,
+                   info: qsgs_info, stream=None) -> tuple[int, qsgs_info]:
+    st = load().qsgs_grow_step(ctypes.byref(make_dims(dims)), ctypes.byref(params), _ptr(grid),
+                               _ptr(front_in), _ptr(front_out), int(front_cap), _ptr(ws),
+                               int(ws_bytes), ctypes.byref(info), _stream(stream))
+    return _check(st), info
+
+
+def qsgs_generate(dims, params, grid, ws, ws_bytes: int, info: qsgs_info | None = None,
+                  stream=None) -> tuple[int, qsgs_info]:
+    info = info if info is not None else qsgs_info()
+    st = load().qsgs_generate(ctypes.byref(make_dims(dims)), ctypes.byref(params), _ptr(grid),
+                              _ptr(ws), int(ws_bytes), ctypes.byref(info), _stream(stream))
+    return _check(st), info
+
+
+def qsgs_read_step_log(ws, ws_bytes: int, max_entries: int = 65536, stream=None):
+    import numpy as np
+    front = np.zeros(max_entries, np.int64)
+    grown = np.zeros(max_entries, np.int64)
+    count = np.zeros(max_entries, np.int64)
+    n = load().qsgs_read_step_log(_ptr(ws), int(ws_bytes), front.ctypes.data, grown.ctypes.data,
+                                  count.ctypes.data, int(max_entries), _stream(stream))
+    n = _check(int(n))
+    return front[:n].copy(), grown[:n].copy(), count[:n].copy()
+
+
+def qsgs_profile_enable(enable: bool) -> None:
+    load().qsgs_profile_enable(1 if enable else 0)
+
+
+def qsgs_profile_read(reset: bool = False) -> dict:
+    out = (ctypes.c_double * 5)()
+    load().qsgs_profile_read(out, 1 if reset else 0)
+    return {"grow_launches": out[0], "grow_ms": out[1], "prune_launches": out[2],
+            "prune_ms": out[3], "seed_ms": out[4]}
+
+
+def qsgs_last_error() -> str:
+    return load().qsgs_last_error().decode()
+
+
+def qsgs_version() -> str:
+    return load().qsgs_version().decode()
+
+
+# ----- convenience: torch-allocated buffers -----
+
+@dataclass
+class Buffers:
+    """Device buffers for one grid size; reused across calls of the same size."""
+    dims: tuple
+    grid: object
+    ws: object
+    ws_bytes: int
+    extra: dict = field(default_factory=dict)
+
+    def view(self):
+        nx, ny, nz = self.dims
+        return self.grid[: nx * ny * nz].view(nz, ny, nx)
+
+
+def alloc(dims, params: qsgs_params, device: str = "cuda") -> Buffers:
+    import torch
+    dims = tuple(int(v) for v in dims)
+    gb = qsgs_grid_bytes(dims)
+    wb = qsgs_workspace_bytes(dims, params)
+    if gb == 0 or wb == 0:
+        raise QsgsError(ERR_INVALID, qsgs_last_error() or "invalid dims or params")
+    grid = torch.empty(gb, dtype=torch.uint8, device=device)
+    ws = torch.empty(wb, dtype=torch.uint8, device=device)
+    return Buffers(dims, grid, ws, wb)
+
+
+def generate(dims, params: qsgs_params, buffers: Buffers | None = None, stream=None):
+    """Run qsgs_generate; returns (grid view [nz, ny, nx] uint8 on the device, info dict)."""
+    if buffers is None or buffers.ws_bytes < qsgs_workspace_bytes(dims, params):
+        buffers = alloc(dims, params)
+    st, info = qsgs_generate(dims, params, buffers.grid, buffers.ws, buffers.ws_bytes,
+                             stream=stream)
+    d = info.as_dict()
+    d["status_name"] = STATUS_NAMES[st]
+    return buffers.view(), d, buffers

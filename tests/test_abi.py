@@ -1,0 +1,121 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qsgs.h")
+
+
+@pytest.fixture(scope="module")
+def q():
+    import paper_2602_11734_amd as q
+    from paper_2602_11734_amd import build
+    build.build_library(force=False)
+    q.load()
+    return q
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsgs_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(q):
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(q.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(q.SIGNATURES), "binding and header disagree"
+
+
+def test_version(q):
+    assert "gfx950" in q.qsgs_version()
+
+
+def test_size_queries(q):
+    p = q.make_params(0.7, 0.005, (0.02, 0.005, 0.00125), 4, 0)
+    assert q.qsgs_grid_bytes((64, 64, 64)) == 64**3
+    assert q.qsgs_grid_bytes((3, 1, 1)) == 4
+    assert q.qsgs_grid_bytes((0, 4, 4)) == 0
+    assert q.qsgs_grid_bytes((2**11, 2**10, 2**10)) == 0  # N = 2^31
+    ws = q.qsgs_workspace_bytes((64, 64, 64), p)
+    n = 64**3
+    assert ws >= 17 * n  # candidates, sorted candidates + priorities, status
+    assert q.qsgs_step_workspace_bytes() >= 4096
+    # a larger spacing needs fewer buckets, never more bytes
+    p2 = q.make_params(0.7, 0.005, (0.02, 0.005, 0.00125), 30, 0)
+    assert q.qsgs_workspace_bytes((64, 64, 64), p2) <= ws
+
+
+@pytest.mark.parametrize("bad", [
+    dict(solid_fraction=0.0), dict(solid_fraction=1.5), dict(solid_fraction=float("nan")),
+    dict(seed_prob=-0.1), dict(seed_prob=1.01), dict(g_ref=(0.1, float("inf"), 0.0)),
+    dict(g_ref=(0.1, 0.2, -0.3)), dict(spacing=-1),
+])
+def test_invalid_params_rejected_before_launch(q, bad):
+    base = dict(solid_fraction=0.7, seed_prob=0.01, g_ref=(0.1, 0.05, 0.01), spacing=3, key=1)
+    base.update(bad)
+    p = q.make_params(**base)
+    assert q.qsgs_workspace_bytes((8, 8, 8), p) == 0
+    info = q.qsgs_info()
+    st = q.load().qsgs_generate(ctypes.byref(q.make_dims((8, 8, 8))), ctypes.byref(p), 256,
+                                256, 1 << 20, ctypes.byref(info), None)
+    assert st == q.ERR_INVALID
+    assert q.qsgs_last_error()
+
+
+def test_invalid_dims_and_pointers(q):
+    p = q.make_params(0.7, 0.01, (0.1, 0.05, 0.01), 3, 1)
+    info = q.qsgs_info()
+    lib = q.load()
+    for dims in ((0, 8, 8), (8, -1, 8), (2**11, 2**10, 2**10)):
+        st = lib.qsgs_generate(ctypes.byref(q.make_dims(dims)), ctypes.byref(p), 256, 256,
+                               1 << 20, ctypes.byref(info), None)
+        assert st == q.ERR_INVALID
+    d = ctypes.byref(q.make_dims((8, 8, 8)))
+    assert lib.qsgs_generate(d, ctypes.byref(p), None, 256, 1 << 20, ctypes.byref(info),
+                             None) == q.ERR_INVALID
+    assert lib.qsgs_generate(d, ctypes.byref(p), 258, 256, 1 << 20, ctypes.byref(info),
+                             None) == q.ERR_INVALID  # misaligned grid
+    assert "aligned" in q.qsgs_last_error()
+    assert lib.qsgs_generate(d, ctypes.byref(p), 256, 256, 16, ctypes.byref(info),
+                             None) == q.ERR_WORKSPACE
+    assert lib.qsgs_grow_step(d, ctypes.byref(p), 256, 512, 512, 100, 256, 1 << 20,
+                              ctypes.byref(info), None) == q.ERR_INVALID  # same buffers
+    assert lib.qsgs_grow_step(d, ctypes.byref(p), 256, 512, 1024, 100, 256, 16,
+                              ctypes.byref(info), None) == q.ERR_WORKSPACE
+    bad_info = q.qsgs_info()
+    bad_info.front_size = 200
+    assert lib.qsgs_grow_step(d, ctypes.byref(p), 256, 512, 1024, 100, 256, 1 << 20,
+                              ctypes.byref(bad_info), None) == q.ERR_INVALID
+    assert lib.qsgs_seed(d, ctypes.byref(p), 256, None, 100, 256, 1 << 30, ctypes.byref(info),
+                         None) == q.ERR_INVALID
+
+
+def test_finished_state_is_a_noop(q):
+    """A grow step on a state whose status is already terminal returns it untouched
+    without launching anything (so it runs on a machine without a GPU)."""
+    p = q.make_params(0.7, 0.01, (0.1, 0.05, 0.01), 3, 1)
+    info = q.qsgs_info()
+    info.status = q.DONE
+    info.front_size = 5
+    st = q.load().qsgs_grow_step(ctypes.byref(q.make_dims((8, 8, 8))), ctypes.byref(p), 256, 512,
+                                 1024, 100, 256, 1 << 20, ctypes.byref(info), None)
+    assert st == q.DONE and info.front_size == 5
+
+
+def test_package_fails_loudly_without_library(tmp_path):
+    import paper_2602_11734_amd as q
+    saved = q._lib
+    q._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="not built"):
+            q.load(str(tmp_path / "missing.so"))
+    finally:
+        q._lib = saved

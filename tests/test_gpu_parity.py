@@ -1,0 +1,225 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle, bit-exact.
+
+Small and ragged grids and the degenerate cases are compared with live oracle runs;
+the 200^3 and 400^3 workloads are compared with the oracle's stored results
+(tests/golden/oracle_runs.json, written by tests/golden/make_goldens.py).
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "oracle_runs.json")
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_11734_amd as q
+    if not os.path.exists(q.LIB_PATH):
+        from paper_2602_11734_amd import build
+        build.build_library()
+    q.load()
+    return q
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run_gpu(q, case):
+    import torch
+    say("GPU generate", case.name, case.dims, "key", case.key)
+    params = q.params_of(case)
+    grid, info, buf = q.generate(case.dims, params)
+    torch.cuda.synchronize()
+    logs = q.qsgs_read_step_log(buf.ws, buf.ws_bytes)
+    return grid.cpu().numpy(), info, logs
+
+
+def run_oracle(orc, case, **kw):
+    return orc.generate(case.dims, case.solid_fraction, case.seed_prob, case.g_ref, case.spacing,
+                        case.key, max_steps=case.max_steps, log_cap=100000, **kw)
+
+
+SMALL = workloads.small_cases() + workloads.config1()
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[c.name for c in SMALL])
+def test_generate_matches_oracle(q, orc, case):
+    got, info, (lf, ln, lc) = run_gpu(q, case)
+    ref = run_oracle(orc, case)
+    assert info["status"] == ref.status
+    assert info["n_candidates"] == ref.n_candidates
+    assert info["n_seeds"] == ref.n_seeds
+    assert info["step"] == ref.steps
+    assert info["solid_count"] == ref.solid_count
+    assert info["target_count"] == ref.target_count
+    assert info["front_size"] == ref.front_size
+    assert np.array_equal(lf, ref.log_front)
+    assert np.array_equal(ln, ref.log_new)
+    assert np.array_equal(lc, ref.log_count)
+    assert np.array_equal(got, ref.grid)
+
+
+def test_generate_is_deterministic(q):
+    import torch
+    case = workloads.small_cases()[0]
+    a, ia, _ = run_gpu(q, case)
+    # a second, separately allocated workspace; a busy stream in between
+    x = torch.randn(1 << 22, device="cuda")
+    (x * 2).sum()
+    b, ib, _ = run_gpu(q, case)
+    assert ia == ib and np.array_equal(a, b)
+
+
+def _step_api_run(q, orc, case, front_cap=None, check_every_step=True):
+    """qsgs_seed + qsgs_grow_step, compared with the oracle's own steps each step."""
+    import torch
+    nx, ny, nz = case.dims
+    n = nx * ny * nz
+    params = q.params_of(case)
+    cap = n if front_cap is None else front_cap
+    grid = torch.empty(q.qsgs_grid_bytes(case.dims), dtype=torch.uint8, device="cuda")
+    fa = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    fb = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    wsb = q.qsgs_workspace_bytes(case.dims, params)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    sws = torch.empty(q.qsgs_step_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    say("GPU seed", case.name)
+    st, info = q.qsgs_seed(case.dims, params, grid, fa, cap, ws, wsb)
+
+    # oracle side, step by step from its own seeds
+    tseed = orc.prob_threshold(case.seed_prob)
+    cand, prio = orc.seed_candidates(case.dims, case.key, tseed)
+    g_ref, _ = orc.seed_select(case.dims, case.spacing, cand, prio)
+    front_ref = orc.interface(g_ref)
+    s_star = orc.target_count(case.solid_fraction, n)
+    t_ref = [orc.prob_threshold(g) for g in case.g_ref]
+    cnt = int(g_ref.sum())
+    assert info.n_seeds == cnt and info.n_candidates == len(cand)
+    assert np.array_equal(grid[:n].view(nz, ny, nx).cpu().numpy(), g_ref)
+    assert np.array_equal(np.sort(fa[: info.front_size].cpu().numpy()), front_ref)
+
+    t = 0
+    while st == q.OK:
+        T = [orc.growth_threshold(tr, cnt, s_star) for tr in t_ref]
+        front_ref, n_new = orc.step_liets(g_ref, front_ref, t, T, case.key)
+        cnt += n_new
+        say("GPU grow_step", case.name, "t", t)
+        st, info = q.qsgs_grow_step(case.dims, params, grid, fa, fb, cap, sws, sws.numel(), info)
+        fa, fb = fb, fa
+        assert info.step == t + 1 and info.solid_count == cnt
+        assert info.grown_last_step == n_new
+        if check_every_step or st != q.OK:
+            assert np.array_equal(grid[:n].view(nz, ny, nx).cpu().numpy(), g_ref), t
+            assert np.array_equal(np.sort(fa[: info.front_size].cpu().numpy()), np.sort(front_ref)), t
+        t += 1
+    ref = run_oracle(orc, case)
+    assert st == ref.status and info.step == ref.steps
+    assert np.array_equal(g_ref, ref.grid)
+    return grid, info
+
+
+@pytest.mark.parametrize("idx", [0, 4, 7, 16])
+def test_step_api_matches_oracle_each_step(q, orc, idx):
+    cases = workloads.small_cases()
+    _step_api_run(q, orc, cases[idx])
+
+
+def test_step_api_config1(q, orc):
+    _step_api_run(q, orc, workloads.config1()[0])
+
+
+def test_capacity_error_restores_state(q, orc):
+    """A front buffer too small for F_t + New_t: the step reports QSGS_ERR_CAPACITY,
+    leaves the grid as it was, and succeeds when retried with room."""
+    import torch
+    case = workloads.config1()[0]
+    nx, ny, nz = case.dims
+    n = nx * ny * nz
+    params = q.params_of(case)
+    grid = torch.empty(q.qsgs_grid_bytes(case.dims), dtype=torch.uint8, device="cuda")
+    wsb = q.qsgs_workspace_bytes(case.dims, params)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    sws = torch.empty(q.qsgs_step_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    small = 3000
+    fa = torch.empty(n, dtype=torch.int32, device="cuda")
+    fb = torch.empty(n, dtype=torch.int32, device="cuda")
+    say("GPU seed (capacity test)")
+    st, info = q.qsgs_seed(case.dims, params, grid, fa, small, ws, wsb)
+    assert st == q.OK and info.front_size <= small
+    before = grid.clone()
+    front_before = fa[: info.front_size].clone()
+    saved = q.qsgs_info.from_buffer_copy(info)
+    say("GPU grow_step with a small front buffer")
+    with pytest.raises(q.QsgsError) as e:
+        q.qsgs_grow_step(case.dims, params, grid, fa, fb, small, sws, sws.numel(), info)
+    assert e.value.status == q.ERR_CAPACITY
+    assert torch.equal(grid, before)
+    assert torch.equal(fa[: info.front_size], front_before)
+    assert bytes(info) == bytes(saved)
+    say("GPU grow_step retry")
+    st, info = q.qsgs_grow_step(case.dims, params, grid, fa, fb, n, sws, sws.numel(), info)
+    # the retried step equals the oracle's first step
+    ref = run_oracle(orc, case, birth=True)
+    g1 = ((ref.birth >= 0) & (ref.birth <= 1)).astype(np.uint8)
+    assert np.array_equal(grid[:n].view(nz, ny, nx).cpu().numpy(), g1)
+
+
+def test_seed_capacity_error(q):
+    import torch
+    case = workloads.config1()[0]
+    params = q.params_of(case)
+    grid = torch.empty(q.qsgs_grid_bytes(case.dims), dtype=torch.uint8, device="cuda")
+    wsb = q.qsgs_workspace_bytes(case.dims, params)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    fa = torch.full((16,), -7, dtype=torch.int32, device="cuda")
+    say("GPU seed with a 10-entry front buffer")
+    with pytest.raises(q.QsgsError) as e:
+        q.qsgs_seed(case.dims, params, grid, fa, 10, ws, wsb)
+    assert e.value.status == q.ERR_CAPACITY
+    assert torch.all(fa[10:] == -7)
+
+
+def _golden():
+    if not os.path.exists(GOLDEN):
+        return {}
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _golden_check(q, entry):
+    import torch
+    c = entry["case"]
+    case = workloads.Case(**{**c, "dims": tuple(c["dims"]), "g_ref": tuple(c["g_ref"])})
+    got, info, (lf, ln, lc) = run_gpu(q, case)
+    assert info["status"] == entry["status"]
+    assert info["n_candidates"] == entry["n_candidates"]
+    assert info["n_seeds"] == entry["n_seeds"]
+    assert info["step"] == entry["steps"]
+    assert info["solid_count"] == entry["solid_count"]
+    assert info["front_size"] == entry["front_size"]
+    assert list(lf) == entry["log_front"]
+    assert list(ln) == entry["log_new"]
+    assert list(lc) == entry["log_count"]
+    assert hashlib.sha256(got.tobytes()).hexdigest() == entry["grid_sha256"]
+    del got
+    torch.cuda.empty_cache()
+
+
+GOLD_NAMES = sorted(_golden().keys())
+
+
+@pytest.mark.parametrize("name", GOLD_NAMES)
+def test_full_size_matches_oracle_golden(q, name):
+    _golden_check(q, _golden()[name])
