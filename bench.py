@@ -63,7 +63,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(realizations shard trivially across GPUs; see DESIGN.md)", file=sys.stderr)
+              "(independent realizations shard across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -103,7 +103,7 @@ size_t qsgs_step_workspace_bytes(void);
  *   d_front  device int32[front_cap]; receives F_0 (linear voxel indices, any order).
  *   d_ws     device workspace of ws_bytes >= qsgs_workspace_bytes(dims, params).
  *   info     host; on return: n_candidates, n_seeds, solid_count = n_seeds, target_count,
- *            front_size = |F_0|, grown_last_step = 0, step = 0, status = the DEF-9 status
+ *            front_size = |F_0|, grown_last_step = 0, step = 0, status = the loop status
  *            of the initial state (QSGS_OK if growth should run).
  * Errors: QSGS_ERR_INVALID (bad dims/params/pointers), QSGS_ERR_WORKSPACE,
  * QSGS_ERR_CAPACITY (|F_0| > front_cap; d_front untouched beyond front_cap),
@@ -121,7 +121,7 @@ qsgs_status qsgs_seed(const qsgs_dims* dims, const qsgs_params* params, uint8_t*
  *   d_front_out device int32[front_cap], must not overlap d_front_in; receives F_{t+1}.
  *   d_ws        device workspace, ws_bytes >= qsgs_step_workspace_bytes().
  *   info        host, in: step, solid_count, front_size (as returned by the previous call);
- *               out: updated fields, grown_last_step = |New_t|, status per DEF-9.  When the
+ *               out: updated fields, grown_last_step = |New_t|, status per the loop rule.  When the
  *               input status is already >= 1 (done, exhausted, max steps) nothing runs.
  * Errors: QSGS_ERR_INVALID, QSGS_ERR_WORKSPACE, QSGS_ERR_DEVICE, and QSGS_ERR_CAPACITY
  * when |F_t| + |New_t| > front_cap: the grid is restored to G_t, info is unchanged, and
@@ -131,7 +131,7 @@ qsgs_status qsgs_grow_step(const qsgs_dims* dims, const qsgs_params* params, uin
                            int32_t* d_front_in, int32_t* d_front_out, int64_t front_cap,
                            void* d_ws, size_t ws_bytes, qsgs_info* info, void* stream);
 
-/* Whole generation: qsgs_seed, then growth steps until DEF-9 stops (Sec. 2.3 step 5).
+/* Whole generation: qsgs_seed, then growth steps until the loop rule stops (Sec. 2.3 step 5).
  * The loop runs on the device; the host reads the loop status once per chunk of steps.
  *   d_grid  device, qsgs_grid_bytes(dims) bytes, 4-byte aligned; receives the final grid.
  *   d_ws    device workspace, ws_bytes >= qsgs_workspace_bytes(dims, params); on return it
@@ -141,12 +141,87 @@ qsgs_status qsgs_grow_step(const qsgs_dims* dims, const qsgs_params* params, uin
 qsgs_status qsgs_generate(const qsgs_dims* dims, const qsgs_params* params, uint8_t* d_grid,
                           void* d_ws, size_t ws_bytes, qsgs_info* info, void* stream);
 
-/* Copies the per-step log of the last qsgs_generate that used this workspace into host
- * arrays (any may be NULL): front[t] = |F_t|, grown[t] = |New_t|, count[t] = solid count
- * at the start of step t, for t < min(steps, max_entries, 65536).  Returns the number of
+/* Batched generation (many independent realizations, e.g. for uncertainty
+ * quantification, Sec. 1): `count` realizations of possibly different sizes and
+ * parameters share one persistent launch per kernel per growth step, addressed
+ * through a per-realization offset table.  Each result is bit-identical to
+ * qsgs_generate of the same realization alone.
+ *   dims, params  host arrays of `count` entries.
+ *   d_grids       host array of `count` device grid pointers (qsgs_grid_bytes each,
+ *                 4-byte aligned).
+ *   d_ws          device workspace, ws_bytes >= qsgs_batch_workspace_bytes(count, dims, params).
+ *   infos         host array of `count` results.
+ * Returns the largest per-realization status (DONE, EXHAUSTED or MAXSTEPS) or an error:
+ * QSGS_ERR_INVALID (any bad entry; nothing launched), QSGS_ERR_WORKSPACE,
+ * QSGS_ERR_DEVICE.  Synchronises `stream`. */
+size_t qsgs_batch_workspace_bytes(int32_t count, const qsgs_dims* dims,
+                                  const qsgs_params* params);
+qsgs_status qsgs_generate_batch(int32_t count, const qsgs_dims* dims, const qsgs_params* params,
+                                uint8_t* const* d_grids, void* d_ws, size_t ws_bytes,
+                                qsgs_info* infos, void* stream);
+
+/* Copies the per-step log of realization `index` of the last qsgs_generate or
+ * qsgs_generate_batch that used this workspace into host arrays (any may be NULL):
+ * front[t] = |F_t|, grown[t] = |New_t|, count[t] = solid count at the start of step t,
+ * for t < min(steps, max_entries, log capacity) where the capacity is 65536 steps for a
+ * single generation and 4096 per realization in a batch.  Returns the number of
  * entries written (>= 0) or a negative qsgs_status.  Synchronises `stream`. */
-int64_t qsgs_read_step_log(const void* d_ws, size_t ws_bytes, int64_t* front, int64_t* grown,
-                           int64_t* count, int64_t max_entries, void* stream);
+int64_t qsgs_read_step_log(const void* d_ws, size_t ws_bytes, int32_t index, int64_t* front,
+                           int64_t* grown, int64_t* count, int64_t max_entries, void* stream);
+
+/* Continuous-batching server.  Generation requests of different sizes are queued on
+ * the host; each tick admits queued requests in arrival order while a slot is free and
+ * their footprint -- grid (qsgs_grid_bytes) plus two front lists (4 N bytes each) --
+ * fits the free part of the caller's device arena (the HBM budget), seeds them (with
+ * transient seeding scratch from the same arena), then advances every resident
+ * realization by `steps_per_tick` growth steps in shared launches.  A finished
+ * request's grid stays in the arena until qsgs_server_take copies it out.  Each
+ * result is bit-identical to qsgs_generate of the same request alone.  A server is
+ * used from one thread; its stream orders all of its work.
+ *   qsgs_server_reserved_bytes  arena bytes the server keeps for its control area.
+ *   qsgs_server_create   d_arena: device, 256-byte aligned, arena_bytes long, owned by
+ *                        the caller until qsgs_server_destroy; max_slots in [1, 65536];
+ *                        steps_per_tick in [1, 1024].
+ *   qsgs_server_submit   queues one request; QSGS_ERR_INVALID for bad dims/params or an
+ *                        id in use, QSGS_ERR_CAPACITY if it cannot fit the arena even
+ *                        when alone.
+ *   qsgs_server_tick     one scheduling tick; reports resident, queued and finished
+ *                        (not yet taken) requests.  Synchronises the stream.
+ *   qsgs_server_ready    ids and infos of finished requests, oldest first (at most max).
+ *   qsgs_server_take     copies the N-byte grid of a finished request to dst (host
+ *                        memory if dst_on_host, else device; dst may be NULL to drop it)
+ *                        and releases its arena space.
+ *   qsgs_server_free_bytes  arena bytes not held by requests. */
+typedef struct qsgs_server qsgs_server;
+size_t qsgs_server_reserved_bytes(int32_t max_slots);
+qsgs_status qsgs_server_create(void* d_arena, size_t arena_bytes, int32_t max_slots,
+                               int32_t steps_per_tick, void* stream, qsgs_server** out);
+qsgs_status qsgs_server_submit(qsgs_server* server, int64_t request_id, const qsgs_dims* dims,
+                               const qsgs_params* params);
+qsgs_status qsgs_server_tick(qsgs_server* server, int32_t* n_resident, int32_t* n_queued,
+                             int32_t* n_ready);
+int32_t qsgs_server_ready(qsgs_server* server, int64_t* ids, qsgs_info* infos, int32_t max);
+qsgs_status qsgs_server_take(qsgs_server* server, int64_t request_id, void* dst,
+                             size_t dst_bytes, int32_t dst_on_host);
+size_t qsgs_server_free_bytes(const qsgs_server* server);
+void qsgs_server_destroy(qsgs_server* server);
+
+/* Launch shape of the item kernels (seed, growth and prune passes): threads per
+ * workgroup (`*_block`, a multiple of 64 in [64, 512]) and workgroups (`*_grid`, a
+ * multiple of 8 so that each of the 8 XCDs gets an equal share), plus the growth steps
+ * issued between two host reads of the loop state (`steps_per_sync`, 0 = adaptive).
+ * The shape never changes a result: every output is a function of the inputs only.
+ * qsgs_set_tuning applies process-wide to calls that start afterwards (NULL restores
+ * the defaults: 256 x 2048 everywhere, adaptive); QSGS_ERR_INVALID for a bad shape. */
+typedef struct {
+  int32_t grow_block, grow_grid;
+  int32_t prune_block, prune_grid;
+  int32_t seed_block, seed_grid;
+  int32_t steps_per_sync;
+} qsgs_tuning;
+
+qsgs_status qsgs_set_tuning(const qsgs_tuning* tuning);
+void qsgs_get_tuning(qsgs_tuning* tuning);
 
 /* Kernel timing for measurement.  While enabled (enable != 0), qsgs_generate records HIP
  * events around each growth-sweep and prune launch on its stream and accumulates their

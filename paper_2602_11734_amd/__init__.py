@@ -48,6 +48,16 @@ class qsgs_info(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class qsgs_tuning(ctypes.Structure):
+    _fields_ = [("grow_block", ctypes.c_int32), ("grow_grid", ctypes.c_int32),
+                ("prune_block", ctypes.c_int32), ("prune_grid", ctypes.c_int32),
+                ("seed_block", ctypes.c_int32), ("seed_grid", ctypes.c_int32),
+                ("steps_per_sync", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # Every symbol the header declares, with its ctypes signature.
 _P = ctypes.POINTER
 _VP, _SZ, _I64, _I32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int32
@@ -61,7 +71,19 @@ SIGNATURES = {
                                       _SZ, _P(qsgs_info), _VP]),
     "qsgs_generate": (ctypes.c_int, [_P(qsgs_dims), _P(qsgs_params), _VP, _VP, _SZ,
                                      _P(qsgs_info), _VP]),
-    "qsgs_read_step_log": (_I64, [_VP, _SZ, _VP, _VP, _VP, _I64, _VP]),
+    "qsgs_batch_workspace_bytes": (_SZ, [_I32, _VP, _VP]),
+    "qsgs_generate_batch": (ctypes.c_int, [_I32, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
+    "qsgs_read_step_log": (_I64, [_VP, _SZ, _I32, _VP, _VP, _VP, _I64, _VP]),
+    "qsgs_server_reserved_bytes": (_SZ, [_I32]),
+    "qsgs_server_create": (ctypes.c_int, [_VP, _SZ, _I32, _I32, _VP, _P(_VP)]),
+    "qsgs_server_submit": (ctypes.c_int, [_VP, _I64, _P(qsgs_dims), _P(qsgs_params)]),
+    "qsgs_server_tick": (ctypes.c_int, [_VP, _P(_I32), _P(_I32), _P(_I32)]),
+    "qsgs_server_ready": (_I32, [_VP, _VP, _VP, _I32]),
+    "qsgs_server_take": (ctypes.c_int, [_VP, _I64, _VP, _SZ, _I32]),
+    "qsgs_server_free_bytes": (_SZ, [_VP]),
+    "qsgs_server_destroy": (None, [_VP]),
+    "qsgs_set_tuning": (ctypes.c_int, [_P(qsgs_tuning)]),
+    "qsgs_get_tuning": (None, [_P(qsgs_tuning)]),
     "qsgs_profile_enable": (None, [_I32]),
     "qsgs_profile_read": (None, [_VP, _I32]),
     "qsgs_last_error": (ctypes.c_char_p, []),
@@ -169,15 +191,95 @@ def qsgs_generate(dims, params, grid, ws, ws_bytes: int, info: qsgs_info | None 
     return _check(st), info
 
 
-def qsgs_read_step_log(ws, ws_bytes: int, max_entries: int = 65536, stream=None):
+def qsgs_read_step_log(ws, ws_bytes: int, index: int = 0, max_entries: int = 65536,
+                       stream=None):
     import numpy as np
     front = np.zeros(max_entries, np.int64)
     grown = np.zeros(max_entries, np.int64)
     count = np.zeros(max_entries, np.int64)
-    n = load().qsgs_read_step_log(_ptr(ws), int(ws_bytes), front.ctypes.data, grown.ctypes.data,
-                                  count.ctypes.data, int(max_entries), _stream(stream))
+    n = load().qsgs_read_step_log(_ptr(ws), int(ws_bytes), int(index), front.ctypes.data,
+                                  grown.ctypes.data, count.ctypes.data, int(max_entries),
+                                  _stream(stream))
     n = _check(int(n))
     return front[:n].copy(), grown[:n].copy(), count[:n].copy()
+
+
+def qsgs_batch_workspace_bytes(dims_list, params_list) -> int:
+    n = len(dims_list)
+    d = (qsgs_dims * n)(*[make_dims(x) for x in dims_list])
+    p = (qsgs_params * n)(*params_list)
+    return int(load().qsgs_batch_workspace_bytes(n, d, p))
+
+
+def qsgs_generate_batch(dims_list, params_list, grids, ws, ws_bytes: int, stream=None):
+    """Batched generation; returns (status, list of qsgs_info)."""
+    n = len(dims_list)
+    d = (qsgs_dims * n)(*[make_dims(x) for x in dims_list])
+    p = (qsgs_params * n)(*params_list)
+    g = (ctypes.c_void_p * n)(*[_ptr(x) for x in grids])
+    infos = (qsgs_info * n)()
+    st = load().qsgs_generate_batch(n, d, p, g, _ptr(ws), int(ws_bytes), infos, _stream(stream))
+    return _check(st), list(infos)
+
+
+def qsgs_server_reserved_bytes(max_slots: int) -> int:
+    return int(load().qsgs_server_reserved_bytes(int(max_slots)))
+
+
+def qsgs_server_create(arena, arena_bytes: int, max_slots: int, steps_per_tick: int = 1,
+                       stream=None) -> int:
+    h = ctypes.c_void_p()
+    _check(load().qsgs_server_create(_ptr(arena), int(arena_bytes), int(max_slots),
+                                     int(steps_per_tick), _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def qsgs_server_submit(server: int, request_id: int, dims, params: qsgs_params) -> None:
+    _check(load().qsgs_server_submit(server, int(request_id), ctypes.byref(make_dims(dims)),
+                                     ctypes.byref(params)))
+
+
+def qsgs_server_tick(server: int) -> tuple[int, int, int]:
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().qsgs_server_tick(server, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def qsgs_server_ready(server: int, max_n: int = 4096):
+    ids = (ctypes.c_int64 * max_n)()
+    infos = (qsgs_info * max_n)()
+    n = load().qsgs_server_ready(server, ids, infos, int(max_n))
+    return [(ids[k], infos[k]) for k in range(n)]
+
+
+def qsgs_server_take(server: int, request_id: int, dst=None, dst_bytes: int = 0,
+                     dst_on_host: bool = False) -> None:
+    if dst is not None and hasattr(dst, "ctypes"):  # numpy array on the host
+        ptr, dst_on_host, dst_bytes = dst.ctypes.data, True, dst.nbytes
+    else:
+        ptr = _ptr(dst)
+    _check(load().qsgs_server_take(server, int(request_id), ptr, int(dst_bytes),
+                                   1 if dst_on_host else 0))
+
+
+def qsgs_server_free_bytes(server: int) -> int:
+    return int(load().qsgs_server_free_bytes(server))
+
+
+def qsgs_server_destroy(server: int) -> None:
+    load().qsgs_server_destroy(server)
+
+
+def qsgs_set_tuning(tuning: qsgs_tuning | dict | None) -> None:
+    if isinstance(tuning, dict):
+        tuning = qsgs_tuning(**tuning)
+    _check(load().qsgs_set_tuning(ctypes.byref(tuning) if tuning is not None else None))
+
+
+def qsgs_get_tuning() -> qsgs_tuning:
+    t = qsgs_tuning()
+    load().qsgs_get_tuning(ctypes.byref(t))
+    return t
 
 
 def qsgs_profile_enable(enable: bool) -> None:

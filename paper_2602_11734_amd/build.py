@@ -9,8 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqsgs.so")
-SOURCES = ["qsgs_kernels.hip", "qsgs_api.hip"]
-HEADERS = ["qsgs_device.h", "qsgs_internal.h"]
+SOURCES = ["qsgs_kernels.hip", "qsgs_api.hip", "qsgs_server.hip"]
+HEADERS = ["qsgs_device.h", "qsgs_internal.h", "qsgs_host.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",

@@ -10,7 +10,8 @@
 namespace qsgs {
 
 constexpr int kWave = 64;
-constexpr int kBlock = 256;            // 4 waves per workgroup
+constexpr int kBlock = 256;            // default workgroup: 4 waves
+constexpr int kMaxBlock = 512;         // largest tunable workgroup of the item kernels
 constexpr uint32_t kNumXcd = 8;        // workgroup b runs on XCD b % 8
 
 // Philox counter word 3: separates the seeding stream from the two growth streams.
@@ -93,22 +94,6 @@ __device__ __forceinline__ uint64_t eq1_threshold(uint64_t t_ref, uint64_t cnt, 
   const uint64_t q_lo = ((r << 32) | p_lo) / s_star;       // < 2^32
   return q_lo;
 }
-
-// Work split: the item range [0, n) is cut into 8 contiguous parts, one per XCD,
-// so neighbouring front entries (neighbouring voxels) share one XCD's L2.  Within a
-// part the XCD's workgroups stride over chunks of kBlock items.  The grid size must
-// be a multiple of kNumXcd.
-struct XcdSplit {
-  uint32_t begin, end, stride;
-  __device__ __forceinline__ XcdSplit(uint32_t n) {
-    const uint32_t xcd = blockIdx.x % kNumXcd;
-    const uint32_t per = (n + kNumXcd - 1) / kNumXcd;
-    const uint32_t b = min(n, xcd * per);
-    begin = b + (blockIdx.x / kNumXcd) * kBlock;
-    end = min(n, b + per);
-    stride = (gridDim.x / kNumXcd) * kBlock;
-  }
-};
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 

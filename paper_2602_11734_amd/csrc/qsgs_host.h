@@ -1,0 +1,552 @@
+// qsgs_host.h -- host-side engine of libqsgs, shared by the C-ABI translation units.
+//
+// An Engine drives a table of realization records in device memory: it seeds the
+// records marked for seeding, advances every growing record by one step per call,
+// and reads the records back.  The single-grid entry points, the batched entry point
+// and the serving loop all run through it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "qsgs.h"
+#include "qsgs_internal.h"
+
+namespace qsgs {
+namespace host {
+
+inline std::string& last_error() {
+  static thread_local std::string e;
+  return e;
+}
+
+inline qsgs_status fail(qsgs_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  last_error() = buf;
+  return s;
+}
+
+#define QSGS_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::qsgs::host::fail(QSGS_ERR_DEVICE, "%s failed: %s", #call,                 \
+                                hipGetErrorString(e_));                                  \
+  } while (0)
+
+#define QSGS_LAUNCHED(what)                                                              \
+  do {                                                                                   \
+    hipError_t e_ = hipGetLastError();                                                   \
+    if (e_ != hipSuccess)                                                                \
+      return ::qsgs::host::fail(QSGS_ERR_DEVICE, "launch of %s failed: %s", what,        \
+                                hipGetErrorString(e_));                                  \
+  } while (0)
+
+#define QSGS_TRY(expr)              \
+  do {                              \
+    qsgs_status st_ = (expr);       \
+    if (st_ != QSGS_OK) return st_; \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int32_t kDefaultMaxSteps = 1 << 20;
+constexpr uint32_t kRoundsPerCheck = 8;
+constexpr uint32_t kLogCapSingle = 65536;  // per-step log entries of a batch of one
+constexpr uint32_t kLogCapBatch = 4096;    // per realization in larger batches
+constexpr uint64_t kMagic = 0x51534753574B5331ull;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+// ----- integer constants (Sec. 2.1 step 2, Sec. 2.3 step 5, Eq. (1)) -----
+
+// min(2^32, floor(p 2^32)); p * 2^32 is exact in binary64.
+inline uint64_t prob_threshold(double p) {
+  if (!(p > 0.0)) return 0;
+  if (p >= 1.0) return kOne32;
+  return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+// S* = ceil(phi_s N) evaluated in binary64, clamped to [0, N].
+inline uint64_t target_count(double phi_s, uint64_t n) {
+  double t = std::ceil(phi_s * (double)n);
+  if (t < 0.0) t = 0.0;
+  if (t > (double)n) t = (double)n;
+  return (uint64_t)t;
+}
+
+inline bool is_prob(double p) { return std::isfinite(p) && p >= 0.0 && p <= 1.0; }
+
+inline qsgs_status check_dims(const qsgs_dims* d, Geometry* g) {
+  if (!d) return fail(QSGS_ERR_INVALID, "dims is NULL");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+    return fail(QSGS_ERR_INVALID, "dims must be >= 1 (got %d x %d x %d)", d->nx, d->ny, d->nz);
+  const int64_t n = (int64_t)d->nx * d->ny * d->nz;
+  if (n >= (int64_t)1 << 31)
+    return fail(QSGS_ERR_INVALID, "nx*ny*nz = %lld must be < 2^31", (long long)n);
+  g->nx = d->nx;
+  g->ny = d->ny;
+  g->nz = d->nz;
+  g->nxy = (uint32_t)d->nx * (uint32_t)d->ny;
+  g->n = (uint32_t)n;
+  g->div_nx.init((uint32_t)d->nx);
+  g->div_ny.init((uint32_t)d->ny);
+  return QSGS_OK;
+}
+
+inline qsgs_status check_params(const qsgs_params* p) {
+  if (!p) return fail(QSGS_ERR_INVALID, "params is NULL");
+  if (!(std::isfinite(p->solid_fraction) && p->solid_fraction > 0.0 && p->solid_fraction <= 1.0))
+    return fail(QSGS_ERR_INVALID, "solid_fraction must be in (0, 1]");
+  if (!is_prob(p->seed_prob)) return fail(QSGS_ERR_INVALID, "seed_prob must be in [0, 1]");
+  for (int c = 0; c < 3; ++c)
+    if (!is_prob(p->g_ref[c])) return fail(QSGS_ERR_INVALID, "g_ref[%d] must be in [0, 1]", c);
+  if (p->spacing < 0) return fail(QSGS_ERR_INVALID, "spacing must be >= 0");
+  return QSGS_OK;
+}
+
+inline qsgs_status check_grid(const uint8_t* grid) {
+  if (!grid) return fail(QSGS_ERR_INVALID, "d_grid is NULL");
+  if ((uintptr_t)grid % 4 != 0) return fail(QSGS_ERR_INVALID, "d_grid must be 4-byte aligned");
+  return QSGS_OK;
+}
+
+inline size_t grid_bytes(const Geometry& g) { return ((size_t)g.n + 3) / 4 * 4; }
+
+inline Buckets make_buckets(const Geometry& g, int32_t spacing) {
+  Buckets b{};
+  if (spacing <= 1) return b;
+  const uint32_t e = (uint32_t)(spacing - 1);
+  b.edge.init(e);
+  b.nbx = (uint32_t)(((uint64_t)g.nx + e - 1) / e);
+  b.nby = (uint32_t)(((uint64_t)g.ny + e - 1) / e);
+  b.nbz = (uint32_t)(((uint64_t)g.nz + e - 1) / e);
+  b.nb = b.nbx * b.nby * b.nbz;
+  b.radius = spacing - 1;
+  return b;
+}
+
+inline Ctl make_ctl(const Geometry& g, const qsgs_params* p) {
+  Ctl c{};
+  c.s_star = target_count(p->solid_fraction, g.n);
+  for (int k = 0; k < 3; ++k) c.t_ref[k] = prob_threshold(p->g_ref[k]);
+  c.max_steps = p->max_steps > 0 ? p->max_steps : kDefaultMaxSteps;
+  return c;
+}
+
+inline void fill_info(const Ctl& c, qsgs_info* info) {
+  info->n_candidates = c.n_cand;
+  info->n_seeds = c.n_seeds;
+  info->solid_count = (int64_t)c.cnt;
+  info->target_count = (int64_t)c.s_star;
+  info->front_size = c.front_size;
+  info->grown_last_step = c.last_new;
+  info->step = c.step;
+  info->status = c.status;
+}
+
+struct Spec {
+  Geometry g;
+  Buckets bk;
+};
+
+// Host-readable description at the start of a workspace (for the step-log reader).
+struct WsHeader {
+  uint64_t magic;
+  uint32_t count, log_cap;
+  uint64_t reals, logs;
+};
+
+// Fixed part of a workspace: header, batch control, realization records, offset
+// table, round counters and per-step logs.
+struct PersistLayout {
+  size_t hdr = 0, bctl = 0, reals = 0, off = 0, live = 0, logs = 0, total = 0;
+  uint32_t log_cap = 0;
+};
+
+inline PersistLayout persist_layout(size_t count, uint32_t log_cap) {
+  PersistLayout L;
+  L.log_cap = log_cap;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t a = off;
+    off = align_up(off + bytes);
+    return a;
+  };
+  L.hdr = take(sizeof(WsHeader));
+  L.bctl = take(sizeof(BatchCtl));
+  L.reals = take(sizeof(Real) * count);
+  L.off = take(sizeof(uint64_t) * (count + 1));
+  L.live = take(sizeof(uint32_t) * kMaxRounds);
+  L.logs = take(sizeof(uint64_t) * 3 * (size_t)log_cap * count);
+  L.total = off;
+  return L;
+}
+
+// Seeding scratch of a group of realizations (offsets relative to its base): the
+// candidate lists, the spacing buckets and the bucket-sorted candidates.
+struct SeedLayout {
+  std::vector<size_t> cand;
+  size_t counts = 0, cursor = 0, sums = 0, sorted_v = 0, sorted_r = 0, prio = 0, status = 0,
+         total = 0;
+  uint32_t total_buckets = 0;
+};
+
+inline SeedLayout seed_layout(const std::vector<Spec>& specs) {
+  SeedLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t a = off;
+    off = align_up(off + bytes);
+    return a;
+  };
+  uint64_t tb = 0, sorted = 0;
+  for (const Spec& s : specs) {
+    tb += s.bk.nb;
+    if (s.bk.nb) sorted += s.g.n;
+  }
+  L.total_buckets = (uint32_t)tb;
+  const size_t nscan = (size_t)tb + 1;
+  L.counts = take(sizeof(uint32_t) * nscan);
+  L.cursor = take(sizeof(uint32_t) * nscan);
+  size_t sums = 0;
+  for (size_t m = nscan; m > 1;) {
+    m = (m + kScanBlock - 1) / kScanBlock;
+    sums += m + 1;
+  }
+  L.sums = take(sizeof(uint32_t) * (sums + 8));
+  L.sorted_v = take(sizeof(int32_t) * sorted);
+  L.sorted_r = take(sizeof(uint32_t) * sorted);
+  L.prio = take(sizeof(uint64_t) * sorted);
+  L.status = take(sorted);
+  for (const Spec& s : specs) L.cand.push_back(take(sizeof(int32_t) * s.g.n));
+  L.total = off;
+  return L;
+}
+
+// Launch shape of the item kernels (block = threads per workgroup, a multiple of 64 up
+// to 512; grid = workgroups, a multiple of 8) and the steps issued between host reads.
+struct Tuning {
+  uint32_t grow_block = kBlock, grow_grid = 2048;
+  uint32_t prune_block = kBlock, prune_grid = 2048;
+  uint32_t seed_block = kBlock, seed_grid = 2048;
+  int32_t steps_per_sync = 0;  // 0: adaptive
+};
+
+inline std::mutex& tuning_mu() {
+  static std::mutex m;
+  return m;
+}
+inline Tuning& tuning_ref() {
+  static Tuning t;
+  return t;
+}
+inline Tuning current_tuning() {
+  std::lock_guard<std::mutex> lk(tuning_mu());
+  return tuning_ref();
+}
+
+// ----- kernel timing -----
+struct Profile {
+  std::mutex mu;
+  bool enabled = false;
+  double grow_launches = 0, grow_ms = 0, prune_launches = 0, prune_ms = 0, seed_ms = 0;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+};
+inline Profile& prof() {
+  static Profile p;
+  return p;
+}
+inline bool prof_on() {
+  std::lock_guard<std::mutex> lk(prof().mu);
+  return prof().enabled;
+}
+inline hipEvent_t prof_event() {
+  Profile& p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  if (p.used == p.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p.pool.push_back(e);
+  }
+  return p.pool[p.used++];
+}
+inline void prof_release_all() {
+  std::lock_guard<std::mutex> lk(prof().mu);
+  prof().used = 0;
+}
+
+// ----- the engine -----
+struct Engine {
+  hipStream_t s = nullptr;
+  void* ws = nullptr;  // base of the persistent part
+  PersistLayout P;
+  std::vector<Real> reals;  // host mirror of the records
+  BatchArgs args{};
+  Tuning tune;
+  WsHeader hdr{};
+
+  // Binds the engine to a persistent region of `count` records at `base`.
+  void bind(void* base, const PersistLayout& L, size_t count, hipStream_t stream) {
+    ws = base;
+    P = L;
+    s = stream;
+    tune = current_tuning();
+    reals.assign(count, Real{});
+    args = BatchArgs{};
+    args.reals = at<Real>(base, L.reals);
+    args.count = (uint32_t)count;
+    args.off = at<uint64_t>(base, L.off);
+    args.bctl = at<BatchCtl>(base, L.bctl);
+    args.live = at<uint32_t>(base, L.live);
+  }
+
+  dim3 rgrid() const { return dim3(((uint32_t)reals.size() + 255) / 256); }
+
+  uint64_t* log_of(size_t r) const {
+    if (P.log_cap == 0) return nullptr;
+    return at<uint64_t>(ws, P.logs) + (size_t)3 * P.log_cap * r;
+  }
+
+  // Fills record r for a new realization (to be seeded).
+  void init_record(size_t r, const Spec& sp, const qsgs_params* p, uint8_t* grid, int32_t* f0,
+                   int32_t* f1, uint32_t cap) {
+    Real& R = reals[r];
+    R = Real{};
+    R.g = sp.g;
+    R.bk = sp.bk;
+    R.grid = grid;
+    R.f0 = f0;
+    R.f1 = f1;
+    R.cap = cap;
+    R.log = log_of(r);
+    R.log_cap = P.log_cap;
+    R.k0 = (uint32_t)p->key;
+    R.k1 = (uint32_t)(p->key >> 32);
+    R.t_seed = prob_threshold(p->seed_prob);
+    R.spacing = p->spacing;
+    R.phase = kPhaseSeed;
+    R.ctl = make_ctl(sp.g, p);
+  }
+
+  qsgs_status upload_header() {
+    hdr = WsHeader{kMagic, (uint32_t)reals.size(), P.log_cap, P.reals, P.logs};
+    QSGS_HIP(hipMemcpyAsync(at<void>(ws, P.hdr), &hdr, sizeof hdr, hipMemcpyHostToDevice, s));
+    return QSGS_OK;
+  }
+
+  qsgs_status upload(size_t first, size_t n) {
+    if (n == 0) return QSGS_OK;
+    QSGS_HIP(hipMemcpyAsync(args.reals + first, reals.data() + first, sizeof(Real) * n,
+                            hipMemcpyHostToDevice, s));
+    return QSGS_OK;
+  }
+
+  qsgs_status offsets(ItemKind kind) {
+    hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, s, args, (uint32_t)kind);
+    QSGS_LAUNCHED("k_offsets");
+    return QSGS_OK;
+  }
+
+  qsgs_status scan(uint32_t* data, uint32_t n, uint32_t* sums) {
+    const uint32_t nb = (n + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanBlock), 0, s, data, n, sums);
+    QSGS_LAUNCHED("k_scan_local");
+    if (nb > 1) {
+      QSGS_TRY(scan(sums, nb, sums + nb + 1));
+      hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, s, data, n, sums);
+      QSGS_LAUNCHED("k_scan_add");
+    }
+    return QSGS_OK;
+  }
+
+  // Points the seeding records `group` at a scratch region laid out by `L` (their
+  // candidate lists and bucket offsets); call before uploading the records.
+  void attach_scratch(const std::vector<size_t>& group, void* scratch, const SeedLayout& L) {
+    uint32_t boff = 0;
+    for (size_t k = 0; k < group.size(); ++k) {
+      Real& R = reals[group[k]];
+      R.cand = at<int32_t>(scratch, L.cand[k]);
+      R.boff = boff;
+      boff += R.bk.nb;
+    }
+    args.counts = at<uint32_t>(scratch, L.counts);
+    args.cursor = at<uint32_t>(scratch, L.cursor);
+    args.sorted_v = at<int32_t>(scratch, L.sorted_v);
+    args.sorted_r = at<uint32_t>(scratch, L.sorted_r);
+    args.sorted_prio = at<uint64_t>(scratch, L.prio);
+    args.status = at<uint8_t>(scratch, L.status);
+  }
+
+  // a1-a3 for every record in the seeding phase: candidates, spacing, seeds, the first
+  // front and the loop state of step 0.
+  qsgs_status seed(void* scratch, const SeedLayout& L) {
+    const dim3 sg(tune.seed_grid), sb(tune.seed_block);
+    hipLaunchKernelGGL(k_ctl_init, dim3(16), dim3(256), 0, s, args, 1u);
+    QSGS_LAUNCHED("k_ctl_init");
+    QSGS_TRY(offsets(kItemsVoxels));
+    hipLaunchKernelGGL(k_seed_draw, sg, sb, 0, s, args);
+    QSGS_LAUNCHED("k_seed_draw");
+    const uint32_t tb = L.total_buckets;
+    hipLaunchKernelGGL(k_fill_u32, dim3(std::min<uint32_t>(1024, tb / 256 + 1)), dim3(256), 0, s,
+                       args.counts, 0u, tb + 1);
+    QSGS_LAUNCHED("k_fill_u32");
+    QSGS_TRY(offsets(kItemsCand));
+    if (tb > 0) {
+      hipLaunchKernelGGL(k_bucket_count, sg, sb, 0, s, args);
+      QSGS_LAUNCHED("k_bucket_count");
+      QSGS_TRY(scan(args.counts, tb + 1, at<uint32_t>(scratch, L.sums)));
+      QSGS_HIP(hipMemcpyAsync(args.cursor, args.counts, sizeof(uint32_t) * (tb + 1),
+                              hipMemcpyDeviceToDevice, s));
+    }
+    hipLaunchKernelGGL(k_bucket_scatter, sg, sb, 0, s, args, tb);
+    QSGS_LAUNCHED("k_bucket_scatter");
+    if (tb > 0) {
+      uint32_t round = 0;
+      for (;;) {
+        for (uint32_t k = 0; k < kRoundsPerCheck; ++k, ++round) {
+          hipLaunchKernelGGL(k_luby_round, sg, sb, 0, s, args, round);
+          QSGS_LAUNCHED("k_luby_round");
+        }
+        uint32_t live = 0;
+        QSGS_HIP(hipMemcpyAsync(&live, args.live + round - 1, sizeof live, hipMemcpyDeviceToHost,
+                                s));
+        QSGS_HIP(hipStreamSynchronize(s));
+        if (live == 0) break;
+        if (round + kRoundsPerCheck > kMaxRounds)
+          return fail(QSGS_ERR_DEVICE, "seed spacing did not settle in %u rounds", kMaxRounds);
+      }
+      hipLaunchKernelGGL(k_collect_seeds, sg, sb, 0, s, args);
+      QSGS_LAUNCHED("k_collect_seeds");
+    }
+    QSGS_TRY(offsets(kItemsSeeds));
+    hipLaunchKernelGGL(k_front_init, sg, sb, 0, s, args);
+    QSGS_LAUNCHED("k_front_init");
+    hipLaunchKernelGGL(k_loop_init, rgrid(), dim3(256), 0, s, args);
+    QSGS_LAUNCHED("k_loop_init");
+    return QSGS_OK;
+  }
+
+  // One growth step of every growing record (a4-a6).
+  qsgs_status step(std::vector<hipEvent_t>* ev) {
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    QSGS_TRY(offsets(kItemsGrow));
+    if (ev) {
+      e0 = prof_event();
+      e1 = prof_event();
+      e2 = prof_event();
+      e3 = prof_event();
+      QSGS_HIP(hipEventRecord(e0, s));
+    }
+    hipLaunchKernelGGL(k_grow, dim3(tune.grow_grid), dim3(tune.grow_block), 0, s, args);
+    QSGS_LAUNCHED("k_grow");
+    if (ev) QSGS_HIP(hipEventRecord(e1, s));
+    QSGS_TRY(offsets(kItemsPrune));
+    if (ev) QSGS_HIP(hipEventRecord(e2, s));
+    hipLaunchKernelGGL(k_prune, dim3(tune.prune_grid), dim3(tune.prune_block), 0, s, args);
+    QSGS_LAUNCHED("k_prune");
+    if (ev) {
+      QSGS_HIP(hipEventRecord(e3, s));
+      ev->push_back(e0);
+      ev->push_back(e1);
+      ev->push_back(e2);
+      ev->push_back(e3);
+    }
+    hipLaunchKernelGGL(k_step_end, rgrid(), dim3(256), 0, s, args);
+    QSGS_LAUNCHED("k_step_end");
+    return QSGS_OK;
+  }
+
+  qsgs_status read_bctl(BatchCtl* h) {
+    QSGS_HIP(hipMemcpyAsync(h, args.bctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+    QSGS_HIP(hipStreamSynchronize(s));
+    return QSGS_OK;
+  }
+
+  qsgs_status read_ctl(size_t r, Ctl* h) {
+    QSGS_HIP(hipMemcpyAsync(h, &args.reals[r].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    QSGS_HIP(hipStreamSynchronize(s));
+    return QSGS_OK;
+  }
+
+  qsgs_status read_all(std::vector<Real>* out) {
+    out->resize(reals.size());
+    QSGS_HIP(hipMemcpyAsync(out->data(), args.reals, sizeof(Real) * reals.size(),
+                            hipMemcpyDeviceToHost, s));
+    QSGS_HIP(hipStreamSynchronize(s));
+    return QSGS_OK;
+  }
+
+  // Accumulates the durations of the first `active` timed steps.
+  qsgs_status record_profile(const std::vector<hipEvent_t>& ev, size_t active) {
+    double grow_ms = 0, prune_ms = 0;
+    const size_t n = std::min(active, ev.size() / 4);
+    for (size_t i = 0; i < n; ++i) {
+      float a = 0.f, c = 0.f;
+      QSGS_HIP(hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]));
+      QSGS_HIP(hipEventElapsedTime(&c, ev[4 * i + 2], ev[4 * i + 3]));
+      grow_ms += a;
+      prune_ms += c;
+    }
+    std::lock_guard<std::mutex> lk(prof().mu);
+    prof().grow_launches += (double)n;
+    prof().grow_ms += grow_ms;
+    prof().prune_launches += (double)n;
+    prof().prune_ms += prune_ms;
+    return QSGS_OK;
+  }
+
+  // Growth loop until every record has stopped.  For a single realization the chunk
+  // length follows the remaining count over the last step's growth, which bounds the
+  // steps left while growth slows down, so chunks rarely run past the end.
+  qsgs_status run_loop() {
+    const bool profiling = prof_on();
+    std::vector<hipEvent_t> ev;
+    BatchCtl b{};
+    QSGS_TRY(read_bctl(&b));
+    while (b.running > 0) {
+      uint32_t chunk = tune.steps_per_sync > 0 ? (uint32_t)tune.steps_per_sync : 8u;
+      if (tune.steps_per_sync <= 0 && reals.size() == 1) {
+        Ctl c{};
+        QSGS_TRY(read_ctl(0, &c));
+        chunk = 16;
+        if (c.step > 0 && c.last_new > 0)
+          chunk = (uint32_t)std::max<uint64_t>(
+              1, std::min<uint64_t>(16, (c.s_star - c.cnt) / c.last_new));
+        else if (c.step > 0)
+          chunk = 4;
+      }
+      for (uint32_t k = 0; k < chunk; ++k) QSGS_TRY(step(profiling ? &ev : nullptr));
+      QSGS_TRY(read_bctl(&b));
+    }
+    if (profiling && !ev.empty()) {
+      std::vector<Real> fin;
+      QSGS_TRY(read_all(&fin));
+      int32_t active = 0;
+      for (const Real& R : fin) active = std::max(active, R.ctl.step);
+      QSGS_TRY(record_profile(ev, (size_t)active));
+    }
+    return QSGS_OK;
+  }
+};
+
+}  // namespace host
+}  // namespace qsgs

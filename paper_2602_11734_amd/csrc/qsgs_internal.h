@@ -1,4 +1,10 @@
 // qsgs_internal.h -- types shared by the kernels and the host side of libqsgs.
+//
+// Every entry point runs a batch of realizations (one for qsgs_generate, qsgs_seed
+// and qsgs_grow_step).  A realization is described by a Real record in device
+// memory; per-step kernels walk the concatenation of all realizations' item lists
+// through an offset table in which each realization's range is padded to a
+// multiple of the wavefront size, so every wavefront serves one realization.
 #pragma once
 
 #include "qsgs_device.h"
@@ -29,7 +35,7 @@ struct Geometry {
 };
 
 // Spacing buckets: cubes of edge B = s - 1 over the grid; conflicts (L1 <= radius = s - 1)
-// lie within one bucket step in each axis.
+// lie within one bucket step in each axis.  nb = 0 when there is no spacing (s <= 1).
 struct Buckets {
   FastDiv edge;
   uint32_t nbx, nby, nbz, nb;
@@ -43,11 +49,10 @@ constexpr int32_t kStatusDone = 1, kStatusExhausted = 2, kStatusMaxSteps = 3,
 // Seed candidate states during the spacing rounds.
 constexpr uint8_t kLive = 0, kAccepted = 1, kDead = 2;
 
-constexpr int kScanBlock = 1024;        // items per workgroup of the bucket scan
+constexpr int kScanBlock = 1024;       // items per workgroup of the bucket scan
 constexpr uint32_t kMaxRounds = 4096;  // spacing rounds (a safety cap; typical runs use < 40)
-constexpr uint32_t kLogCap = 65536;    // steps recorded in the per-step log
 
-// Device control block: the growth loop's state, carried between kernels.
+// Loop state of one realization, carried between kernels.
 struct Ctl {
   uint64_t cnt;         // solid count at the start of step `step`
   uint64_t s_star;      // target count S*
@@ -67,77 +72,76 @@ struct Ctl {
   uint32_t n_seeds;     // accepted seeds
 };
 
-struct CtlInit {
-  uint64_t cnt, s_star, t_ref[3];
-  uint32_t front_size, cur;
-  int32_t step, max_steps;
-};
+// Phase of a realization record: an empty slot, waiting for the seeding kernels,
+// or in the growth loop (finished ones keep this phase with a non-zero status).
+constexpr uint32_t kPhaseEmpty = 0, kPhaseSeed = 1, kPhaseGrow = 2;
 
-struct SeedArgs {
-  Geometry g;
-  uint8_t* grid;
-  int32_t* cand;
-  Ctl* ctl;
-  uint64_t t_seed;
-  uint32_t k0, k1;
-};
-
-struct MarkArgs {
-  uint8_t* grid;
-  const int32_t* list;
-  Ctl* ctl;
-};
-
-struct BucketArgs {
+// One realization of a batch.
+struct Real {
   Geometry g;
   Buckets bk;
-  const int32_t* cand;
-  uint32_t* counts;         // per-bucket counts, scanned in place into offsets
-  uint32_t* cursor;         // scatter cursors (a copy of the offsets)
-  const uint32_t* offsets;  // == counts after the scan; nb + 1 entries
+  uint8_t* grid;        // caller's grid, qsgs_grid_bytes bytes
+  int32_t* f0;          // front buffers, cap entries each
+  int32_t* f1;
+  int32_t* cand;        // candidates, then the seed list (N entries)
+  uint64_t* log;        // per-step log (3 words per step) or null
+  uint32_t log_cap;
+  uint32_t cap;
+  uint32_t boff;        // first bucket of this realization in the batch's bucket arrays
+  uint32_t k0, k1;      // Philox key
+  uint64_t t_seed;
+  int32_t spacing;
+  uint32_t phase;
+  Ctl ctl;
+};
+
+// Batch-wide state.
+struct BatchCtl {
+  uint32_t running;     // realizations still growing after the last step end
+  uint32_t n_sorted;    // bucket-sorted candidates of the spacing rounds
+  uint32_t pad[2];
+};
+
+// What an offset table counts per realization.
+enum ItemKind : uint32_t {
+  kItemsVoxels = 0,  // every voxel (seed draw)
+  kItemsCand = 1,    // seed candidates
+  kItemsSeeds = 2,   // accepted seeds (front construction)
+  kItemsGrow = 3,    // F_t of running realizations
+  kItemsPrune = 4,   // F_t + New_t of running realizations
+};
+
+struct BatchArgs {
+  Real* reals;
+  uint32_t count;
+  uint64_t* off;        // count + 1 item offsets (multiples of kWave)
+  BatchCtl* bctl;
+  uint32_t* live;       // per-round count of undecided candidates
+  // bucket-sorted candidates of all realizations with spacing
+  uint32_t* counts;     // per-bucket counts, scanned in place into offsets
+  uint32_t* cursor;
   int32_t* sorted_v;
+  uint32_t* sorted_r;
   uint64_t* sorted_prio;
   uint8_t* status;
-  uint32_t* live;           // per-round count of undecided candidates
-  Ctl* ctl;
-  uint32_t k0, k1;
 };
 
-struct FrontInitArgs {
-  Geometry g;
-  const uint8_t* grid;
-  const int32_t* seeds;
-  int32_t* out;
-  uint32_t cap;
-  Ctl* ctl;
-};
-
-struct StepArgs {
-  Geometry g;
-  uint8_t* grid;
-  int32_t* f0;
-  int32_t* f1;
-  uint32_t cap;
-  Ctl* ctl;
-  uint32_t k0, k1;
-};
-
-__global__ void k_ctl_init(Ctl* ctl, CtlInit init, uint32_t* live, uint32_t n_live);
+__global__ void k_ctl_init(BatchArgs A, uint32_t zero_live);
+__global__ void k_offsets(BatchArgs A, uint32_t kind);
 __global__ void k_fill_u32(uint32_t* p, uint32_t value, uint32_t n);
-__global__ void k_seed_draw(SeedArgs A);
-__global__ void k_mark_all_seeds(MarkArgs A);
-__global__ void k_bucket_count(BucketArgs A);
 __global__ void k_scan_local(uint32_t* data, uint32_t n, uint32_t* sums);
 __global__ void k_scan_add(uint32_t* data, uint32_t n, const uint32_t* sums);
-__global__ void k_bucket_scatter(BucketArgs A);
-__global__ void k_luby_round(BucketArgs A, uint32_t round);
-__global__ void k_collect_seeds(BucketArgs A, int32_t* seeds, uint8_t* grid);
-__global__ void k_front_init(FrontInitArgs A);
-__global__ void k_loop_init(Ctl* ctl, uint32_t cur);
-__global__ void k_loop_resume(Ctl* ctl);
-__global__ void k_grow(StepArgs A);
-__global__ void k_prune(StepArgs A);
-__global__ void k_step_end(Ctl* ctl, uint64_t* log, uint32_t log_cap);
+__global__ void k_seed_draw(BatchArgs A);
+__global__ void k_bucket_count(BatchArgs A);
+__global__ void k_bucket_scatter(BatchArgs A, uint32_t total_buckets);
+__global__ void k_luby_round(BatchArgs A, uint32_t round);
+__global__ void k_collect_seeds(BatchArgs A);
+__global__ void k_front_init(BatchArgs A);
+__global__ void k_loop_init(BatchArgs A);
+__global__ void k_loop_resume(BatchArgs A);
+__global__ void k_grow(BatchArgs A);
+__global__ void k_prune(BatchArgs A);
+__global__ void k_step_end(BatchArgs A);
 __global__ void k_rollback(uint8_t* grid, uint32_t n);
 
 }  // namespace qsgs

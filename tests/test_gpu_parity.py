@@ -223,3 +223,129 @@ GOLD_NAMES = sorted(_golden().keys())
 @pytest.mark.parametrize("name", GOLD_NAMES)
 def test_full_size_matches_oracle_golden(q, name):
     _golden_check(q, _golden()[name])
+
+
+def test_batch_matches_oracle(q, orc):
+    """Uneven realizations (sizes, spacing, degenerate cases) in one batch: each result
+    equals the oracle's run of that realization alone."""
+    import torch
+    cases = workloads.small_cases() + workloads.config1()
+    params = [q.params_of(c) for c in cases]
+    dims = [c.dims for c in cases]
+    grids = [torch.empty(q.qsgs_grid_bytes(d), dtype=torch.uint8, device="cuda") for d in dims]
+    wsb = q.qsgs_batch_workspace_bytes(dims, params)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    say("GPU generate_batch of", len(cases))
+    st, infos = q.qsgs_generate_batch(dims, params, grids, ws, wsb)
+    torch.cuda.synchronize()
+    for k, (c, g, info) in enumerate(zip(cases, grids, infos)):
+        ref = run_oracle(orc, c)
+        nx, ny, nz = c.dims
+        got = g[: nx * ny * nz].view(nz, ny, nx).cpu().numpy()
+        assert info.status == ref.status, c.name
+        assert info.step == ref.steps and info.solid_count == ref.solid_count, c.name
+        assert info.n_seeds == ref.n_seeds and info.front_size == ref.front_size, c.name
+        assert np.array_equal(got, ref.grid), c.name
+        lf, ln, lc = q.qsgs_read_step_log(ws, wsb, index=k)
+        assert np.array_equal(lf, ref.log_front[: len(lf)]) and len(lf) == min(ref.steps, 4096)
+        assert np.array_equal(ln, ref.log_new[: len(ln)])
+        assert np.array_equal(lc, ref.log_count[: len(lc)])
+
+
+def test_batch_reuses_workspace(q, orc):
+    """Two batches in a row on one workspace, the second smaller and with other keys."""
+    import torch
+    base = workloads.small_cases()[:6]
+    for rnd, cases in enumerate((base, base[1:4])):
+        cases = [workloads.Case(**{**c.as_dict(), "key": c.key + 1000 * rnd}) for c in cases]
+        params = [q.params_of(c) for c in cases]
+        dims = [c.dims for c in cases]
+        grids = [torch.empty(q.qsgs_grid_bytes(d), dtype=torch.uint8, device="cuda")
+                 for d in dims]
+        if rnd == 0:
+            wsb = q.qsgs_batch_workspace_bytes(dims, params)
+            ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        assert q.qsgs_batch_workspace_bytes(dims, params) <= wsb
+        say("GPU generate_batch round", rnd)
+        q.qsgs_generate_batch(dims, params, grids, ws, wsb)
+        for c, g in zip(cases, grids):
+            ref = run_oracle(orc, c)
+            nx, ny, nz = c.dims
+            assert np.array_equal(g[: nx * ny * nz].view(nz, ny, nx).cpu().numpy(), ref.grid)
+
+
+def test_server_results_equal_solo_runs(q, orc):
+    """Requests of mixed sizes through the continuous-batching server with an arena
+    small enough that admission has to wait: every result equals the oracle's run of
+    that request alone, and the arena is fully returned at the end."""
+    import torch
+    cases = workloads.small_cases()[:10] + workloads.config1()
+    reserved = q.qsgs_server_reserved_bytes(4)
+    # the 64^3 request needs ~30 N bytes with its seeding scratch: admission binds
+    arena_bytes = reserved + 40 * 64**3
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    srv = q.qsgs_server_create(arena, arena_bytes, 4, steps_per_tick=2)
+    try:
+        free0 = q.qsgs_server_free_bytes(srv)
+        pending = list(enumerate(cases))
+        results = {}
+        ticks = 0
+        max_resident = 0
+        while len(results) < len(cases):
+            if pending and ticks % 2 == 0:  # staggered arrivals
+                rid, c = pending.pop(0)
+                q.qsgs_server_submit(srv, rid, c.dims, q.params_of(c))
+            say("server tick", ticks)
+            res, queued, nready = q.qsgs_server_tick(srv)
+            max_resident = max(max_resident, res)
+            for rid, info in q.qsgs_server_ready(srv):
+                c = cases[rid]
+                nx, ny, nz = c.dims
+                out = np.empty(nx * ny * nz, dtype=np.uint8)
+                q.qsgs_server_take(srv, rid, out)
+                results[rid] = (out.reshape(nz, ny, nx), info)
+            ticks += 1
+            assert ticks < 2000
+        assert max_resident >= 2  # requests overlapped on the device
+        assert q.qsgs_server_free_bytes(srv) == free0
+    finally:
+        q.qsgs_server_destroy(srv)
+    for rid, c in enumerate(cases):
+        grid, info = results[rid]
+        ref = run_oracle(orc, c)
+        assert info.status == ref.status and info.step == ref.steps, c.name
+        assert info.solid_count == ref.solid_count, c.name
+        assert np.array_equal(grid, ref.grid), c.name
+
+
+def test_server_rejects_oversized_request(q):
+    import torch
+    reserved = q.qsgs_server_reserved_bytes(2)
+    arena = torch.empty(reserved + (1 << 20), dtype=torch.uint8, device="cuda")
+    srv = q.qsgs_server_create(arena, arena.numel(), 2)
+    try:
+        c = workloads.config1()[0]
+        with pytest.raises(q.QsgsError) as e:
+            q.qsgs_server_submit(srv, 1, c.dims, q.params_of(c))
+        assert e.value.status == q.ERR_CAPACITY
+    finally:
+        q.qsgs_server_destroy(srv)
+
+
+def test_tuning_does_not_change_results(q, orc):
+    case = workloads.small_cases()[0]
+    ref = run_oracle(orc, case)
+    try:
+        for t in ({"grow_block": 64, "grow_grid": 8, "prune_block": 512, "prune_grid": 64,
+                   "seed_block": 128, "seed_grid": 16, "steps_per_sync": 1},
+                  {"grow_block": 512, "grow_grid": 4096, "prune_block": 128, "prune_grid": 1024,
+                   "seed_block": 512, "seed_grid": 4096, "steps_per_sync": 5}):
+            q.qsgs_set_tuning(t)
+            got, info, _ = run_gpu(q, case)
+            assert np.array_equal(got, ref.grid) and info["step"] == ref.steps
+    finally:
+        q.qsgs_set_tuning(None)
+    with pytest.raises(q.QsgsError):
+        q.qsgs_set_tuning({"grow_block": 100, "grow_grid": 8, "prune_block": 64,
+                           "prune_grid": 8, "seed_block": 64, "seed_grid": 8,
+                           "steps_per_sync": 0})
