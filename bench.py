@@ -25,18 +25,22 @@ import workloads  # noqa: E402
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 
-def grow_bytes(front, grown):
-    """Algorithmic bytes of one growth-sweep launch: read the front list (4 B per
-    entry), read each front voxel's occupancy neighbourhood (counted as 2 B per front
-    voxel: the voxel and, on average, one void neighbour of the 26-dilated band),
-    write the new voxels (1 B claim in the grid + 4 B list append)."""
-    return 4 * front + 2 * front + 5 * grown
-
-
-def prune_bytes(front, grown, next_front):
-    """Algorithmic bytes of one prune launch: read F_t and New_t (4 B each), their
-    occupancy (2 B per entry as above), fold the new voxels (1 B), write F_{t+1} (4 B)."""
-    return 6 * (front + grown) + grown + 4 * next_front
+def sweep_pass_bytes(log_front, log_new, n_seeds, final_front):
+    """Algorithmic bytes of every fused-sweep pass of one generation (one pass per step
+    plus the final prune-only pass).  Pass t reads L_t = F_{t-1} + New_{t-1} (4 B per
+    entry) and each entry's own grid byte (1 B; the rest of its 3x3x3 neighbourhood is
+    shared with neighbouring entries), folds New_{t-1} (1 B each), claims New_t (1 B
+    each) and writes L_{t+1} = F_t + New_t (4 B per entry).  L_0 is the seed list."""
+    out = []
+    prev_f, prev_n = None, None
+    fronts = list(log_front) + [final_front]
+    news = list(log_new) + [0]
+    for t, (f, g) in enumerate(zip(fronts, news)):
+        l_in = n_seeds if t == 0 else prev_f + prev_n
+        folded = 0 if t == 0 else prev_n
+        out.append(5 * l_in + folded + g + 4 * (f + g))
+        prev_f, prev_n = f, g
+    return out
 
 
 def cpu_baseline(case, steps: int):
@@ -110,21 +114,14 @@ def main():
 
     grown = sum(info["solid_count"] - info["n_seeds"] for _, info, _, _ in runs)
     value = grown / elapsed
-    # algorithmic bytes over the timed growth launches (steps actually taken)
-    gbytes = 0
-    pbytes = 0
-    launches = 0
-    for _, info, lf, ln in runs:
-        nxt = list(lf[1:]) + [info["front_size"]]
-        for f, g, nf in zip(lf, ln, nxt):
-            gbytes += grow_bytes(int(f), int(g))
-            pbytes += prune_bytes(int(f), int(g), int(nf))
-            launches += 1
+    # algorithmic bytes of the timed sweep launches (every pass of every generation)
+    passes = [sweep_pass_bytes(lf, ln, info["n_seeds"], info["front_size"])
+              for _, info, lf, ln in runs]
+    launches = sum(len(x) for x in passes)
+    sbytes = sum(sum(x) for x in passes)
     assert launches == int(prof["grow_launches"]), (launches, prof)
-    grow_avg_ms = prof["grow_ms"] / max(prof["grow_launches"], 1)
-    prune_avg_ms = prof["prune_ms"] / max(prof["prune_launches"], 1)
-    grow_gbs = (gbytes / launches) / (grow_avg_ms * 1e-3) / 1e9 if launches else 0.0
-    prune_gbs = (pbytes / launches) / (prune_avg_ms * 1e-3) / 1e9 if launches else 0.0
+    sweep_avg_ms = prof["grow_ms"] / max(launches, 1)
+    sweep_gbs = (sbytes / launches) / (sweep_avg_ms * 1e-3) / 1e9 if launches else 0.0
 
     per_case = {}
     for name, info, lf, ln in runs:
@@ -150,15 +147,12 @@ def main():
                                "G_ref 0.01/0.0025/0.000625, diamond spacing s=20, key 1; "
                                "one step = the three generations end to end",
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": grow_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": grow_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_grow", "avg_launch_ms": grow_avg_ms,
-                     "launches": launches},
-        "detail": {"grow_ms_total": prof["grow_ms"], "prune_ms_total": prof["prune_ms"],
-                   "prune_avg_ms": prune_avg_ms, "prune_gbs": prune_gbs,
-                   "seed_ms_total": prof["seed_ms"],
-                   "growth_only_voxels_per_s": grown / ((prof["grow_ms"] + prof["prune_ms"])
-                                                         * 1e-3),
+        "roofline": {"bound": "hbm", "achieved": sweep_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": sweep_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_sweep", "avg_launch_ms": sweep_avg_ms,
+                     "launches": launches, "bytes_per_launch": sbytes / max(launches, 1)},
+        "detail": {"sweep_ms_total": prof["grow_ms"], "seed_ms_total": prof["seed_ms"],
+                   "growth_only_voxels_per_s": grown / (prof["grow_ms"] * 1e-3),
                    "n_over_t_per_realization": cases[0].n * 3 * args.steps / elapsed,
                    "realizations": per_case},
     }

@@ -83,9 +83,10 @@ typedef struct {
   int32_t status;         /* a qsgs_status value >= 0                                       */
 } qsgs_info;
 
-/* Bytes a grid buffer needs: N rounded up to a multiple of 4 (the growth step claims
- * voxels with 32-bit atomics).  The voxels occupy the first N bytes; the rest is
- * padding the library never changes.  0 for invalid dims. */
+/* Bytes a grid buffer needs: N + 8 rounded up to a multiple of 4.  The voxels occupy the
+ * first N bytes; the padding lets the growth kernels claim voxels with 32-bit atomics and
+ * read rows with 8-byte loads.  The library never changes the padding's value (the
+ * claim atomics OR zero into it).  0 for invalid dims. */
 size_t qsgs_grid_bytes(const qsgs_dims* dims);
 
 /* Workspace bytes for qsgs_seed and qsgs_generate with these dims and parameters
@@ -146,7 +147,7 @@ qsgs_status qsgs_generate(const qsgs_dims* dims, const qsgs_params* params, uint
  * parameters share one persistent launch per kernel per growth step, addressed
  * through a per-realization offset table.  Each result is bit-identical to
  * qsgs_generate of the same realization alone.
- *   dims, params  host arrays of `count` entries.
+ *   dims, params  host arrays of `count` entries, 1 <= count <= 4096.
  *   d_grids       host array of `count` device grid pointers (qsgs_grid_bytes each,
  *                 4-byte aligned).
  *   d_ws          device workspace, ws_bytes >= qsgs_batch_workspace_bytes(count, dims, params).
@@ -171,7 +172,7 @@ int64_t qsgs_read_step_log(const void* d_ws, size_t ws_bytes, int32_t index, int
 
 /* Continuous-batching server.  Generation requests of different sizes are queued on
  * the host; each tick admits queued requests in arrival order while a slot is free and
- * their footprint -- grid (qsgs_grid_bytes) plus two front lists (4 N bytes each) --
+ * their footprint -- grid (qsgs_grid_bytes) plus two lists (8 N bytes each) --
  * fits the free part of the caller's device arena (the HBM budget), seeds them (with
  * transient seeding scratch from the same arena), then advances every resident
  * realization by `steps_per_tick` growth steps in shared launches.  A finished
@@ -180,7 +181,7 @@ int64_t qsgs_read_step_log(const void* d_ws, size_t ws_bytes, int32_t index, int
  * used from one thread; its stream orders all of its work.
  *   qsgs_server_reserved_bytes  arena bytes the server keeps for its control area.
  *   qsgs_server_create   d_arena: device, 256-byte aligned, arena_bytes long, owned by
- *                        the caller until qsgs_server_destroy; max_slots in [1, 65536];
+ *                        the caller until qsgs_server_destroy; max_slots in [1, 4096];
  *                        steps_per_tick in [1, 1024].
  *   qsgs_server_submit   queues one request; QSGS_ERR_INVALID for bad dims/params or an
  *                        id in use, QSGS_ERR_CAPACITY if it cannot fit the arena even

@@ -1,0 +1,110 @@
+"""Autotuner for the launch shape of the item kernels.
+
+Times every candidate (workgroup size x workgroup count of the fused sweep and of the
+seeding kernels) on the given workload with the library's own kernel timers, checks
+that every candidate produces the same grids (the shape must never change a result),
+applies the fastest, and caches it per device and workload size bucket.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+import os
+import time
+
+from . import (QsgsError, params_of, qsgs_generate_batch, qsgs_batch_workspace_bytes,
+               qsgs_grid_bytes, qsgs_profile_enable, qsgs_profile_read, qsgs_set_tuning,
+               qsgs_tuning)
+
+SWEEP_BLOCKS = (128, 256, 512)
+SWEEP_GRIDS = (512, 1024, 2048, 4096)
+SEED_SHAPES = ((256, 2048), (512, 4096))
+
+
+def cache_path() -> str:
+    base = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(base, "qsgs", "tuning.json")
+
+
+def bucket_of(cases) -> str:
+    total = sum(c.n for c in cases)
+    return f"n{len(cases)}_v2^{int(math.log2(max(total, 1)))}"
+
+
+def _device_name() -> str:
+    import torch
+    return torch.cuda.get_device_name(0)
+
+
+def _run(cases, grids, ws, wsb):
+    import torch
+    dims = [c.dims for c in cases]
+    params = [params_of(c) for c in cases]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qsgs_generate_batch(dims, params, grids, ws, wsb)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def autotune(cases, repeats: int = 2, use_cache: bool = True, verbose: bool = False) -> dict:
+    """Returns (and applies) the fastest tuning for this batch of cases."""
+    import torch
+    key = f"{_device_name()}|{bucket_of(cases)}"
+    path = cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+        if key in cache:
+            qsgs_set_tuning(cache[key]["tuning"])
+            return cache[key]
+    dims = [c.dims for c in cases]
+    params = [params_of(c) for c in cases]
+    grids = [torch.empty(qsgs_grid_bytes(d), dtype=torch.uint8, device="cuda") for d in dims]
+    wsb = qsgs_batch_workspace_bytes(dims, params)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    results = []
+    ref_digest = None
+    try:
+        for sb, sg in SEED_SHAPES:
+            for b in SWEEP_BLOCKS:
+                for g in SWEEP_GRIDS:
+                    t = {"grow_block": b, "grow_grid": g, "prune_block": b, "prune_grid": g,
+                         "seed_block": sb, "seed_grid": sg, "steps_per_sync": 0}
+                    qsgs_set_tuning(t)
+                    _run(cases, grids, ws, wsb)  # warm-up
+                    qsgs_profile_enable(True)
+                    qsgs_profile_read(reset=True)
+                    wall = min(_run(cases, grids, ws, wsb) for _ in range(repeats))
+                    prof = qsgs_profile_read(reset=True)
+                    qsgs_profile_enable(False)
+                    h = hashlib.sha256()
+                    for d, gr in zip(dims, grids):
+                        h.update(gr[: d[0] * d[1] * d[2]].cpu().numpy().tobytes())
+                    digest = h.hexdigest()
+                    if ref_digest is None:
+                        ref_digest = digest
+                    elif digest != ref_digest:
+                        raise QsgsError(-4, f"tuning {t} changed the result")
+                    results.append((wall, t, prof))
+                    if verbose:
+                        print(f"tune {t}: {wall * 1e3:.2f} ms", flush=True)
+    finally:
+        qsgs_set_tuning(None)
+    wall, best, prof = min(results, key=lambda r: r[0])
+    entry = {"tuning": best, "wall_ms": wall * 1e3, "candidates": len(results),
+             "default_wall_ms": next(r[0] for r in results
+                                     if r[1]["grow_block"] == 256 and r[1]["grow_grid"] == 2048
+                                     and r[1]["seed_block"] == 256) * 1e3}
+    qsgs_set_tuning(best)
+    if use_cache:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        cache[key] = entry
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return entry
+
+
+__all__ = ["autotune", "cache_path", "bucket_of", "qsgs_tuning"]

@@ -7,7 +7,7 @@ using namespace qsgs::host;
 
 namespace {
 
-constexpr size_t kStepWorkspace = 64 * 1024;
+constexpr size_t kStepWorkspace = 1024 * 1024;
 
 // Workspace of qsgs_generate / qsgs_generate_batch: the persistent part, the two front
 // lists of every realization, then the seeding scratch of the whole batch.
@@ -25,20 +25,21 @@ GenLayout gen_layout(const std::vector<Spec>& specs, bool with_fronts) {
   if (with_fronts) {
     for (const Spec& s : specs) {
       G.f0.push_back(off);
-      off = align_up(off + sizeof(int32_t) * s.g.n);
+      off = align_up(off + 2 * sizeof(int32_t) * s.g.n);
       G.f1.push_back(off);
-      off = align_up(off + sizeof(int32_t) * s.g.n);
+      off = align_up(off + 2 * sizeof(int32_t) * s.g.n);
     }
   }
   G.seed = off;
-  G.S = seed_layout(specs);
+  G.S = seed_layout(specs, !with_fronts);
   G.total = off + G.S.total;
   return G;
 }
 
 qsgs_status make_specs(int32_t count, const qsgs_dims* dims, const qsgs_params* params,
                        uint8_t* const* grids, std::vector<Spec>* specs) {
-  if (count < 1) return fail(QSGS_ERR_INVALID, "count must be >= 1");
+  if (count < 1 || (uint32_t)count > kMaxBatch)
+    return fail(QSGS_ERR_INVALID, "count must be in [1, %u]", kMaxBatch);
   if (!dims || !params || !grids) return fail(QSGS_ERR_INVALID, "NULL array argument");
   specs->resize((size_t)count);
   for (int32_t r = 0; r < count; ++r) {
@@ -64,7 +65,7 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
   std::vector<size_t> group;
   for (int32_t r = 0; r < count; ++r) {
     E.init_record((size_t)r, specs[r], &params[r], grids[r], at<int32_t>(ws, G.f0[r]),
-                  at<int32_t>(ws, G.f1[r]), specs[r].g.n);
+                  at<int32_t>(ws, G.f1[r]), 2 * specs[r].g.n);
     group.push_back((size_t)r);
   }
   E.attach_scratch(group, at<void>(ws, G.seed), G.S);
@@ -77,10 +78,12 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
     QSGS_HIP(hipEventRecord(e0, s));
   }
   QSGS_TRY(E.upload_header());
+  QSGS_TRY(E.upload_control());
   QSGS_TRY(E.upload(0, E.reals.size()));
-  QSGS_TRY(E.seed(at<void>(ws, G.seed), G.S));
+  QSGS_TRY(E.seed_core(at<void>(ws, G.seed), G.S));
+  QSGS_TRY(E.sweep_start());
   if (profiling) QSGS_HIP(hipEventRecord(e1, s));
-  QSGS_TRY(E.run_loop());
+  QSGS_TRY(E.run_sweep_loop());
   std::vector<Real> fin;
   QSGS_TRY(E.read_all(&fin));
   if (profiling) {
@@ -147,7 +150,8 @@ qsgs_status qsgs_seed(const qsgs_dims* dims, const qsgs_params* params, uint8_t*
   E.attach_scratch({0}, at<void>(d_ws, G.seed), G.S);
   QSGS_TRY(E.upload_header());
   QSGS_TRY(E.upload(0, 1));
-  QSGS_TRY(E.seed(at<void>(d_ws, G.seed), G.S));
+  QSGS_TRY(E.seed_core(at<void>(d_ws, G.seed), G.S));
+  QSGS_TRY(E.seed_fronts());
   Ctl h{};
   QSGS_TRY(E.read_ctl(0, &h));
   if (h.status == kStatusOverflow)
@@ -264,8 +268,9 @@ qsgs_status qsgs_set_tuning(const qsgs_tuning* t) {
       if (blocks[k] < 64 || blocks[k] > (uint32_t)kMaxBlock || blocks[k] % 64)
         return fail(QSGS_ERR_INVALID, "block sizes must be multiples of 64 in [64, %d]",
                     kMaxBlock);
-      if (grids[k] < 8 || grids[k] > 65536 || grids[k] % 8)
-        return fail(QSGS_ERR_INVALID, "grid sizes must be multiples of 8 in [8, 65536]");
+      if (grids[k] < 8 || grids[k] > kMaxSweepGrid || grids[k] % 8)
+        return fail(QSGS_ERR_INVALID, "grid sizes must be multiples of 8 in [8, %u]",
+                    kMaxSweepGrid);
     }
     if (t->steps_per_sync < 0 || t->steps_per_sync > 1024)
       return fail(QSGS_ERR_INVALID, "steps_per_sync must be in [0, 1024]");

@@ -128,7 +128,9 @@ inline qsgs_status check_grid(const uint8_t* grid) {
   return QSGS_OK;
 }
 
-inline size_t grid_bytes(const Geometry& g) { return ((size_t)g.n + 3) / 4 * 4; }
+// N bytes of voxels, rounded up to a multiple of 4 for the 32-bit claim atomics, plus
+// 8 bytes of padding read (never written) by the 8-byte neighbourhood windows.
+inline size_t grid_bytes(const Geometry& g) { return ((size_t)g.n + 8 + 3) / 4 * 4; }
 
 inline Buckets make_buckets(const Geometry& g, int32_t spacing) {
   Buckets b{};
@@ -178,7 +180,9 @@ struct WsHeader {
 // table, round counters and per-step logs.
 struct PersistLayout {
   size_t hdr = 0, bctl = 0, reals = 0, off = 0, live = 0, logs = 0, total = 0;
-  uint32_t log_cap = 0;
+  size_t seg[2] = {0, 0}, segchunk[2] = {0, 0}, rseg[2] = {0, 0}, wgoff[2] = {0, 0};
+  size_t wgkept = 0, tailfill = 0;
+  uint32_t log_cap = 0, seg_cap = 0;
 };
 
 inline PersistLayout persist_layout(size_t count, uint32_t log_cap) {
@@ -196,6 +200,15 @@ inline PersistLayout persist_layout(size_t count, uint32_t log_cap) {
   L.off = take(sizeof(uint64_t) * (count + 1));
   L.live = take(sizeof(uint32_t) * kMaxRounds);
   L.logs = take(sizeof(uint64_t) * 3 * (size_t)log_cap * count);
+  L.seg_cap = kMaxSweepGrid + 2 * (uint32_t)count + 8;
+  for (int q = 0; q < 2; ++q) {
+    L.seg[q] = take(sizeof(SegEntry) * L.seg_cap);
+    L.segchunk[q] = take(sizeof(uint32_t) * (L.seg_cap + 1));
+    L.rseg[q] = take(sizeof(uint32_t) * (count + 1));
+    L.wgoff[q] = take(sizeof(uint32_t) * (count + 1));
+  }
+  L.wgkept = take(sizeof(uint32_t) * kMaxSweepGrid);
+  L.tailfill = take(sizeof(uint32_t) * count);
   L.total = off;
   return L;
 }
@@ -209,7 +222,7 @@ struct SeedLayout {
   uint32_t total_buckets = 0;
 };
 
-inline SeedLayout seed_layout(const std::vector<Spec>& specs) {
+inline SeedLayout seed_layout(const std::vector<Spec>& specs, bool with_cand = true) {
   SeedLayout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -236,7 +249,8 @@ inline SeedLayout seed_layout(const std::vector<Spec>& specs) {
   L.sorted_r = take(sizeof(uint32_t) * sorted);
   L.prio = take(sizeof(uint64_t) * sorted);
   L.status = take(sorted);
-  for (const Spec& s : specs) L.cand.push_back(take(sizeof(int32_t) * s.g.n));
+  for (const Spec& s : specs)
+    L.cand.push_back(with_cand ? take(sizeof(int32_t) * s.g.n) : (size_t)-1);
   L.total = off;
   return L;
 }
@@ -303,6 +317,7 @@ struct Engine {
   BatchArgs args{};
   Tuning tune;
   WsHeader hdr{};
+  uint32_t sweep_grid = 2048;
 
   // Binds the engine to a persistent region of `count` records at `base`.
   void bind(void* base, const PersistLayout& L, size_t count, hipStream_t stream) {
@@ -317,6 +332,27 @@ struct Engine {
     args.off = at<uint64_t>(base, L.off);
     args.bctl = at<BatchCtl>(base, L.bctl);
     args.live = at<uint32_t>(base, L.live);
+    for (int q = 0; q < 2; ++q) {
+      args.plan[q].seg = at<SegEntry>(base, L.seg[q]);
+      args.plan[q].segchunk = at<uint32_t>(base, L.segchunk[q]);
+      args.plan[q].rseg = at<uint32_t>(base, L.rseg[q]);
+      args.plan[q].wgoff = at<uint32_t>(base, L.wgoff[q]);
+    }
+    args.seg_cap = L.seg_cap;
+    args.wgkept = at<uint32_t>(base, L.wgkept);
+    args.tailfill = at<uint32_t>(base, L.tailfill);
+    const uint32_t want = std::max<uint32_t>(tune.grow_grid, 2 * (uint32_t)count);
+    sweep_grid = std::min<uint32_t>(kMaxSweepGrid, (want + kNumXcd - 1) / kNumXcd * kNumXcd);
+  }
+
+  // Control block, plan index and the zeroed tail counters: once per engine.
+  qsgs_status upload_control() {
+    BatchCtl b{};
+    b.grid = sweep_grid;
+    QSGS_HIP(hipMemcpyAsync(args.bctl, &b, sizeof b, hipMemcpyHostToDevice, s));
+    QSGS_HIP(hipMemsetAsync(args.tailfill, 0, sizeof(uint32_t) * reals.size(), s));
+    QSGS_HIP(hipMemsetAsync(args.plan[0].rseg, 0, sizeof(uint32_t) * (reals.size() + 1), s));
+    return QSGS_OK;
   }
 
   dim3 rgrid() const { return dim3(((uint32_t)reals.size() + 255) / 256); }
@@ -326,7 +362,8 @@ struct Engine {
     return at<uint64_t>(ws, P.logs) + (size_t)3 * P.log_cap * r;
   }
 
-  // Fills record r for a new realization (to be seeded).
+  // Fills record r for a new realization (to be seeded).  The fused sweep's lists
+  // f0 / f1 hold 2 N entries each (parts in the first half, spills in the second).
   void init_record(size_t r, const Spec& sp, const qsgs_params* p, uint8_t* grid, int32_t* f0,
                    int32_t* f1, uint32_t cap) {
     Real& R = reals[r];
@@ -361,6 +398,7 @@ struct Engine {
   }
 
   qsgs_status offsets(ItemKind kind) {
+    if (reals.size() == 1 && kind != kItemsPrune) return QSGS_OK;  // kernels count directly
     hipLaunchKernelGGL(k_offsets, dim3(1), dim3(1024), 0, s, args, (uint32_t)kind);
     QSGS_LAUNCHED("k_offsets");
     return QSGS_OK;
@@ -384,7 +422,8 @@ struct Engine {
     uint32_t boff = 0;
     for (size_t k = 0; k < group.size(); ++k) {
       Real& R = reals[group[k]];
-      R.cand = at<int32_t>(scratch, L.cand[k]);
+      // without a candidate slice the candidates (then the seeds, i.e. L_0) go to f0
+      R.cand = L.cand[k] == (size_t)-1 ? R.f0 : at<int32_t>(scratch, L.cand[k]);
       R.boff = boff;
       boff += R.bk.nb;
     }
@@ -396,9 +435,8 @@ struct Engine {
     args.status = at<uint8_t>(scratch, L.status);
   }
 
-  // a1-a3 for every record in the seeding phase: candidates, spacing, seeds, the first
-  // front and the loop state of step 0.
-  qsgs_status seed(void* scratch, const SeedLayout& L) {
+  // a1-a2 for every record in the seeding phase: candidates, spacing, seed lists.
+  qsgs_status seed_core(void* scratch, const SeedLayout& L) {
     const dim3 sg(tune.seed_grid), sb(tune.seed_block);
     hipLaunchKernelGGL(k_ctl_init, dim3(16), dim3(256), 0, s, args, 1u);
     QSGS_LAUNCHED("k_ctl_init");
@@ -437,6 +475,12 @@ struct Engine {
       hipLaunchKernelGGL(k_collect_seeds, sg, sb, 0, s, args);
       QSGS_LAUNCHED("k_collect_seeds");
     }
+    return QSGS_OK;
+  }
+
+  // a3 for the step-by-step path: F_0 = interface(G_0) into front buffer 0, step 0.
+  qsgs_status seed_fronts() {
+    const dim3 sg(tune.seed_grid), sb(tune.seed_block);
     QSGS_TRY(offsets(kItemsSeeds));
     hipLaunchKernelGGL(k_front_init, sg, sb, 0, s, args);
     QSGS_LAUNCHED("k_front_init");
@@ -495,6 +539,78 @@ struct Engine {
     return QSGS_OK;
   }
 
+  // Loop state of the fused sweep for freshly seeded records (L_0 = their seed lists).
+  qsgs_status sweep_start() {
+    hipLaunchKernelGGL(k_sweep_prepare, dim3(1), dim3(1024), 0, s, args);
+    QSGS_LAUNCHED("k_sweep_prepare");
+    return QSGS_OK;
+  }
+
+  // One fused pass (prune of step t-1 + growth of step t) over every record with a
+  // pending pass; the kernel's last workgroup ends the step.
+  qsgs_status sweep_pass(std::vector<hipEvent_t>* ev) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ev) {
+      e0 = prof_event();
+      e1 = prof_event();
+      QSGS_HIP(hipEventRecord(e0, s));
+    }
+    hipLaunchKernelGGL(k_sweep, dim3(sweep_grid), dim3(tune.grow_block), 0, s, args);
+    QSGS_LAUNCHED("k_sweep");
+    if (ev) {
+      QSGS_HIP(hipEventRecord(e1, s));
+      ev->push_back(e0);
+      ev->push_back(e1);
+    }
+    hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(1024), 0, s, args);
+    QSGS_LAUNCHED("k_sweep_end");
+    return QSGS_OK;
+  }
+
+  // Fused-sweep loop until every record has stopped.  A realization takes steps + 1
+  // passes (the last one only prunes and folds).  For a single realization the chunk
+  // length follows the remaining count over the last step's growth.
+  qsgs_status run_sweep_loop() {
+    const bool profiling = prof_on();
+    std::vector<hipEvent_t> ev;
+    BatchCtl b{};
+    QSGS_TRY(read_bctl(&b));
+    while (b.running > 0) {
+      uint32_t chunk = tune.steps_per_sync > 0 ? (uint32_t)tune.steps_per_sync : 8u;
+      if (tune.steps_per_sync <= 0 && reals.size() == 1) {
+        Ctl c{};
+        QSGS_TRY(read_ctl(0, &c));
+        chunk = 16;
+        if (c.mode == kModeFinal)
+          chunk = 1;
+        else if (c.step > 0 && c.last_new > 0)
+          chunk = (uint32_t)std::max<uint64_t>(
+              1, std::min<uint64_t>(16, (c.s_star - c.cnt) / c.last_new + 1));
+        else if (c.step > 0)
+          chunk = 4;
+      }
+      for (uint32_t k = 0; k < chunk; ++k) QSGS_TRY(sweep_pass(profiling ? &ev : nullptr));
+      QSGS_TRY(read_bctl(&b));
+    }
+    if (profiling && !ev.empty()) {
+      std::vector<Real> fin;
+      QSGS_TRY(read_all(&fin));
+      size_t active = 0;
+      for (const Real& R : fin) active = std::max(active, (size_t)R.ctl.step + 1);
+      const size_t n = std::min(active, ev.size() / 2);
+      double ms_total = 0;
+      for (size_t i = 0; i < n; ++i) {
+        float a = 0.f;
+        QSGS_HIP(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]));
+        ms_total += a;
+      }
+      std::lock_guard<std::mutex> lk(prof().mu);
+      prof().grow_launches += (double)n;
+      prof().grow_ms += ms_total;
+    }
+    return QSGS_OK;
+  }
+
   // Accumulates the durations of the first `active` timed steps.
   qsgs_status record_profile(const std::vector<hipEvent_t>& ev, size_t active) {
     double grow_ms = 0, prune_ms = 0;
@@ -511,39 +627,6 @@ struct Engine {
     prof().grow_ms += grow_ms;
     prof().prune_launches += (double)n;
     prof().prune_ms += prune_ms;
-    return QSGS_OK;
-  }
-
-  // Growth loop until every record has stopped.  For a single realization the chunk
-  // length follows the remaining count over the last step's growth, which bounds the
-  // steps left while growth slows down, so chunks rarely run past the end.
-  qsgs_status run_loop() {
-    const bool profiling = prof_on();
-    std::vector<hipEvent_t> ev;
-    BatchCtl b{};
-    QSGS_TRY(read_bctl(&b));
-    while (b.running > 0) {
-      uint32_t chunk = tune.steps_per_sync > 0 ? (uint32_t)tune.steps_per_sync : 8u;
-      if (tune.steps_per_sync <= 0 && reals.size() == 1) {
-        Ctl c{};
-        QSGS_TRY(read_ctl(0, &c));
-        chunk = 16;
-        if (c.step > 0 && c.last_new > 0)
-          chunk = (uint32_t)std::max<uint64_t>(
-              1, std::min<uint64_t>(16, (c.s_star - c.cnt) / c.last_new));
-        else if (c.step > 0)
-          chunk = 4;
-      }
-      for (uint32_t k = 0; k < chunk; ++k) QSGS_TRY(step(profiling ? &ev : nullptr));
-      QSGS_TRY(read_bctl(&b));
-    }
-    if (profiling && !ev.empty()) {
-      std::vector<Real> fin;
-      QSGS_TRY(read_all(&fin));
-      int32_t active = 0;
-      for (const Real& R : fin) active = std::max(active, R.ctl.step);
-      QSGS_TRY(record_profile(ev, (size_t)active));
-    }
     return QSGS_OK;
   }
 };

@@ -49,6 +49,8 @@ constexpr int32_t kStatusDone = 1, kStatusExhausted = 2, kStatusMaxSteps = 3,
 // Seed candidate states during the spacing rounds.
 constexpr uint8_t kLive = 0, kAccepted = 1, kDead = 2;
 
+constexpr uint32_t kMaxSweepGrid = 8192;  // workgroups of a fused sweep launch (at most)
+constexpr uint32_t kMaxBatch = 4096;      // realizations per batch / server slots
 constexpr int kScanBlock = 1024;       // items per workgroup of the bucket scan
 constexpr uint32_t kMaxRounds = 4096;  // spacing rounds (a safety cap; typical runs use < 40)
 
@@ -70,7 +72,21 @@ struct Ctl {
   uint32_t last_new;    // |New| of the last completed step
   uint32_t n_cand;      // seed candidates
   uint32_t n_seeds;     // accepted seeds
+  // fused sweep (qsgs_generate*, server): the list L_t = F_{t-1} + New_{t-1} in buffer
+  // `cur`, the mode of the next pass over it and the pass's counters
+  uint32_t n_list;      // |L_t|
+  uint32_t mode;        // kModeIdle / kModeRun / kModeFinal
+  uint32_t kept;        // entries of L_t kept as F_t in this pass
+  uint32_t pad0;
 };
+
+// Pass modes of the fused sweep: a running pass prunes L_t to F_t and grows from it;
+// a final pass only prunes (and folds), to report F_T and leave a clean 0/1 grid.
+constexpr uint32_t kModeIdle = 0, kModeRun = 1, kModeFinal = 2;
+
+// List entries of the fused sweep: bit 31 marks a voxel grown in the previous step,
+// whose grid value is folded to 1 by the next pass (N < 2^31 leaves the bit free).
+constexpr uint32_t kNewFlag = 0x80000000u;
 
 // Phase of a realization record: an empty slot, waiting for the seeding kernels,
 // or in the growth loop (finished ones keep this phase with a non-zero status).
@@ -86,7 +102,7 @@ struct Real {
   int32_t* cand;        // candidates, then the seed list (N entries)
   uint64_t* log;        // per-step log (3 words per step) or null
   uint32_t log_cap;
-  uint32_t cap;
+  uint32_t cap;         // entries of f0 / f1 (the fused sweep uses 2 N: two halves)
   uint32_t boff;        // first bucket of this realization in the batch's bucket arrays
   uint32_t k0, k1;      // Philox key
   uint64_t t_seed;
@@ -99,7 +115,32 @@ struct Real {
 struct BatchCtl {
   uint32_t running;     // realizations still growing after the last step end
   uint32_t n_sorted;    // bucket-sorted candidates of the spacing rounds
-  uint32_t pad[2];
+  uint32_t blocks_done; // workgroups of the current sweep that have finished
+  uint32_t plan;        // which of the two sweep plans is the input of the next pass
+  uint32_t grid;        // workgroups of every fused sweep launch
+  uint32_t pad[3];
+};
+
+// Fused-sweep lists are read through a segment table: segment = a contiguous run of
+// `fill` entries at `base` of realization r's current list buffer.  A realization's
+// segments are consecutive in the table.  Each pass gives every active realization
+// G_r workgroups; workgroup k of r reads the k-th equal share of r's chunks and
+// writes its output into the k-th equal part of the first half of r's other list
+// buffer (an LDS counter, no global atomic); a part that fills up spills into the
+// buffer's second half through r's tail counter.  The output table of a pass holds,
+// per realization, its G_r parts and then its tail.
+struct SegEntry {
+  uint32_t r, base, fill, pad;
+};
+
+// One sweep plan: an input segment table with its chunk prefix (chunks of kWave
+// entries, per segment), the realization ranges in the table, and the workgroup
+// assignment (exclusive prefix of G_r).
+struct SweepPlan {
+  SegEntry* seg;        // seg_cap entries
+  uint32_t* segchunk;   // seg_cap + 1
+  uint32_t* rseg;       // count + 1
+  uint32_t* wgoff;      // count + 1
 };
 
 // What an offset table counts per realization.
@@ -109,6 +150,7 @@ enum ItemKind : uint32_t {
   kItemsSeeds = 2,   // accepted seeds (front construction)
   kItemsGrow = 3,    // F_t of running realizations
   kItemsPrune = 4,   // F_t + New_t of running realizations
+  kItemsList = 5,    // L_t of realizations with a pending fused pass
 };
 
 struct BatchArgs {
@@ -124,6 +166,11 @@ struct BatchArgs {
   uint32_t* sorted_r;
   uint64_t* sorted_prio;
   uint8_t* status;
+  // fused sweep
+  SweepPlan plan[2];
+  uint32_t seg_cap;     // entries of each segment table
+  uint32_t* wgkept;     // kept entries per logical workgroup of the current pass
+  uint32_t* tailfill;   // per realization: entries spilled into the tail half
 };
 
 __global__ void k_ctl_init(BatchArgs A, uint32_t zero_live);
@@ -143,5 +190,8 @@ __global__ void k_grow(BatchArgs A);
 __global__ void k_prune(BatchArgs A);
 __global__ void k_step_end(BatchArgs A);
 __global__ void k_rollback(uint8_t* grid, uint32_t n);
+__global__ void k_sweep_prepare(BatchArgs A);
+__global__ void k_sweep(BatchArgs A);
+__global__ void k_sweep_end(BatchArgs A);
 
 }  // namespace qsgs

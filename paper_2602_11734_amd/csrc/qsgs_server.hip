@@ -83,7 +83,7 @@ struct qsgs_server {
   std::deque<int64_t> ready;      // finished, grid not yet taken
   std::unordered_map<int64_t, Request> done;
 
-  static size_t front_bytes(const Geometry& g) { return 2 * align_up(sizeof(int32_t) * g.n); }
+  static size_t front_bytes(const Geometry& g) { return 2 * align_up(2 * sizeof(int32_t) * g.n); }
   static size_t footprint(const Geometry& g) { return align_up(grid_bytes(g)) + front_bytes(g); }
 };
 
@@ -128,7 +128,8 @@ qsgs_status qsgs_server_create(void* d_arena, size_t arena_bytes, int32_t max_sl
   *out = nullptr;
   if (!d_arena || (uintptr_t)d_arena % kAlign)
     return fail(QSGS_ERR_INVALID, "d_arena must be a 256-byte aligned device pointer");
-  if (max_slots < 1 || max_slots > 65536) return fail(QSGS_ERR_INVALID, "max_slots in [1, 65536]");
+  if (max_slots < 1 || (uint32_t)max_slots > kMaxBatch)
+    return fail(QSGS_ERR_INVALID, "max_slots in [1, %u]", kMaxBatch);
   if (steps_per_tick < 1 || steps_per_tick > 1024)
     return fail(QSGS_ERR_INVALID, "steps_per_tick in [1, 1024]");
   const PersistLayout P = persist_layout((size_t)max_slots, 0);
@@ -143,6 +144,7 @@ qsgs_status qsgs_server_create(void* d_arena, size_t arena_bytes, int32_t max_sl
   S->heap.reset(P.total, arena_bytes);
   S->slot_req.assign((size_t)max_slots, -1);
   qsgs_status st = S->eng.upload_header();
+  if (st == QSGS_OK) st = S->eng.upload_control();
   if (st == QSGS_OK) st = S->eng.upload(0, (size_t)max_slots);  // every slot empty
   if (st != QSGS_OK) {
     delete S;
@@ -168,7 +170,7 @@ qsgs_status qsgs_server_submit(qsgs_server* S, int64_t request_id, const qsgs_di
   q.id = request_id;
   q.dims = *dims;
   q.params = *params;
-  const size_t need = qsgs_server::footprint(q.spec.g) + seed_layout({q.spec}).total;
+  const size_t need = qsgs_server::footprint(q.spec.g) + seed_layout({q.spec}, false).total;
   if (need > S->heap.hi - S->heap.lo)
     return fail(QSGS_ERR_CAPACITY, "request needs %zu arena bytes, the arena holds %zu", need,
                 S->heap.hi - S->heap.lo);
@@ -189,7 +191,7 @@ qsgs_status qsgs_server_tick(qsgs_server* S, int32_t* n_resident, int32_t* n_que
   while (!group.empty()) {
     std::vector<Spec> specs;
     for (size_t slot : group) specs.push_back(S->resident.at(S->slot_req[slot]).spec);
-    const SeedLayout L = seed_layout(specs);
+    const SeedLayout L = seed_layout(specs, false);
     if (S->heap.alloc(L.total, &scratch_off)) {
       scratch_bytes = L.total;
       for (size_t k = 0; k < group.size(); ++k) {
@@ -198,12 +200,13 @@ qsgs_status qsgs_server_tick(qsgs_server* S, int32_t* n_resident, int32_t* n_que
                       reinterpret_cast<uint8_t*>(S->arena + q.grid_off),
                       reinterpret_cast<int32_t*>(S->arena + q.front_off),
                       reinterpret_cast<int32_t*>(S->arena + q.front_off +
-                                                 align_up(sizeof(int32_t) * q.spec.g.n)),
-                      q.spec.g.n);
+                                                 align_up(2 * sizeof(int32_t) * q.spec.g.n)),
+                      2 * q.spec.g.n);
       }
       E.attach_scratch(group, S->arena + scratch_off, L);
       for (size_t slot : group) QSGS_TRY(E.upload(slot, 1));
-      QSGS_TRY(E.seed(S->arena + scratch_off, L));
+      QSGS_TRY(E.seed_core(S->arena + scratch_off, L));
+      QSGS_TRY(E.sweep_start());
       break;
     }
     const size_t slot = group.back();
@@ -219,7 +222,7 @@ qsgs_status qsgs_server_tick(qsgs_server* S, int32_t* n_resident, int32_t* n_que
   if (scratch_bytes) S->heap.release(scratch_off, scratch_bytes);  // stream-ordered reuse
 
   if (!S->resident.empty())
-    for (int32_t k = 0; k < S->steps_per_tick; ++k) QSGS_TRY(E.step(nullptr));
+    for (int32_t k = 0; k < S->steps_per_tick; ++k) QSGS_TRY(E.sweep_pass(nullptr));
 
   // Retire finished requests: their fronts return to the arena, the grid waits.
   std::vector<Real> recs;

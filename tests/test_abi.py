@@ -40,8 +40,8 @@ def test_version(q):
 
 def test_size_queries(q):
     p = q.make_params(0.7, 0.005, (0.02, 0.005, 0.00125), 4, 0)
-    assert q.qsgs_grid_bytes((64, 64, 64)) == 64**3
-    assert q.qsgs_grid_bytes((3, 1, 1)) == 4
+    assert q.qsgs_grid_bytes((64, 64, 64)) == 64**3 + 8  # N + 8 padding, multiple of 4
+    assert q.qsgs_grid_bytes((3, 1, 1)) == 12
     assert q.qsgs_grid_bytes((0, 4, 4)) == 0
     assert q.qsgs_grid_bytes((2**11, 2**10, 2**10)) == 0  # N = 2^31
     ws = q.qsgs_workspace_bytes((64, 64, 64), p)
