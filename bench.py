@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy kernel over BYTES bytes three times "
+                         "(the reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -80,6 +83,16 @@ def main():
         build.build_library()
     q.load()
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # an elementwise kernel that reads and writes BYTES bytes (a DMA copy would
+        # not show up as a kernel dispatch)
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_calibration, "copies": 3}))
+        return
     cases = workloads.config3()
     params = [q.params_of(c) for c in cases]
     bufs = [q.alloc(c.dims, p) for c, p in zip(cases, params)]  # one workspace per case

@@ -9,29 +9,28 @@ namespace {
 
 constexpr size_t kStepWorkspace = 1024 * 1024;
 
-// Workspace of qsgs_generate / qsgs_generate_batch: the persistent part, the two front
-// lists of every realization, then the seeding scratch of the whole batch.
+// Workspace of qsgs_generate / qsgs_generate_batch: the persistent part, the sweep
+// state (tile lists and stamps) of every realization, then the seeding scratch of
+// the whole batch.
 struct GenLayout {
   PersistLayout P;
-  std::vector<size_t> f0, f1;
+  std::vector<size_t> sweep;
   size_t seed = 0, total = 0;
   SeedLayout S;
 };
 
-GenLayout gen_layout(const std::vector<Spec>& specs, bool with_fronts) {
+GenLayout gen_layout(const std::vector<Spec>& specs, bool with_sweep) {
   GenLayout G;
   G.P = persist_layout(specs.size(), specs.size() == 1 ? kLogCapSingle : kLogCapBatch);
   size_t off = G.P.total;
-  if (with_fronts) {
+  if (with_sweep) {
     for (const Spec& s : specs) {
-      G.f0.push_back(off);
-      off = align_up(off + 2 * sizeof(int32_t) * s.g.n);
-      G.f1.push_back(off);
-      off = align_up(off + 2 * sizeof(int32_t) * s.g.n);
+      G.sweep.push_back(off);
+      off = align_up(off + sweep_state_bytes(s.g));
     }
   }
   G.seed = off;
-  G.S = seed_layout(specs, !with_fronts);
+  G.S = seed_layout(specs, true);
   G.total = off + G.S.total;
   return G;
 }
@@ -64,8 +63,7 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
   E.bind(ws, G.P, (size_t)count, s);
   std::vector<size_t> group;
   for (int32_t r = 0; r < count; ++r) {
-    E.init_record((size_t)r, specs[r], &params[r], grids[r], at<int32_t>(ws, G.f0[r]),
-                  at<int32_t>(ws, G.f1[r]), 2 * specs[r].g.n);
+    E.init_sweep_record((size_t)r, specs[r], &params[r], grids[r], at<void>(ws, G.sweep[r]));
     group.push_back((size_t)r);
   }
   E.attach_scratch(group, at<void>(ws, G.seed), G.S);

@@ -132,6 +132,25 @@ inline qsgs_status check_grid(const uint8_t* grid) {
 // 8 bytes of padding read (never written) by the 8-byte neighbourhood windows.
 inline size_t grid_bytes(const Geometry& g) { return ((size_t)g.n + 8 + 3) / 4 * 4; }
 
+inline Tiles make_tiles(const Geometry& g) {
+  Tiles t{};
+  t.ntx = (uint32_t)((g.nx + kTileX - 1) / kTileX);
+  t.nty = (uint32_t)((g.ny + kTileY - 1) / kTileY);
+  t.ntz = (uint32_t)((g.nz + kTileZ - 1) / kTileZ);
+  t.n = t.ntx * t.nty * t.ntz;  // <= N: every tile holds a voxel
+  t.div_ntx.init(t.ntx);
+  t.div_nty.init(t.nty);
+  return t;
+}
+
+// Device memory of the fused sweep per realization: two tile lists of 2 x tiles
+// entries (parts, then spills) and the tile stamps.
+inline size_t list_bytes(const Geometry& g) { return 2 * sizeof(int32_t) * (size_t)make_tiles(g).n; }
+inline size_t stamp_bytes(const Geometry& g) { return sizeof(uint32_t) * (size_t)make_tiles(g).n; }
+inline size_t sweep_state_bytes(const Geometry& g) {
+  return 2 * align_up(list_bytes(g)) + align_up(stamp_bytes(g));
+}
+
 inline Buckets make_buckets(const Geometry& g, int32_t spacing) {
   Buckets b{};
   if (spacing <= 1) return b;
@@ -181,7 +200,7 @@ struct WsHeader {
 struct PersistLayout {
   size_t hdr = 0, bctl = 0, reals = 0, off = 0, live = 0, logs = 0, total = 0;
   size_t seg[2] = {0, 0}, segchunk[2] = {0, 0}, rseg[2] = {0, 0}, wgoff[2] = {0, 0};
-  size_t wgkept = 0, tailfill = 0;
+  size_t wgkept = 0, wggrown = 0, tailfill = 0;
   uint32_t log_cap = 0, seg_cap = 0;
 };
 
@@ -208,6 +227,7 @@ inline PersistLayout persist_layout(size_t count, uint32_t log_cap) {
     L.wgoff[q] = take(sizeof(uint32_t) * (count + 1));
   }
   L.wgkept = take(sizeof(uint32_t) * kMaxSweepGrid);
+  L.wggrown = take(sizeof(uint32_t) * kMaxSweepGrid);
   L.tailfill = take(sizeof(uint32_t) * count);
   L.total = off;
   return L;
@@ -340,6 +360,7 @@ struct Engine {
     }
     args.seg_cap = L.seg_cap;
     args.wgkept = at<uint32_t>(base, L.wgkept);
+    args.wggrown = at<uint32_t>(base, L.wggrown);
     args.tailfill = at<uint32_t>(base, L.tailfill);
     const uint32_t want = std::max<uint32_t>(tune.grow_grid, 2 * (uint32_t)count);
     sweep_grid = std::min<uint32_t>(kMaxSweepGrid, (want + kNumXcd - 1) / kNumXcd * kNumXcd);
@@ -362,14 +383,17 @@ struct Engine {
     return at<uint64_t>(ws, P.logs) + (size_t)3 * P.log_cap * r;
   }
 
-  // Fills record r for a new realization (to be seeded).  The fused sweep's lists
-  // f0 / f1 hold 2 N entries each (parts in the first half, spills in the second).
+  // Fills record r for a new realization (to be seeded).  For the fused sweep,
+  // `sweep` is the realization's sweep_state_bytes region (two tile lists of 2 x tiles
+  // entries, parts in the first half and spills in the second, then the stamps); the
+  // step-by-step path passes its caller's front buffers instead.
   void init_record(size_t r, const Spec& sp, const qsgs_params* p, uint8_t* grid, int32_t* f0,
                    int32_t* f1, uint32_t cap) {
     Real& R = reals[r];
     R = Real{};
     R.g = sp.g;
     R.bk = sp.bk;
+    R.tl = make_tiles(sp.g);
     R.grid = grid;
     R.f0 = f0;
     R.f1 = f1;
@@ -382,6 +406,14 @@ struct Engine {
     R.spacing = p->spacing;
     R.phase = kPhaseSeed;
     R.ctl = make_ctl(sp.g, p);
+  }
+
+  void init_sweep_record(size_t r, const Spec& sp, const qsgs_params* p, uint8_t* grid,
+                         void* sweep) {
+    const size_t lb = align_up(list_bytes(sp.g));
+    init_record(r, sp, p, grid, at<int32_t>(sweep, 0), at<int32_t>(sweep, lb),
+                2 * make_tiles(sp.g).n);
+    reals[r].stamp = at<uint32_t>(sweep, 2 * lb);
   }
 
   qsgs_status upload_header() {
@@ -422,7 +454,7 @@ struct Engine {
     uint32_t boff = 0;
     for (size_t k = 0; k < group.size(); ++k) {
       Real& R = reals[group[k]];
-      // without a candidate slice the candidates (then the seeds, i.e. L_0) go to f0
+      // without a candidate slice the candidates (then the seeds) go to f0
       R.cand = L.cand[k] == (size_t)-1 ? R.f0 : at<int32_t>(scratch, L.cand[k]);
       R.boff = boff;
       boff += R.bk.nb;
@@ -539,15 +571,19 @@ struct Engine {
     return QSGS_OK;
   }
 
-  // Loop state of the fused sweep for freshly seeded records (L_0 = their seed lists).
+  // Loop state of the fused sweep for freshly seeded records: their first tile lists
+  // (the tiles of their seeds) and the plan of the first pass.
   qsgs_status sweep_start() {
+    QSGS_TRY(offsets(kItemsSeeds));
+    hipLaunchKernelGGL(k_seed_tiles, dim3(tune.seed_grid), dim3(tune.seed_block), 0, s, args);
+    QSGS_LAUNCHED("k_seed_tiles");
     hipLaunchKernelGGL(k_sweep_prepare, dim3(1), dim3(1024), 0, s, args);
     QSGS_LAUNCHED("k_sweep_prepare");
     return QSGS_OK;
   }
 
-  // One fused pass (prune of step t-1 + growth of step t) over every record with a
-  // pending pass; the kernel's last workgroup ends the step.
+  // One fused pass (front of step t and its growth) over every record with a pending
+  // pass; k_sweep_end ends the step.
   qsgs_status sweep_pass(std::vector<hipEvent_t>* ev) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ev) {
@@ -555,7 +591,8 @@ struct Engine {
       e1 = prof_event();
       QSGS_HIP(hipEventRecord(e0, s));
     }
-    hipLaunchKernelGGL(k_sweep, dim3(sweep_grid), dim3(tune.grow_block), 0, s, args);
+    hipLaunchKernelGGL(k_sweep, dim3(sweep_grid), dim3(tune.grow_block),
+                       sweep_lds_bytes(tune.grow_block), s, args);
     QSGS_LAUNCHED("k_sweep");
     if (ev) {
       QSGS_HIP(hipEventRecord(e1, s));

@@ -42,6 +42,18 @@ struct Buckets {
   int32_t radius;
 };
 
+// Tiles of the fused sweep: 64 x 4 x 4 voxels (one wavefront spans a tile row).
+// Tile (ix, iy, iz) has id ix + ntx (iy + nty iz).
+constexpr int kTileX = 64, kTileY = 4, kTileZ = 4;
+constexpr int kTileRows = kTileY * kTileZ;                // 16 interior rows
+constexpr int kHaloRows = (kTileY + 2) * (kTileZ + 2);    // 36 rows with the halo
+constexpr int kTileVoxels = kTileX * kTileRows;           // 1024
+
+struct Tiles {
+  uint32_t ntx, nty, ntz, n;
+  FastDiv div_ntx, div_nty;
+};
+
 // Loop status codes on the device (the public values plus an internal overflow code).
 constexpr int32_t kStatusDone = 1, kStatusExhausted = 2, kStatusMaxSteps = 3,
                   kStatusOverflow = 100;
@@ -72,21 +84,17 @@ struct Ctl {
   uint32_t last_new;    // |New| of the last completed step
   uint32_t n_cand;      // seed candidates
   uint32_t n_seeds;     // accepted seeds
-  // fused sweep (qsgs_generate*, server): the list L_t = F_{t-1} + New_{t-1} in buffer
-  // `cur`, the mode of the next pass over it and the pass's counters
-  uint32_t n_list;      // |L_t|
+  // fused sweep (qsgs_generate*, server): the active tile list of step t in buffer
+  // `cur` and the mode of the next pass over it
+  uint32_t n_list;      // tiles in the list
   uint32_t mode;        // kModeIdle / kModeRun / kModeFinal
-  uint32_t kept;        // entries of L_t kept as F_t in this pass
+  uint32_t kept;
   uint32_t pad0;
 };
 
-// Pass modes of the fused sweep: a running pass prunes L_t to F_t and grows from it;
-// a final pass only prunes (and folds), to report F_T and leave a clean 0/1 grid.
+// Pass modes of the fused sweep: a running pass finds F_t in its tiles and grows from
+// it; a final pass only counts F_T and folds the last step's marks (clean 0/1 grid).
 constexpr uint32_t kModeIdle = 0, kModeRun = 1, kModeFinal = 2;
-
-// List entries of the fused sweep: bit 31 marks a voxel grown in the previous step,
-// whose grid value is folded to 1 by the next pass (N < 2^31 leaves the bit free).
-constexpr uint32_t kNewFlag = 0x80000000u;
 
 // Phase of a realization record: an empty slot, waiting for the seeding kernels,
 // or in the growth loop (finished ones keep this phase with a non-zero status).
@@ -97,12 +105,14 @@ struct Real {
   Geometry g;
   Buckets bk;
   uint8_t* grid;        // caller's grid, qsgs_grid_bytes bytes
-  int32_t* f0;          // front buffers, cap entries each
+  int32_t* f0;          // front buffers, cap entries each (fused sweep: tile lists)
   int32_t* f1;
+  uint32_t* stamp;      // fused sweep: per tile, 1 + the last pass whose list holds it
+  Tiles tl;
   int32_t* cand;        // candidates, then the seed list (N entries)
   uint64_t* log;        // per-step log (3 words per step) or null
   uint32_t log_cap;
-  uint32_t cap;         // entries of f0 / f1 (the fused sweep uses 2 N: two halves)
+  uint32_t cap;         // entries of f0 / f1 (the fused sweep: 2 x tiles, two halves)
   uint32_t boff;        // first bucket of this realization in the batch's bucket arrays
   uint32_t k0, k1;      // Philox key
   uint64_t t_seed;
@@ -121,24 +131,23 @@ struct BatchCtl {
   uint32_t pad[3];
 };
 
-// Fused-sweep lists are read through a segment table: segment = a contiguous run of
-// `fill` entries at `base` of realization r's current list buffer.  A realization's
-// segments are consecutive in the table.  Each pass gives every active realization
-// G_r workgroups; workgroup k of r reads the k-th equal share of r's chunks and
-// writes its output into the k-th equal part of the first half of r's other list
-// buffer (an LDS counter, no global atomic); a part that fills up spills into the
-// buffer's second half through r's tail counter.  The output table of a pass holds,
-// per realization, its G_r parts and then its tail.
+// Fused-sweep tile lists are read through a segment table: segment = a contiguous run
+// of `fill` entries at `base` of realization r's current list buffer.  A
+// realization's segments are consecutive in the table.  Each pass gives every active
+// realization G_r workgroups; workgroup k of r takes the k-th equal share of r's
+// entries and writes the tiles it activates into the k-th equal part of the first
+// half of r's other list buffer (an LDS counter, no global atomic); a part that fills
+// up spills into the buffer's second half through r's tail counter.  The output table
+// of a pass holds, per realization, its G_r parts and then its tail.
 struct SegEntry {
   uint32_t r, base, fill, pad;
 };
 
-// One sweep plan: an input segment table with its chunk prefix (chunks of kWave
-// entries, per segment), the realization ranges in the table, and the workgroup
-// assignment (exclusive prefix of G_r).
+// One sweep plan: an input segment table with its entry prefix, the realization
+// ranges in the table, and the workgroup assignment (exclusive prefix of G_r).
 struct SweepPlan {
   SegEntry* seg;        // seg_cap entries
-  uint32_t* segchunk;   // seg_cap + 1
+  uint32_t* segchunk;   // seg_cap + 1: entries before each segment
   uint32_t* rseg;       // count + 1
   uint32_t* wgoff;      // count + 1
 };
@@ -169,7 +178,8 @@ struct BatchArgs {
   // fused sweep
   SweepPlan plan[2];
   uint32_t seg_cap;     // entries of each segment table
-  uint32_t* wgkept;     // kept entries per logical workgroup of the current pass
+  uint32_t* wgkept;     // front voxels found per logical workgroup of the current pass
+  uint32_t* wggrown;    // voxels grown per logical workgroup of the current pass
   uint32_t* tailfill;   // per realization: entries spilled into the tail half
 };
 
@@ -190,8 +200,10 @@ __global__ void k_grow(BatchArgs A);
 __global__ void k_prune(BatchArgs A);
 __global__ void k_step_end(BatchArgs A);
 __global__ void k_rollback(uint8_t* grid, uint32_t n);
+__global__ void k_seed_tiles(BatchArgs A);
 __global__ void k_sweep_prepare(BatchArgs A);
-__global__ void k_sweep(BatchArgs A);
+__global__ void k_sweep(BatchArgs A);  // dynamic LDS: sweep_lds_bytes(blockDim.x)
+size_t sweep_lds_bytes(uint32_t block);
 __global__ void k_sweep_end(BatchArgs A);
 
 }  // namespace qsgs

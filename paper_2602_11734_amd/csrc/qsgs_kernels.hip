@@ -271,6 +271,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
       const U4 w = philox10(v, 0u, 0u, kTagSeed, R.k0, R.k1);
       cand = (uint64_t)w.x < R.t_seed;
       R.grid[v] = kVoid;
+      if (R.stamp && v < R.tl.n) R.stamp[v] = 0;  // fused sweep: no tile listed yet
     }
     const uint32_t pos = wave_append_flag(cand, &R.ctl.n_cand);
     if (cand) R.cand[pos] = (int32_t)v;  // capacity N: cannot overflow
@@ -386,6 +387,24 @@ __global__ __launch_bounds__(kMaxBlock) void k_collect_seeds(BatchArgs A) {
   }
 }
 
+// The fused sweep's first list: the tiles holding a seed, each once (stamp 1 = listed
+// for pass 0), appended to list buffer 0 with one atomic per wavefront.
+__global__ __launch_bounds__(kMaxBlock) void k_seed_tiles(BatchArgs A) {
+  for_each_chunk(A, kItemsSeeds, [&](uint32_t r, uint32_t i) {
+    Real& R = A.reals[r];
+    bool fresh = false;
+    uint32_t u = 0;
+    if (i < R.ctl.n_seeds) {
+      uint32_t x, y, z;
+      coords_of(R.g, (uint32_t)R.cand[i], x, y, z);
+      u = x / kTileX + R.tl.ntx * (y / kTileY + R.tl.nty * (z / kTileZ));
+      fresh = atomicMax(&R.stamp[u], 1u) == 0u;
+    }
+    const uint32_t pos = wave_append_flag(fresh, &R.ctl.n_list);
+    if (fresh) R.f0[pos] = (int32_t)u;
+  });
+}
+
 // ---------------------------------------------------------------------------
 // a3: initial front F_0 = interface(G_0) (Sec. 2.3 step 2), compacted from the seed
 // list into front buffer 0; then the loop state for step 0.
@@ -454,7 +473,10 @@ __global__ void k_loop_resume(BatchArgs A) {
 // j = 0, 1, ... in ascending direction; a passing draw claims the neighbour with a
 // 32-bit atomicOr that writes `mark` into its grid byte.  Returns the directions this
 // thread claimed first (the neighbour was still 0).
-__device__ __forceinline__ uint32_t grow_draws(const Real& R, const Geometry& g, uint32_t a,
+// The key and grid pointer are passed by value: read through the record they would be
+// reloaded after every claim atomic.
+__device__ __forceinline__ uint32_t grow_draws(uint8_t* __restrict__ grid, uint32_t k0,
+                                               uint32_t k1, const Geometry& g, uint32_t a,
                                                uint32_t t, const Nbhd& nb, uint64_t T0,
                                                uint64_t T1, uint64_t T2, uint8_t mark) {
   uint32_t claims = 0;
@@ -468,7 +490,7 @@ __device__ __forceinline__ uint32_t grow_draws(const Real& R, const Geometry& g,
     if (!((nb.grown >> d) & 1u)) {  // a target already grown this step needs no draw
       const int32_t blk = (int32_t)(j >> 3);
       if (blk != hi_block) {
-        H = philox10(a, t, (uint32_t)blk, kTagGrowHi, R.k0, R.k1);
+        H = philox10(a, t, (uint32_t)blk, kTagGrowHi, k0, k1);
         hi_block = blk;
       }
       const uint32_t wh = pick(H, (j >> 1) & 3u);
@@ -479,7 +501,7 @@ __device__ __forceinline__ uint32_t grow_draws(const Real& R, const Geometry& g,
       bool pass = h < th;
       if (h == th) {  // high halves tie: decide on the low halves
         if (blk != lo_block) {
-          L = philox10(a, t, (uint32_t)blk, kTagGrowLo, R.k0, R.k1);
+          L = philox10(a, t, (uint32_t)blk, kTagGrowLo, k0, k1);
           lo_block = blk;
         }
         const uint32_t wl = pick(L, (j >> 1) & 3u);
@@ -489,7 +511,7 @@ __device__ __forceinline__ uint32_t grow_draws(const Real& R, const Geometry& g,
       if (pass) {
         const uint32_t q = (uint32_t)((int32_t)a + dir_offset(g, d));
         const uint32_t sh = (q & 3u) * 8u;
-        const uint32_t old = atomicOr((uint32_t*)(R.grid + (q & ~3u)), (uint32_t)mark << sh);
+        const uint32_t old = atomicOr((uint32_t*)(grid + (q & ~3u)), (uint32_t)mark << sh);
         if (((old >> sh) & 0xFFu) == kVoid) claims |= 1u << d;
       }
     }
@@ -524,7 +546,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_grow(BatchArgs A) {
         uint32_t x, y, z;
         coords_of(g, a, x, y, z);
         const Nbhd nb = load_neighbourhood(R.grid, g, a, x, y, z);
-        claims = grow_draws(R, g, a, t, nb, T0, T1, T2, kGrown);
+        claims = grow_draws(R.grid, uniform(R.k0), uniform(R.k1), g, a, t, nb, T0, T1, T2,
+                            kGrown);
       }
     }
     uint32_t pos = wave_append((uint32_t)__builtin_popcount(claims), &c.new_count);
@@ -616,21 +639,34 @@ __global__ __launch_bounds__(kBlock) void k_rollback(uint8_t* grid, uint32_t n) 
 
 
 // ---------------------------------------------------------------------------
-// Fused sweep (qsgs_generate*, server).  One pass over L_t = F_{t-1} + New_{t-1}
-// does the prune of step t-1 and the growth of step t, which read the same
-// neighbourhoods (the state at the start of step t): entries flagged new are folded
-// from the previous step's mark to 1, entries with an in-domain void neighbour form
-// F_t, and in a running pass each of them draws for its void neighbours.  Voxels
-// grown in step t carry mark 2 + (t & 1), so marks of consecutive steps differ.
+// Fused sweep (qsgs_generate*, server), indexed by active tiles.
+//
+// F_t is exactly the interface of the grid at the start of step t (the solid voxels
+// with an in-domain void neighbour): a voxel of F_{t-1} keeps a void neighbour only
+// if it had one, since the void set only shrinks, and a voxel grown in step t-1
+// joins F_t iff it has one.  The list carried from step to step therefore names
+// 64 x 4 x 4 tiles rather than voxels: the list of step t holds every tile that
+// contains a voxel of F_t (a superset is harmless).  A pass stages each listed tile
+// with its one-voxel halo by coalesced row loads, finds F_t in the tile with 64-bit
+// row masks, compacts those voxels into an LDS queue (wavefront ballot + prefix),
+// and every queue entry draws for its void neighbours (Sec. 2.3 step 3, Eq. (1)) and
+// claims winners with a 32-bit atomicOr of the step's mark 2 + (t & 1).  A voxel of
+// F_{t+1} either was in F_t or was grown in step t, so the next list holds the tiles
+// that had a front voxel and the tiles that received a claim, each once: a tile's
+// stamp (1 + the pass whose list holds it) is raised with atomicMax and the first
+// raiser appends it.  Voxels grown in step t-1 still carry the previous mark; the
+// pass that owns their tile (listed, because a claim lists its tile) folds them to 1
+// with an atomicXor, so a byte equal to the current mark always means "grown in this
+// step", i.e. void at the step's start, and stale reads never change a decision.
 //
 // Output without contended atomics: every active realization r gets G_r workgroups;
-// workgroup k reads the k-th equal share of r's chunks (through the segment table of
-// the input plan) and appends L_{t+1} entries to the k-th part of r's other list
-// buffer with an LDS counter.  Its part's fill and its kept count go to per-workgroup
-// slots; a part that fills up spills into the second half of the buffer through r's
-// tail counter.  The last workgroup to finish (ticket) ends the step for every
-// realization (a6: log, count, status, Eq. (1) thresholds of the next step) and
-// builds the next plan.
+// workgroup k takes the k-th equal share of r's list entries (through the segment
+// table of the input plan) and appends the tiles it activates to the k-th part of
+// r's other list buffer with an LDS counter.  Its part's fill, its front count and
+// its growth count go to per-workgroup slots; a part that fills up spills into the
+// second half of the buffer through r's tail counter.  k_sweep_end then ends the step
+// for every realization (a6: log, count, status, Eq. (1) thresholds of the next step)
+// and builds the next plan.
 // ---------------------------------------------------------------------------
 
 // Block-wide exclusive scan of n values val(i), handing out(i, prefix); returns the
@@ -675,15 +711,15 @@ __device__ __forceinline__ bool sweep_active(const Real& R) {
   return R.phase == kPhaseGrow && R.ctl.status == 0 && R.ctl.mode != kModeIdle;
 }
 
-// Chunk prefix and workgroup assignment of plan q, whose segment table and
+// Entry prefix and workgroup assignment of plan q, whose segment table and
 // realization ranges are complete.  G_r = max(1, floor((G - B) n_r / n)) for an
-// active realization with n_r > 0 chunks (B of them, n chunks in all), so that
+// active realization with n_r > 0 entries (B of them, n entries in all), so that
 // sum G_r <= G.  One workgroup.
 __device__ void plan_assign(const BatchArgs& A, uint32_t q) {
   const SweepPlan& P = A.plan[q];
   const uint32_t S = P.rseg[A.count];
   const uint32_t chunks = block_scan_u32(
-      S, [&](uint32_t i) { return (atomic_load(&P.seg[i].fill) + kWave - 1) / (uint32_t)kWave; },
+      S, [&](uint32_t i) { return atomic_load(&P.seg[i].fill); },
       [&](uint32_t i, uint32_t x) { P.segchunk[i] = x; });
   if (threadIdx.x == 0) P.segchunk[S] = chunks;
   __syncthreads();
@@ -706,8 +742,8 @@ __device__ void plan_assign(const BatchArgs& A, uint32_t q) {
   __syncthreads();
 }
 
-// Loop state of step 0 for every freshly seeded realization (L_0 = its seed list,
-// at the start of list buffer 0), and the input plan of the next pass: realizations
+// Loop state of step 0 for every freshly seeded realization (its list: the tiles of
+// its seeds, at the start of list buffer 0), and the input plan of the next pass: realizations
 // already growing keep their segments, new ones get one segment, finished ones none.
 // One workgroup.
 __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
@@ -725,7 +761,6 @@ __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
     R.phase = kPhaseGrow;
     Ctl& c = R.ctl;
     c.cnt = c.n_seeds;
-    c.n_list = c.n_seeds;
     c.cur = 0;
     c.step = 0;
     c.kept = 0;
@@ -743,8 +778,7 @@ __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
       }
       c.bad_entry = 0;
       c.last_new = 0;
-      // mark as new for the table rebuild below (seed lists need no fold)
-      c.pad0 = 1;
+      c.pad0 = 1;  // new: one segment in the table rebuild below
     }
   }
   __syncthreads();
@@ -774,8 +808,10 @@ __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
   if (threadIdx.x == 0) A.bctl->plan = qo;
 }
 
-// End of a pass for realization r: kept = |F_t|, out = |L_{t+1}|.
-__device__ void sweep_end(const BatchArgs& A, uint32_t r, uint32_t kept, uint32_t out) {
+// End of a pass for realization r: kept = |F_t|, out = tiles listed for the next
+// pass, grown = voxels grown in the pass.
+__device__ void sweep_end(const BatchArgs& A, uint32_t r, uint32_t kept, uint32_t out,
+                          uint32_t grown) {
   Real& R = A.reals[r];
   Ctl& c = R.ctl;
   const uint32_t bad = atomic_load(&c.overflow) | atomic_load(&c.bad_entry);
@@ -784,7 +820,6 @@ __device__ void sweep_end(const BatchArgs& A, uint32_t r, uint32_t kept, uint32_
     c.mode = kModeIdle;
     return;
   }
-  const uint32_t grown = out - kept;
   c.front_size = kept;
   c.n_list = out;
   c.cur ^= 1u;
@@ -824,8 +859,69 @@ __device__ __forceinline__ uint32_t wave_prefix(uint32_t cnt, uint32_t* total) {
   return incl - cnt;
 }
 
+// LDS image of one tile at the step's start.  Halo row h = hy + 6 hz (hy, hz in 0..5)
+// covers y = y0 - 1 + hy, z = z0 - 1 + hz; interior row i = jy + 4 jz is halo row
+// (jy + 1) + 6 (jz + 1).  Bit i of a row mask is voxel x0 + i.
+struct TileImage {
+  uint64_t V[kHaloRows];   // in-domain and void at the step's start (0 or the mark)
+  uint32_t LR[kHaloRows];  // bit 0: voxel x0 - 1 void, bit 1: voxel x0 + 64 void
+  uint64_t S[kTileRows];   // solid (interior rows)
+  uint16_t q[kTileVoxels]; // front voxels: interior row << 6 | x - x0
+};
+
+// The 26-bit void mask (direction order) of front voxel (xl, jy, jz) of the image.
+__device__ __forceinline__ uint32_t tile_void_mask(const TileImage& T, int xl, int jy, int jz) {
+  uint32_t vm = 0;
+  int d = 0;
+#pragma unroll
+  for (int kz = 0; kz < 3; ++kz)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      const int h = (jy + ky) + (kTileY + 2) * (jz + kz);
+      const uint64_t V = T.V[h];
+      const uint32_t lr = T.LR[h];
+      const uint32_t left = xl == 0 ? (lr & 1u) : (uint32_t)(V >> (xl - 1)) & 1u;
+      const uint32_t right = xl == kTileX - 1 ? (lr >> 1) : (uint32_t)(V >> (xl + 1)) & 1u;
+      if (kz == 1 && ky == 1) {
+        vm |= (left | right << 1) << d;
+        d += 2;
+      } else {
+        const uint32_t mid = (uint32_t)(V >> xl) & 1u;
+        vm |= (left | mid << 1 | right << 2) << d;
+        d += 3;
+      }
+    }
+  return vm;
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Orders LDS accesses of the lanes of one wavefront (a wave executes in lockstep; this
+// keeps the compiler from moving LDS accesses across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Dynamic LDS of k_sweep: one TileImage per wavefront.
+size_t sweep_lds_bytes(uint32_t block) { return sizeof(TileImage) * (block / kWave); }
+
+// Each wavefront sweeps whole tiles on its own (no workgroup barrier per tile); the
+// workgroup resolves its share of list entries into LDS a block at a time.
 __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
-  __shared__ uint32_t s_fill, s_commit, s_kept;
+  extern __shared__ __align__(16) unsigned char sweep_lds[];
+  __shared__ uint32_t s_tiles[kMaxBlock];
+  __shared__ uint32_t s_fill, s_commit, s_kept, s_grown;
   const uint32_t G = gridDim.x;
   const uint32_t p = uniform(A.bctl->plan);
   const SweepPlan& P = A.plan[p];
@@ -833,12 +929,14 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
   // logical workgroup index: XCD x (workgroups b with b % 8 == x) holds [x G/8, (x+1) G/8)
   const uint32_t beta = (blockIdx.x % kNumXcd) * (G / kNumXcd) + blockIdx.x / kNumXcd;
   const uint32_t nwg = uniform(P.wgoff[A.count]);
+  const uint32_t lane = lane_id(), wib = uniform(threadIdx.x / kWave), wpb = blockDim.x / kWave;
+  TileImage& T = reinterpret_cast<TileImage*>(sweep_lds)[wib];
   if (threadIdx.x == 0) {
     s_fill = 0;
     s_commit = 0;
     s_kept = 0;
+    s_grown = 0;
   }
-  __syncthreads();
   uint32_t r = 0, k = 0, part_base = 0;
   if (beta < nwg) {
     uint32_t a = 0, b = A.count;  // largest r with wgoff[r] <= beta
@@ -852,87 +950,193 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
     Real& R = A.reals[r];
     Ctl& c = R.ctl;
     const Geometry g = R.g;
+    const Tiles tl = R.tl;
+    uint8_t* __restrict__ grid = R.grid;
+    uint32_t* __restrict__ stamp = R.stamp;
+    const uint32_t k0 = uniform(R.k0), k1 = uniform(R.k1);
     const uint32_t sb = uniform(P.rseg[r]), se = uniform(P.rseg[r + 1]);
-    const uint32_t ch0 = uniform(P.segchunk[sb]);
-    const uint64_t nch = uniform(P.segchunk[se]) - ch0;
-    const uint32_t c_lo = ch0 + (uint32_t)(nch * k / Gr);
-    const uint32_t c_hi = ch0 + (uint32_t)(nch * (k + 1) / Gr);
-    const uint64_t half = g.n;
+    const uint32_t e0 = uniform(P.segchunk[sb]);
+    const uint64_t ne = uniform(P.segchunk[se]) - e0;
+    const uint32_t e_lo = e0 + (uint32_t)(ne * k / Gr);
+    const uint32_t e_hi = e0 + (uint32_t)(ne * (k + 1) / Gr);
+    const uint64_t half = tl.n;
     part_base = (uint32_t)(half * k / Gr);
     const uint32_t part_cap = (uint32_t)(half * (k + 1) / Gr) - part_base;
-    const uint32_t t = (uint32_t)c.step;
-    const bool run = c.mode == kModeRun;
-    const uint8_t mark = (uint8_t)(kGrown + (t & 1u));
-    const uint64_t T0 = c.T[0], T1 = c.T[1], T2 = c.T[2];
-    const int32_t* __restrict__ lin = c.cur ? R.f1 : R.f0;
-    int32_t* __restrict__ lout = c.cur ? R.f0 : R.f1;
-    const uint32_t wib = uniform(threadIdx.x / kWave), wpb = blockDim.x / kWave;
-    uint32_t s = sb;
-    if (c_lo + wib < c_hi) {  // first segment of this wave: largest s with segchunk[s] <= chunk
-      uint32_t a = sb, b = se;
-      while (b - a > 1) {
-        const uint32_t mid = (a + b) >> 1;
-        if (uniform(P.segchunk[mid]) <= c_lo + wib) a = mid; else b = mid;
+    const uint32_t t = uniform((uint32_t)c.step);
+    const bool run = uniform(c.mode) == kModeRun;
+    const uint32_t mark = kGrown + (t & 1u), pmark = mark ^ 1u;
+    const uint64_t T0 = uniform64(c.T[0]), T1 = uniform64(c.T[1]), T2 = uniform64(c.T[2]);
+    const int32_t* __restrict__ lin = uniform(c.cur) ? R.f1 : R.f0;
+    int32_t* __restrict__ lout = uniform(c.cur) ? R.f0 : R.f1;
+    uint32_t kept_w = 0, grown_w = 0;
+    for (uint32_t base = e_lo; base < e_hi; base += blockDim.x) {
+      __syncthreads();  // the previous block of entries is consumed
+      {
+        const uint32_t e = base + threadIdx.x;
+        if (e < e_hi) {  // segment of entry e: largest s with segchunk[s] <= e
+          uint32_t lo = sb, hi = se;
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (P.segchunk[mid] <= e) lo = mid; else hi = mid;
+          }
+          s_tiles[threadIdx.x] = (uint32_t)lin[P.seg[lo].base + e - P.segchunk[lo]];
+        }
       }
-      s = a;
+      __syncthreads();
+      const uint32_t nb = min((uint32_t)blockDim.x, e_hi - base);
+      for (uint32_t j = wib; j < nb; j += wpb) {
+        const uint32_t u = uniform(s_tiles[j]);
+        if (u >= tl.n) {
+          if (lane == 0) atomicOr(&c.bad_entry, 1u);
+          continue;
+        }
+        const uint32_t q1 = tl.div_ntx.div(u);
+        const uint32_t iz = tl.div_nty.div(q1);
+        const int32_t x0 = (int32_t)(u - q1 * tl.ntx) * kTileX;
+        const int32_t y0 = (int32_t)(q1 - iz * tl.nty) * kTileY;
+        const int32_t z0 = (int32_t)iz * kTileZ;
+        wave_sync();  // the previous tile's image is no longer read
+        // 1. stage the rows of the tile and its halo, one z plane (6 rows) of loads in
+        // flight at a time (off-domain lanes read byte 0 and are masked); fold the
+        // previous step's marks
+        for (int hz = 0; hz < kTileZ + 2; ++hz) {
+          const int32_t z = z0 - 1 + hz;
+          const bool zin = z >= 0 && z < g.nz;
+          uint32_t bv[kTileY + 2], be[kTileY + 2];
+          int32_t rowv[kTileY + 2];
+#pragma unroll
+          for (int hy = 0; hy < kTileY + 2; ++hy) {
+            const int32_t y = y0 - 1 + hy;
+            const bool rin = zin && y >= 0 && y < g.ny;
+            const int32_t row = rin ? y * g.nx + z * (int32_t)g.nxy : 0;
+            const int32_t x = x0 + (int32_t)lane;
+            const int32_t xe = lane == 0 ? x0 - 1 : x0 + kTileX;
+            const bool in = rin && x < g.nx;
+            const bool ine = rin && lane < 2 && xe >= 0 && xe < g.nx;
+            rowv[hy] = in ? row + x : -1;
+            bv[hy] = grid[in ? row + x : 0];
+            be[hy] = ine ? grid[row + xe] : 0xFFu;
+          }
+#pragma unroll
+          for (int hy = 0; hy < kTileY + 2; ++hy) {
+            const bool in = rowv[hy] >= 0;
+            const bool vd = in && (bv[hy] == kVoid || bv[hy] == mark);
+            const uint64_t V = __ballot(vd);
+            const uint64_t E = __ballot(be[hy] == kVoid || be[hy] == mark);
+            const int h = hy + (kTileY + 2) * hz;
+            if (hy >= 1 && hy <= kTileY && hz >= 1 && hz <= kTileZ) {
+              const uint64_t Sm = __ballot(in && !vd);
+              if (in && bv[hy] == pmark) {  // grown in the previous step: fold to 1
+                const uint32_t q = (uint32_t)rowv[hy];
+                atomicXor((uint32_t*)(grid + (q & ~3u)), (pmark ^ kSolid) << ((q & 3u) * 8u));
+              }
+              if (lane == 0) T.S[(hy - 1) + kTileY * (hz - 1)] = Sm;
+            }
+            if (lane == 0) {
+              T.V[h] = V;
+              T.LR[h] = (uint32_t)E & 3u;
+            }
+          }
+        }
+        wave_sync();
+        // 2. front rows (solid with a void neighbour) and their prefix
+        uint64_t F = 0;
+        if (lane < (uint32_t)kTileRows) {
+          const int jy = (int)lane % kTileY, jz = (int)lane / kTileY;
+          uint64_t D = 0;
+#pragma unroll
+          for (int kz = 0; kz < 3; ++kz)
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky) {
+              const int h = (jy + ky) + (kTileY + 2) * (jz + kz);
+              const uint64_t V = T.V[h];
+              const uint32_t lr = T.LR[h];
+              D |= V | (V << 1) | (V >> 1) | (uint64_t)(lr & 1u) | ((uint64_t)(lr >> 1) << 63);
+            }
+          F = T.S[lane] & D;
+        }
+        const uint32_t cnt = (uint32_t)__popcll(F);
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int o = 1; o < kTileRows; o <<= 1) {
+          const uint32_t v = __shfl_up(incl, o, kWave);
+          if (lane >= (uint32_t)o) incl += v;
+        }
+        const uint32_t nq = uniform(__shfl(incl, kTileRows - 1, kWave));
+        kept_w += nq;
+        if (!run || nq == 0) continue;
+        // 3. compact the front voxels into the queue (row i's prefix and mask are
+        // broadcast from lane i)
+        const uint32_t excl = incl - cnt;
+        const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll 4
+        for (int i = 0; i < kTileRows; ++i) {
+          // (the builtin returns int: widen through uint32_t, never by sign extension)
+          const uint64_t Fi =
+              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(F >> 32), i) << 32) |
+              (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)F, i);
+          const uint32_t pi = (uint32_t)__builtin_amdgcn_readlane(excl, i);
+          if ((Fi >> lane) & 1ull)
+            T.q[pi + (uint32_t)__popcll(Fi & below)] = (uint16_t)((uint32_t)i << 6 | lane);
+        }
+        wave_sync();
+        // 4. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1))
+        uint32_t tm = 0, grown = 0;
+        for (uint32_t qi = lane; qi < nq; qi += kWave) {
+          const uint32_t ent = T.q[qi];
+          const int i = (int)(ent >> 6), xl = (int)(ent & 63u);
+          const int jy = i % kTileY, jz = i / kTileY;
+          const uint32_t vm = tile_void_mask(T, xl, jy, jz);
+          const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
+                             (uint32_t)(z0 + jz) * g.nxy;
+          uint32_t claims =
+              grow_draws(grid, k0, k1, g, a, t, Nbhd{vm, 0u, 0u}, T0, T1, T2, (uint8_t)mark);
+          grown += (uint32_t)__builtin_popcount(claims);
+          while (claims) {
+            const int d = __builtin_ctz(claims);
+            claims &= claims - 1u;
+            const int xn = xl + dir_field(kDirDX, d) - 1, yn = jy + dir_field(kDirDY, d) - 1,
+                      zn = jz + dir_field(kDirDZ, d) - 1;
+            const int ox = xn < 0 ? 0 : (xn >= kTileX ? 2 : 1);
+            const int oy = yn < 0 ? 0 : (yn >= kTileY ? 2 : 1);
+            const int oz = zn < 0 ? 0 : (zn >= kTileZ ? 2 : 1);
+            tm |= 1u << (ox + 3 * oy + 9 * oz);
+          }
+        }
+        grown_w += wave_sum(grown);
+        // 5. list the tiles that may hold F_{t+1} for the next pass, each once: this
+        // tile (it has front voxels) and every tile that received a claim
+        const uint32_t tmask = wave_or(tm) | 1u << 13;
+        if (lane < 27u && ((tmask >> lane) & 1u)) {
+          const int ox = (int)lane % 3 - 1, oy = (int)(lane / 3) % 3 - 1, oz = (int)lane / 9 - 1;
+          const uint32_t un =
+              (uint32_t)((int32_t)u + ox + (int32_t)tl.ntx * (oy + (int32_t)tl.nty * oz));
+          if (atomicMax(&stamp[un], t + 2u) < t + 2u) {
+            const uint32_t pos = atomicAdd(&s_fill, 1u);
+            if (pos < part_cap) {
+              lout[part_base + pos] = (int32_t)un;
+              atomicMax(&s_commit, pos + 1u);
+            } else {  // the part is full: spill into the tail half
+              const uint32_t tb = atomicAdd(&A.tailfill[r], 1u);
+              if (tb < tl.n)
+                lout[tl.n + tb] = (int32_t)un;
+              else
+                atomicOr(&c.overflow, 1u);
+            }
+          }
+        }
+      }
     }
-    for (uint32_t ch = c_lo + wib; ch < c_hi; ch += wpb) {
-      while (uniform(P.segchunk[s + 1]) <= ch) ++s;
-      const SegEntry seg = P.seg[s];
-      const uint32_t idx = (ch - uniform(P.segchunk[s])) * kWave + lane_id();
-      uint32_t v = 0, claims = 0;
-      bool keep = false;
-      if (idx < seg.fill) {
-        const uint32_t raw = (uint32_t)lin[seg.base + idx];
-        v = raw & ~kNewFlag;
-        if (v >= g.n) {
-          atomicOr(&c.bad_entry, 1u);
-        } else {
-          if (raw & kNewFlag) R.grid[v] = kSolid;  // grown last step: fold its mark
-          uint32_t x, y, z;
-          coords_of(g, v, x, y, z);
-          const Nbhd nb = load_neighbourhood(R.grid, g, v, x, y, z, mark);
-          keep = nb.voidm != 0;
-          if (keep && run) claims = grow_draws(R, g, v, t, nb, T0, T1, T2, mark);
-        }
-      }
-      const uint32_t cnt = (keep ? 1u : 0u) + (uint32_t)__builtin_popcount(claims);
-      uint32_t total = 0;
-      uint32_t pos = wave_prefix(cnt, &total);
-      const uint64_t kmask = __ballot(keep);
-      uint32_t dst = 0;
-      if (lane_id() == kWave - 1 && total) {
-        const uint32_t base = atomicAdd(&s_fill, total);
-        if (base + total <= part_cap) {
-          atomicMax(&s_commit, base + total);
-          dst = part_base + base;
-        } else {  // the part is full: spill into the tail half
-          const uint32_t tb = atomicAdd(&A.tailfill[r], total);
-          if (tb + total <= g.n)
-            dst = g.n + tb;
-          else
-            dst = 0xFFFFFFFFu;
-        }
-      }
-      if (lane_id() == 0 && kmask) atomicAdd(&s_kept, (uint32_t)__popcll(kmask));
-      dst = __shfl(dst, kWave - 1, kWave);
-      if (dst == 0xFFFFFFFFu) {
-        if (cnt) atomicOr(&c.overflow, 1u);
-        continue;
-      }
-      pos += dst;
-      if (keep) lout[pos++] = (int32_t)v;
-      while (claims) {
-        const int d = __builtin_ctz(claims);
-        claims &= claims - 1u;
-        lout[pos++] = (int32_t)((uint32_t)((int32_t)v + dir_offset(g, d)) | kNewFlag);
-      }
+    if (lane == 0) {
+      if (kept_w) atomicAdd(&s_kept, kept_w);
+      if (grown_w) atomicAdd(&s_grown, grown_w);
     }
   }
   __syncthreads();
   if (beta < nwg && threadIdx.x == 0) {
     Q.seg[P.wgoff[r] + r + k] = SegEntry{r, part_base, s_commit, 0u};
     A.wgkept[beta] = s_kept;
+    A.wggrown[beta] = s_grown;
   }
 }
 
@@ -943,11 +1147,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
 __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
   __shared__ uint32_t acc_kept[kMaxBatch];
   __shared__ uint32_t acc_out[kMaxBatch];
+  __shared__ uint32_t acc_grown[kMaxBatch];
   const uint32_t p = A.bctl->plan;
   const SweepPlan& P = A.plan[p];
   const SweepPlan& Q = A.plan[p ^ 1u];
   for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) {
     acc_kept[r] = 0;
+    acc_grown[r] = 0;
     acc_out[r] = A.tailfill[r];
   }
   if (threadIdx.x == 0) A.bctl->running = 0;
@@ -960,15 +1166,16 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
       if (P.wgoff[mid] <= w) a = mid; else b = mid;
     }
     atomicAdd(&acc_kept[a], A.wgkept[w]);
+    atomicAdd(&acc_grown[a], A.wggrown[w]);
     atomicAdd(&acc_out[a], Q.seg[w + a].fill);
   }
   __syncthreads();
   for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) {
     const uint32_t w0 = P.wgoff[r], w1 = P.wgoff[r + 1];
-    Q.seg[w1 + r] = SegEntry{r, A.reals[r].g.n, A.tailfill[r], 0u};
+    Q.seg[w1 + r] = SegEntry{r, A.reals[r].tl.n, A.tailfill[r], 0u};
     A.tailfill[r] = 0;
     Q.rseg[r] = w0 + r;
-    if (sweep_active(A.reals[r])) sweep_end(A, r, acc_kept[r], acc_out[r]);
+    if (sweep_active(A.reals[r])) sweep_end(A, r, acc_kept[r], acc_out[r], acc_grown[r]);
   }
   if (threadIdx.x == 0) Q.rseg[A.count] = nwg + A.count;
   __syncthreads();

@@ -1,7 +1,7 @@
 // qsgs_server.hip -- continuous-batching generation server (C ABI in include/qsgs.h).
 //
 // Requests of different sizes queue on the host; each tick admits queued requests in
-// arrival order while a slot is free and their footprint (grid + two front lists) fits
+// arrival order while a slot is free and their footprint (grid + tile lists) fits
 // the free part of the caller's device arena, seeds them, and advances every resident
 // realization by a few growth steps with the same per-step kernels that serve batches,
 // so the growth steps of all resident requests share each launch.  Finished requests
@@ -83,7 +83,7 @@ struct qsgs_server {
   std::deque<int64_t> ready;      // finished, grid not yet taken
   std::unordered_map<int64_t, Request> done;
 
-  static size_t front_bytes(const Geometry& g) { return 2 * align_up(2 * sizeof(int32_t) * g.n); }
+  static size_t front_bytes(const Geometry& g) { return sweep_state_bytes(g); }
   static size_t footprint(const Geometry& g) { return align_up(grid_bytes(g)) + front_bytes(g); }
 };
 
@@ -170,7 +170,7 @@ qsgs_status qsgs_server_submit(qsgs_server* S, int64_t request_id, const qsgs_di
   q.id = request_id;
   q.dims = *dims;
   q.params = *params;
-  const size_t need = qsgs_server::footprint(q.spec.g) + seed_layout({q.spec}, false).total;
+  const size_t need = qsgs_server::footprint(q.spec.g) + seed_layout({q.spec}, true).total;
   if (need > S->heap.hi - S->heap.lo)
     return fail(QSGS_ERR_CAPACITY, "request needs %zu arena bytes, the arena holds %zu", need,
                 S->heap.hi - S->heap.lo);
@@ -191,17 +191,14 @@ qsgs_status qsgs_server_tick(qsgs_server* S, int32_t* n_resident, int32_t* n_que
   while (!group.empty()) {
     std::vector<Spec> specs;
     for (size_t slot : group) specs.push_back(S->resident.at(S->slot_req[slot]).spec);
-    const SeedLayout L = seed_layout(specs, false);
+    const SeedLayout L = seed_layout(specs, true);
     if (S->heap.alloc(L.total, &scratch_off)) {
       scratch_bytes = L.total;
       for (size_t k = 0; k < group.size(); ++k) {
         qsgs_server::Request& q = S->resident.at(S->slot_req[group[k]]);
-        E.init_record(group[k], q.spec, &q.params,
-                      reinterpret_cast<uint8_t*>(S->arena + q.grid_off),
-                      reinterpret_cast<int32_t*>(S->arena + q.front_off),
-                      reinterpret_cast<int32_t*>(S->arena + q.front_off +
-                                                 align_up(2 * sizeof(int32_t) * q.spec.g.n)),
-                      2 * q.spec.g.n);
+        E.init_sweep_record(group[k], q.spec, &q.params,
+                            reinterpret_cast<uint8_t*>(S->arena + q.grid_off),
+                            S->arena + q.front_off);
       }
       E.attach_scratch(group, S->arena + scratch_off, L);
       for (size_t slot : group) QSGS_TRY(E.upload(slot, 1));
