@@ -468,54 +468,108 @@ __global__ void k_loop_resume(BatchArgs A) {
   set_status_and_thresholds(c);
 }
 
+// Eq. (1) thresholds of one step split for the 32-bit draws (H << 16 | L): a draw
+// passes iff H < hi, or H == hi and L < lo.  T = 2^32 gives hi = 65536 (always passes).
+// (Named fields, not arrays: a dynamically indexed array would live in scratch memory.)
+struct DrawThresholds {
+  uint32_t hi_face, hi_edge, hi_corner, lo_face, lo_edge, lo_corner;
+};
+
+__device__ __forceinline__ DrawThresholds draw_thresholds(uint64_t T0, uint64_t T1, uint64_t T2) {
+  return DrawThresholds{(uint32_t)(T0 >> 16),     (uint32_t)(T1 >> 16),
+                        (uint32_t)(T2 >> 16),     (uint32_t)(T0 & 0xFFFFu),
+                        (uint32_t)(T1 & 0xFFFFu), (uint32_t)(T2 & 0xFFFFu)};
+}
+
+// Linear offsets of the 26 directions for one geometry, computed on the fly.
+struct DirOffsetCalc {
+  const Geometry& g;
+  __device__ __forceinline__ int32_t operator()(int d) const { return dir_offset(g, d); }
+};
+// The same from a table (26 entries, e.g. in LDS).
+struct DirOffsetTable {
+  const int32_t* off;
+  __device__ __forceinline__ int32_t operator()(int d) const { return off[d]; }
+};
+
+// Directions of each class as 26-bit masks (bit d).
+constexpr uint32_t class_mask(int cls) {
+  uint32_t m = 0;
+  for (int d = 0; d < 26; ++d)
+    if ((int)((kDirClass >> (2 * d)) & 3u) == cls) m |= 1u << d;
+  return m;
+}
+constexpr uint32_t kEdgeDirs = class_mask(1), kCornerDirs = class_mask(2);
+
 // Draws of source voxel a at step t (Sec. 2.3 step 3; the draw rule is stated in qsgs.h):
 // its in-domain void neighbours (at the step's start) take the draws of ranks
 // j = 0, 1, ... in ascending direction; a passing draw claims the neighbour with a
 // 32-bit atomicOr that writes `mark` into its grid byte.  Returns the directions this
-// thread claimed first (the neighbour was still 0).
-// The key and grid pointer are passed by value: read through the record they would be
-// reloaded after every claim atomic.
+// thread claimed first (the neighbour was still 0).  Ranks are taken eight at a time,
+// one Philox block per eight, with the word and half of each rank fixed by unrolling;
+// a block's claim atomics are all issued before their results are read.  Targets in
+// `skip` (already grown this step) take their rank but need no claim.  The key and
+// grid pointer are passed by value: read through the record they would be reloaded
+// after every claim atomic.
+template <typename DirOffset>
 __device__ __forceinline__ uint32_t grow_draws(uint8_t* __restrict__ grid, uint32_t k0,
-                                               uint32_t k1, const Geometry& g, uint32_t a,
-                                               uint32_t t, const Nbhd& nb, uint64_t T0,
-                                               uint64_t T1, uint64_t T2, uint8_t mark) {
+                                               uint32_t k1, DirOffset doff, uint32_t a,
+                                               uint32_t t, uint32_t voidm, uint32_t skip,
+                                               DrawThresholds th, uint8_t mark) {
+  // values, selected per draw with v_cndmask (a select of field addresses would put
+  // the thresholds in scratch memory)
+  const uint32_t hf = th.hi_face, he = th.hi_edge, hc = th.hi_corner;
+  const uint32_t lf = th.lo_face, le = th.lo_edge, lc = th.lo_corner;
   uint32_t claims = 0;
-  uint32_t m = nb.voidm;
-  uint32_t j = 0;
-  int32_t hi_block = -1, lo_block = -1;
-  U4 H{0, 0, 0, 0}, L{0, 0, 0, 0};
-  while (m) {
-    const int d = __builtin_ctz(m);
-    m &= m - 1u;
-    if (!((nb.grown >> d) & 1u)) {  // a target already grown this step needs no draw
-      const int32_t blk = (int32_t)(j >> 3);
-      if (blk != hi_block) {
-        H = philox10(a, t, (uint32_t)blk, kTagGrowHi, k0, k1);
-        hi_block = blk;
-      }
-      const uint32_t wh = pick(H, (j >> 1) & 3u);
-      const uint32_t h = (j & 1u) ? (wh >> 16) : (wh & 0xFFFFu);
-      const int cls = dir_field(kDirClass, d);
-      const uint64_t Tc = cls == 0 ? T0 : (cls == 1 ? T1 : T2);
-      const uint32_t th = (uint32_t)(Tc >> 16);  // 65536 when Tc = 2^32
-      bool pass = h < th;
-      if (h == th) {  // high halves tie: decide on the low halves
-        if (blk != lo_block) {
-          L = philox10(a, t, (uint32_t)blk, kTagGrowLo, k0, k1);
-          lo_block = blk;
-        }
-        const uint32_t wl = pick(L, (j >> 1) & 3u);
-        const uint32_t l = (j & 1u) ? (wl >> 16) : (wl & 0xFFFFu);
-        pass = l < (uint32_t)(Tc & 0xFFFFu);
-      }
-      if (pass) {
-        const uint32_t q = (uint32_t)((int32_t)a + dir_offset(g, d));
-        const uint32_t sh = (q & 3u) * 8u;
-        const uint32_t old = atomicOr((uint32_t*)(grid + (q & ~3u)), (uint32_t)mark << sh);
-        if (((old >> sh) & 0xFFu) == kVoid) claims |= 1u << d;
+  uint32_t m = voidm;
+  for (uint32_t blk = 0; m; ++blk) {
+    const U4 H = philox10(a, t, blk, kTagGrowHi, k0, k1);
+    uint32_t dir[8];
+    uint32_t pass = 0, tie = 0, cls2 = 0, cls1 = 0;
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) {
+      dir[sl] = 0;
+      if (m) {
+        const int d = __builtin_ctz(m);
+        m &= m - 1u;
+        dir[sl] = (uint32_t)d;
+        const uint32_t w = sl < 2 ? H.x : (sl < 4 ? H.y : (sl < 6 ? H.z : H.w));
+        const uint32_t h = (sl & 1) ? (w >> 16) : (w & 0xFFFFu);
+        const bool edge = (kEdgeDirs >> d) & 1u, corner = (kCornerDirs >> d) & 1u;
+        const uint32_t hi = corner ? hc : (edge ? he : hf);
+        pass |= (uint32_t)(h < hi) << sl;
+        tie |= (uint32_t)(h == hi) << sl;
+        cls1 |= (uint32_t)edge << sl;
+        cls2 |= (uint32_t)corner << sl;
       }
     }
-    ++j;
+    if (tie) {  // high halves tie (rare): decide those slots on the low halves
+      const U4 L = philox10(a, t, blk, kTagGrowLo, k0, k1);
+#pragma unroll
+      for (int sl = 0; sl < 8; ++sl) {
+        const uint32_t wl = sl < 2 ? L.x : (sl < 4 ? L.y : (sl < 6 ? L.z : L.w));
+        const uint32_t l = (sl & 1) ? (wl >> 16) : (wl & 0xFFFFu);
+        const uint32_t lo = ((cls2 >> sl) & 1u) ? lc : (((cls1 >> sl) & 1u) ? le : lf);
+        if ((tie >> sl) & 1u) pass |= (uint32_t)(l < lo) << sl;
+      }
+    }
+    uint32_t old[8], shift[8];
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) {
+      old[sl] = 0;
+      shift[sl] = 0;
+      if (((pass >> sl) & 1u) && !((skip >> dir[sl]) & 1u)) {
+        const uint32_t q = (uint32_t)((int32_t)a + doff((int)dir[sl]));
+        shift[sl] = (q & 3u) * 8u;
+        old[sl] = atomicOr((uint32_t*)(grid + (q & ~3u)), (uint32_t)mark << shift[sl]);
+      } else {
+        pass &= ~(1u << sl);
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl)
+      if (((pass >> sl) & 1u) && ((old[sl] >> shift[sl]) & 0xFFu) == kVoid)
+        claims |= 1u << dir[sl];
   }
   return claims;
 }
@@ -542,12 +596,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_grow(BatchArgs A) {
       if (a >= g.n) {
         c.bad_entry = 1u;
       } else {
-        const uint64_t T0 = c.T[0], T1 = c.T[1], T2 = c.T[2];
+        const DrawThresholds th = draw_thresholds(c.T[0], c.T[1], c.T[2]);
         uint32_t x, y, z;
         coords_of(g, a, x, y, z);
         const Nbhd nb = load_neighbourhood(R.grid, g, a, x, y, z);
-        claims = grow_draws(R.grid, uniform(R.k0), uniform(R.k1), g, a, t, nb, T0, T1, T2,
-                            kGrown);
+        claims = grow_draws(R.grid, uniform(R.k0), uniform(R.k1), DirOffsetCalc{g}, a, t,
+                            nb.voidm, nb.grown, th, kGrown);
       }
     }
     uint32_t pos = wave_append((uint32_t)__builtin_popcount(claims), &c.new_count);
@@ -866,7 +920,10 @@ struct TileImage {
   uint64_t V[kHaloRows];   // in-domain and void at the step's start (0 or the mark)
   uint32_t LR[kHaloRows];  // bit 0: voxel x0 - 1 void, bit 1: voxel x0 + 64 void
   uint64_t S[kTileRows];   // solid (interior rows)
-  uint16_t q[kTileVoxels]; // front voxels: interior row << 6 | x - x0
+  uint16_t q[kTileVoxels];   // front voxels: interior row << 6 | x - x0
+  uint32_t vm[kTileVoxels];  // their void masks (direction order)
+  uint16_t ord[kTileVoxels]; // queue order by void count (similar work per round)
+  uint32_t hist[32];         // void-count histogram, then bucket cursors
 };
 
 // The 26-bit void mask (direction order) of front voxel (xl, jy, jz) of the image.
@@ -921,6 +978,7 @@ size_t sweep_lds_bytes(uint32_t block) { return sizeof(TileImage) * (block / kWa
 __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char sweep_lds[];
   __shared__ uint32_t s_tiles[kMaxBlock];
+  __shared__ int32_t s_doff[26];
   __shared__ uint32_t s_fill, s_commit, s_kept, s_grown;
   const uint32_t G = gridDim.x;
   const uint32_t p = uniform(A.bctl->plan);
@@ -953,6 +1011,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
     const Tiles tl = R.tl;
     uint8_t* __restrict__ grid = R.grid;
     uint32_t* __restrict__ stamp = R.stamp;
+    if (threadIdx.x < 26u) s_doff[threadIdx.x] = dir_offset(g, (int)threadIdx.x);  // read after
+                                                                                 // the first barrier
     const uint32_t k0 = uniform(R.k0), k1 = uniform(R.k1);
     const uint32_t sb = uniform(P.rseg[r]), se = uniform(P.rseg[r + 1]);
     const uint32_t e0 = uniform(P.segchunk[sb]);
@@ -965,7 +1025,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
     const uint32_t t = uniform((uint32_t)c.step);
     const bool run = uniform(c.mode) == kModeRun;
     const uint32_t mark = kGrown + (t & 1u), pmark = mark ^ 1u;
-    const uint64_t T0 = uniform64(c.T[0]), T1 = uniform64(c.T[1]), T2 = uniform64(c.T[2]);
+    const DrawThresholds th =
+        draw_thresholds(uniform64(c.T[0]), uniform64(c.T[1]), uniform64(c.T[2]));
     const int32_t* __restrict__ lin = uniform(c.cur) ? R.f1 : R.f0;
     int32_t* __restrict__ lout = uniform(c.cur) ? R.f0 : R.f1;
     uint32_t kept_w = 0, grown_w = 0;
@@ -1080,17 +1141,44 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
             T.q[pi + (uint32_t)__popcll(Fi & below)] = (uint16_t)((uint32_t)i << 6 | lane);
         }
         wave_sync();
-        // 4. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1))
-        uint32_t tm = 0, grown = 0;
+        // 4. void masks of the queue, then a counting sort of the queue by void count
+        // so that the lanes of one round draw similar numbers of blocks and slots
+        if (lane < 32u) T.hist[lane] = 0;
+        wave_sync();
         for (uint32_t qi = lane; qi < nq; qi += kWave) {
           const uint32_t ent = T.q[qi];
           const int i = (int)(ent >> 6), xl = (int)(ent & 63u);
+          const uint32_t vm = tile_void_mask(T, xl, i % kTileY, i / kTileY);
+          T.vm[qi] = vm;
+          atomicAdd(&T.hist[__builtin_popcount(vm)], 1u);
+        }
+        wave_sync();
+        {
+          const uint32_t hc = lane < 32u ? T.hist[lane] : 0u;
+          uint32_t hin = hc;
+#pragma unroll
+          for (int o = 1; o < 32; o <<= 1) {
+            const uint32_t v = __shfl_up(hin, o, kWave);
+            if (lane >= (uint32_t)o) hin += v;
+          }
+          if (lane < 32u) T.hist[lane] = hin - hc;
+        }
+        wave_sync();
+        for (uint32_t qi = lane; qi < nq; qi += kWave)
+          T.ord[atomicAdd(&T.hist[__builtin_popcount(T.vm[qi])], 1u)] = (uint16_t)qi;
+        wave_sync();
+        // 5. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1))
+        uint32_t tm = 0, grown = 0;
+        for (uint32_t k = lane; k < nq; k += kWave) {
+          const uint32_t qi = T.ord[k];
+          const uint32_t ent = T.q[qi];
+          const int i = (int)(ent >> 6), xl = (int)(ent & 63u);
           const int jy = i % kTileY, jz = i / kTileY;
-          const uint32_t vm = tile_void_mask(T, xl, jy, jz);
+          const uint32_t vm = T.vm[qi];
           const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
                              (uint32_t)(z0 + jz) * g.nxy;
           uint32_t claims =
-              grow_draws(grid, k0, k1, g, a, t, Nbhd{vm, 0u, 0u}, T0, T1, T2, (uint8_t)mark);
+              grow_draws(grid, k0, k1, DirOffsetTable{s_doff}, a, t, vm, 0u, th, (uint8_t)mark);
           grown += (uint32_t)__builtin_popcount(claims);
           while (claims) {
             const int d = __builtin_ctz(claims);
@@ -1104,7 +1192,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
           }
         }
         grown_w += wave_sum(grown);
-        // 5. list the tiles that may hold F_{t+1} for the next pass, each once: this
+        // 6. list the tiles that may hold F_{t+1} for the next pass, each once: this
         // tile (it has front voxels) and every tile that received a claim
         const uint32_t tmask = wave_or(tm) | 1u << 13;
         if (lane < 27u && ((tmask >> lane) & 1u)) {
