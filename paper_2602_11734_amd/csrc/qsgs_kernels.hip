@@ -468,6 +468,15 @@ __global__ void k_loop_resume(BatchArgs A) {
   set_status_and_thresholds(c);
 }
 
+// Directions of each class as 26-bit masks (bit d).
+constexpr uint32_t class_mask(int cls) {
+  uint32_t m = 0;
+  for (int d = 0; d < 26; ++d)
+    if ((int)((kDirClass >> (2 * d)) & 3u) == cls) m |= 1u << d;
+  return m;
+}
+constexpr uint32_t kEdgeDirs = class_mask(1), kCornerDirs = class_mask(2);
+
 // Eq. (1) thresholds of one step split for the 32-bit draws (H << 16 | L): a draw
 // passes iff H < hi, or H == hi and L < lo.  T = 2^32 gives hi = 65536 (always passes).
 // (Named fields, not arrays: a dynamically indexed array would live in scratch memory.)
@@ -492,14 +501,18 @@ struct DirOffsetTable {
   __device__ __forceinline__ int32_t operator()(int d) const { return off[d]; }
 };
 
-// Directions of each class as 26-bit masks (bit d).
-constexpr uint32_t class_mask(int cls) {
-  uint32_t m = 0;
-  for (int d = 0; d < 26; ++d)
-    if ((int)((kDirClass >> (2 * d)) & 3u) == cls) m |= 1u << d;
-  return m;
-}
-constexpr uint32_t kEdgeDirs = class_mask(1), kCornerDirs = class_mask(2);
+// High-half threshold of direction d: from its class, or from a 26-entry table.
+struct DirThresholdCalc {
+  uint32_t hf, he, hc;
+  __device__ __forceinline__ uint32_t operator()(int d) const {
+    return ((kCornerDirs >> d) & 1u) ? hc : (((kEdgeDirs >> d) & 1u) ? he : hf);
+  }
+};
+struct DirThresholdTable {
+  const uint32_t* hi;
+  __device__ __forceinline__ uint32_t operator()(int d) const { return hi[d]; }
+};
+
 
 // Draws of source voxel a at step t (Sec. 2.3 step 3; the draw rule is stated in qsgs.h):
 // its in-domain void neighbours (at the step's start) take the draws of ranks
@@ -511,46 +524,50 @@ constexpr uint32_t kEdgeDirs = class_mask(1), kCornerDirs = class_mask(2);
 // `skip` (already grown this step) take their rank but need no claim.  The key and
 // grid pointer are passed by value: read through the record they would be reloaded
 // after every claim atomic.
-template <typename DirOffset>
+template <typename DirOffset, typename DirThreshold>
 __device__ __forceinline__ uint32_t grow_draws(uint8_t* __restrict__ grid, uint32_t k0,
-                                               uint32_t k1, DirOffset doff, uint32_t a,
-                                               uint32_t t, uint32_t voidm, uint32_t skip,
-                                               DrawThresholds th, uint8_t mark) {
+                                               uint32_t k1, DirOffset doff, DirThreshold dhi,
+                                               uint32_t a, uint32_t t, uint32_t voidm,
+                                               uint32_t skip, DrawThresholds th, uint8_t mark) {
   // values, selected per draw with v_cndmask (a select of field addresses would put
   // the thresholds in scratch memory)
-  const uint32_t hf = th.hi_face, he = th.hi_edge, hc = th.hi_corner;
   const uint32_t lf = th.lo_face, le = th.lo_edge, lc = th.lo_corner;
   uint32_t claims = 0;
   uint32_t m = voidm;
   for (uint32_t blk = 0; m; ++blk) {
     const U4 H = philox10(a, t, blk, kTagGrowHi, k0, k1);
     uint32_t dir[8];
-    uint32_t pass = 0, tie = 0, cls2 = 0, cls1 = 0;
+    bool pass[8], tie[8];
+    bool any_tie = false;
 #pragma unroll
     for (int sl = 0; sl < 8; ++sl) {
       dir[sl] = 0;
+      pass[sl] = false;
+      tie[sl] = false;
       if (m) {
         const int d = __builtin_ctz(m);
         m &= m - 1u;
         dir[sl] = (uint32_t)d;
         const uint32_t w = sl < 2 ? H.x : (sl < 4 ? H.y : (sl < 6 ? H.z : H.w));
         const uint32_t h = (sl & 1) ? (w >> 16) : (w & 0xFFFFu);
-        const bool edge = (kEdgeDirs >> d) & 1u, corner = (kCornerDirs >> d) & 1u;
-        const uint32_t hi = corner ? hc : (edge ? he : hf);
-        pass |= (uint32_t)(h < hi) << sl;
-        tie |= (uint32_t)(h == hi) << sl;
-        cls1 |= (uint32_t)edge << sl;
-        cls2 |= (uint32_t)corner << sl;
+        const uint32_t hi = dhi(d);
+        pass[sl] = h < hi;
+        tie[sl] = h == hi;
       }
+      any_tie |= tie[sl];
     }
-    if (tie) {  // high halves tie (rare): decide those slots on the low halves
+    if (any_tie) {  // high halves tie (rare): decide those slots on the low halves
       const U4 L = philox10(a, t, blk, kTagGrowLo, k0, k1);
 #pragma unroll
       for (int sl = 0; sl < 8; ++sl) {
-        const uint32_t wl = sl < 2 ? L.x : (sl < 4 ? L.y : (sl < 6 ? L.z : L.w));
-        const uint32_t l = (sl & 1) ? (wl >> 16) : (wl & 0xFFFFu);
-        const uint32_t lo = ((cls2 >> sl) & 1u) ? lc : (((cls1 >> sl) & 1u) ? le : lf);
-        if ((tie >> sl) & 1u) pass |= (uint32_t)(l < lo) << sl;
+        if (tie[sl]) {
+          const uint32_t wl = sl < 2 ? L.x : (sl < 4 ? L.y : (sl < 6 ? L.z : L.w));
+          const uint32_t l = (sl & 1) ? (wl >> 16) : (wl & 0xFFFFu);
+          const uint32_t d = dir[sl];
+          const uint32_t lo =
+              ((kCornerDirs >> d) & 1u) ? lc : (((kEdgeDirs >> d) & 1u) ? le : lf);
+          pass[sl] = l < lo;
+        }
       }
     }
     uint32_t old[8], shift[8];
@@ -558,18 +575,16 @@ __device__ __forceinline__ uint32_t grow_draws(uint8_t* __restrict__ grid, uint3
     for (int sl = 0; sl < 8; ++sl) {
       old[sl] = 0;
       shift[sl] = 0;
-      if (((pass >> sl) & 1u) && !((skip >> dir[sl]) & 1u)) {
+      pass[sl] = pass[sl] && !((skip >> dir[sl]) & 1u);
+      if (pass[sl]) {
         const uint32_t q = (uint32_t)((int32_t)a + doff((int)dir[sl]));
         shift[sl] = (q & 3u) * 8u;
         old[sl] = atomicOr((uint32_t*)(grid + (q & ~3u)), (uint32_t)mark << shift[sl]);
-      } else {
-        pass &= ~(1u << sl);
       }
     }
 #pragma unroll
     for (int sl = 0; sl < 8; ++sl)
-      if (((pass >> sl) & 1u) && ((old[sl] >> shift[sl]) & 0xFFu) == kVoid)
-        claims |= 1u << dir[sl];
+      if (pass[sl] && ((old[sl] >> shift[sl]) & 0xFFu) == kVoid) claims |= 1u << dir[sl];
   }
   return claims;
 }
@@ -600,7 +615,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_grow(BatchArgs A) {
         uint32_t x, y, z;
         coords_of(g, a, x, y, z);
         const Nbhd nb = load_neighbourhood(R.grid, g, a, x, y, z);
-        claims = grow_draws(R.grid, uniform(R.k0), uniform(R.k1), DirOffsetCalc{g}, a, t,
+        claims = grow_draws(R.grid, uniform(R.k0), uniform(R.k1), DirOffsetCalc{g},
+                            DirThresholdCalc{th.hi_face, th.hi_edge, th.hi_corner}, a, t,
                             nb.voidm, nb.grown, th, kGrown);
       }
     }
@@ -918,7 +934,7 @@ __device__ __forceinline__ uint32_t wave_prefix(uint32_t cnt, uint32_t* total) {
 // (jy + 1) + 6 (jz + 1).  Bit i of a row mask is voxel x0 + i.
 struct TileImage {
   uint64_t V[kHaloRows];   // in-domain and void at the step's start (0 or the mark)
-  uint32_t LR[kHaloRows];  // bit 0: voxel x0 - 1 void, bit 1: voxel x0 + 64 void
+  uint64_t L, R;           // bit h: voxel x0 - 1 (L) / x0 + 64 (R) of halo row h void
   uint64_t S[kTileRows];   // solid (interior rows)
   uint16_t q[kTileVoxels];   // front voxels: interior row << 6 | x - x0
   uint32_t vm[kTileVoxels];  // their void masks (direction order)
@@ -936,9 +952,9 @@ __device__ __forceinline__ uint32_t tile_void_mask(const TileImage& T, int xl, i
     for (int ky = 0; ky < 3; ++ky) {
       const int h = (jy + ky) + (kTileY + 2) * (jz + kz);
       const uint64_t V = T.V[h];
-      const uint32_t lr = T.LR[h];
-      const uint32_t left = xl == 0 ? (lr & 1u) : (uint32_t)(V >> (xl - 1)) & 1u;
-      const uint32_t right = xl == kTileX - 1 ? (lr >> 1) : (uint32_t)(V >> (xl + 1)) & 1u;
+      const uint32_t left = xl == 0 ? (uint32_t)(T.L >> h) & 1u : (uint32_t)(V >> (xl - 1)) & 1u;
+      const uint32_t right =
+          xl == kTileX - 1 ? (uint32_t)(T.R >> h) & 1u : (uint32_t)(V >> (xl + 1)) & 1u;
       if (kz == 1 && ky == 1) {
         vm |= (left | right << 1) << d;
         d += 2;
@@ -979,6 +995,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char sweep_lds[];
   __shared__ uint32_t s_tiles[kMaxBlock];
   __shared__ int32_t s_doff[26];
+  __shared__ uint32_t s_dhi[26];
   __shared__ uint32_t s_fill, s_commit, s_kept, s_grown;
   const uint32_t G = gridDim.x;
   const uint32_t p = uniform(A.bctl->plan);
@@ -1027,6 +1044,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
     const uint32_t mark = kGrown + (t & 1u), pmark = mark ^ 1u;
     const DrawThresholds th =
         draw_thresholds(uniform64(c.T[0]), uniform64(c.T[1]), uniform64(c.T[2]));
+    if (threadIdx.x < 26u) {  // read after the first barrier
+      const uint32_t hf = th.hi_face, he = th.hi_edge, hc = th.hi_corner;
+      const uint32_t d = threadIdx.x;
+      s_dhi[d] = ((kCornerDirs >> d) & 1u) ? hc : (((kEdgeDirs >> d) & 1u) ? he : hf);
+    }
     const int32_t* __restrict__ lin = uniform(c.cur) ? R.f1 : R.f0;
     int32_t* __restrict__ lout = uniform(c.cur) ? R.f0 : R.f1;
     uint32_t kept_w = 0, grown_w = 0;
@@ -1059,11 +1081,27 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
         wave_sync();  // the previous tile's image is no longer read
         // 1. stage the rows of the tile and its halo, one z plane (6 rows) of loads in
         // flight at a time (off-domain lanes read byte 0 and are masked); fold the
-        // previous step's marks
+        // previous step's marks.  The halo columns x0 - 1 and x0 + 64 of all 36 rows are
+        // read by 36 lanes at once.
+        {
+          const int h = (int)lane;
+          const int32_t y = y0 - 1 + h % (kTileY + 2), z = z0 - 1 + h / (kTileY + 2);
+          const bool rin = h < kHaloRows && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+          const int32_t row = rin ? y * g.nx + z * (int32_t)g.nxy : 0;
+          const bool inl = rin && x0 > 0, inr = rin && x0 + kTileX < g.nx;
+          const uint32_t bl = inl ? grid[row + x0 - 1] : 0xFFu;
+          const uint32_t br = inr ? grid[row + x0 + kTileX] : 0xFFu;
+          const uint64_t Lm = __ballot(bl == kVoid || bl == mark);
+          const uint64_t Rm = __ballot(br == kVoid || br == mark);
+          if (lane == 0) {
+            T.L = Lm;
+            T.R = Rm;
+          }
+        }
         for (int hz = 0; hz < kTileZ + 2; ++hz) {
           const int32_t z = z0 - 1 + hz;
           const bool zin = z >= 0 && z < g.nz;
-          uint32_t bv[kTileY + 2], be[kTileY + 2];
+          uint32_t bv[kTileY + 2];
           int32_t rowv[kTileY + 2];
 #pragma unroll
           for (int hy = 0; hy < kTileY + 2; ++hy) {
@@ -1071,19 +1109,15 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
             const bool rin = zin && y >= 0 && y < g.ny;
             const int32_t row = rin ? y * g.nx + z * (int32_t)g.nxy : 0;
             const int32_t x = x0 + (int32_t)lane;
-            const int32_t xe = lane == 0 ? x0 - 1 : x0 + kTileX;
             const bool in = rin && x < g.nx;
-            const bool ine = rin && lane < 2 && xe >= 0 && xe < g.nx;
             rowv[hy] = in ? row + x : -1;
             bv[hy] = grid[in ? row + x : 0];
-            be[hy] = ine ? grid[row + xe] : 0xFFu;
           }
 #pragma unroll
           for (int hy = 0; hy < kTileY + 2; ++hy) {
             const bool in = rowv[hy] >= 0;
             const bool vd = in && (bv[hy] == kVoid || bv[hy] == mark);
             const uint64_t V = __ballot(vd);
-            const uint64_t E = __ballot(be[hy] == kVoid || be[hy] == mark);
             const int h = hy + (kTileY + 2) * hz;
             if (hy >= 1 && hy <= kTileY && hz >= 1 && hz <= kTileZ) {
               const uint64_t Sm = __ballot(in && !vd);
@@ -1093,10 +1127,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
               }
               if (lane == 0) T.S[(hy - 1) + kTileY * (hz - 1)] = Sm;
             }
-            if (lane == 0) {
-              T.V[h] = V;
-              T.LR[h] = (uint32_t)E & 3u;
-            }
+            if (lane == 0) T.V[h] = V;
           }
         }
         wave_sync();
@@ -1111,8 +1142,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
             for (int ky = 0; ky < 3; ++ky) {
               const int h = (jy + ky) + (kTileY + 2) * (jz + kz);
               const uint64_t V = T.V[h];
-              const uint32_t lr = T.LR[h];
-              D |= V | (V << 1) | (V >> 1) | (uint64_t)(lr & 1u) | ((uint64_t)(lr >> 1) << 63);
+              D |= V | (V << 1) | (V >> 1) | ((T.L >> h) & 1ull) | (((T.R >> h) & 1ull) << 63);
             }
           F = T.S[lane] & D;
         }
@@ -1177,8 +1207,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
           const uint32_t vm = T.vm[qi];
           const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
                              (uint32_t)(z0 + jz) * g.nxy;
-          uint32_t claims =
-              grow_draws(grid, k0, k1, DirOffsetTable{s_doff}, a, t, vm, 0u, th, (uint8_t)mark);
+          uint32_t claims = grow_draws(grid, k0, k1, DirOffsetTable{s_doff},
+                                       DirThresholdTable{s_dhi}, a, t, vm, 0u, th, (uint8_t)mark);
           grown += (uint32_t)__builtin_popcount(claims);
           while (claims) {
             const int d = __builtin_ctz(claims);
