@@ -12,6 +12,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +24,22 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# 32-bit integer vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one op per lane
+# per cycle
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# algorithmic integer ops: a Philox4x32-10 block is 10 rounds of two 32x32->64
+# products (2 ops each), four XORs and two key additions; a draw extracts a 16-bit
+# half and compares it; a front voxel tests its 26 neighbours
+OPS_PER_BLOCK, OPS_PER_DRAW, OPS_PER_FRONT = 100, 2, 26
+
+
+def sweep_pass_ops(log_front, log_draws, log_blocks, final_front):
+    """Algorithmic integer ops of every fused-sweep pass of one generation: a running
+    pass finds F_t (26 tests per front voxel) and draws for it; the final pass only
+    finds F_T."""
+    out = [OPS_PER_BLOCK * b + OPS_PER_DRAW * d + OPS_PER_FRONT * f
+           for f, d, b in zip(log_front, log_draws, log_blocks)]
+    return out + [OPS_PER_FRONT * final_front]
 
 
 def sweep_pass_bytes(log_front, log_new, n_seeds, final_front):
@@ -43,6 +60,35 @@ def sweep_pass_bytes(log_front, log_new, n_seeds, final_front):
     return out
 
 
+KERNEL_SOURCES = ("qsgs_kernels.hip", "qsgs_device.h", "qsgs_internal.h")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_400cube_hbm_traffic.md")
+
+
+def kernel_source_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the sweep kernel's sources."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2602_11734_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launches_per_step: float):
+    """HBM bytes per k_sweep launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed
+    counter summary, or None when the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+
+
 def cpu_baseline(case, steps: int):
     """The oracle (single thread) on the first `steps` growth steps of `case`."""
     from oracle import oracle
@@ -57,6 +103,60 @@ def cpu_baseline(case, steps: int):
                       f"({grown} voxels grown) in {dt:.1f} s on one host core"}
 
 
+def batched_vs_plain(q, torch):
+    """Realizations/s of the 64-realization mix: one batched call (one sweep launch per
+    step over all realizations) against one qsgs_generate per realization, outputs
+    compared byte for byte."""
+    cases = workloads.config4()
+    dims = [c.dims for c in cases]
+    params = [q.params_of(c) for c in cases]
+    grids = [torch.empty(q.qsgs_grid_bytes(d), dtype=torch.uint8, device="cuda") for d in dims]
+    wsb = q.qsgs_batch_workspace_bytes(dims, params)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    q.qsgs_generate_batch(dims, params, grids, ws, wsb)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, infos = q.qsgs_generate_batch(dims, params, grids, ws, wsb)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    grid1 = torch.empty(max(q.qsgs_grid_bytes(d) for d in dims), dtype=torch.uint8,
+                        device="cuda")
+    pws = max(q.qsgs_workspace_bytes(d, p) for d, p in zip(dims, params))
+    ws1 = torch.empty(pws, dtype=torch.uint8, device="cuda")
+    same = True
+    t_plain = 0.0
+    for c, p, g in zip(cases, params, grids):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q.qsgs_generate(c.dims, p, grid1, ws1, pws)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        n = c.n
+        same = same and bool(torch.equal(grid1[:n], g[:n]))
+    vox = sum(c.n for c in cases)
+    return {"workload": "64 realizations, edges {96..256}, porosity U[0.05,0.25], s U{4..30}, "
+                        "S_d 5e-4, face 0.01 at 4:1:0.25, keys 0..63",
+            "voxels": vox, "batched_realizations_per_s": len(cases) / t_batch,
+            "plain_realizations_per_s": len(cases) / t_plain,
+            "speedup": t_plain / t_batch, "identical_outputs": same}
+
+
+def served_vs_plain(n_requests: int, rate: float):
+    """Poisson request stream (mixed sizes): continuous batching against the plain
+    one-at-a-time path on the same arrivals; p50/p99 latency and realizations/s."""
+    from paper_2602_11734_amd import serving
+    import paper_2602_11734_amd as q
+    reqs = workloads.config5(n_requests=n_requests, rate_per_s=rate)
+    budget = 24 << 30
+    arena = serving.server_arena_bytes(reqs, 64, budget)
+    served = serving.serve_stream(reqs, arena, max_slots=64, steps_per_tick=4).summary()
+    plain = serving.plain_stream(reqs).summary()
+    return {"workload": f"{n_requests} requests at {rate:g}/s, edge U{{64..320}}, porosity "
+                        "U[0.05,0.30], s U{4..30}, S_d U[5e-4,5e-3], face U[0.005,0.02], "
+                        "key = request id", "arena_budget_bytes": budget,
+            "served": served, "plain": plain}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +164,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched vs plain realizations/s measurement")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served vs plain request-stream measurement")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-rate", type=float, default=150.0, help="arrivals per second")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy kernel over BYTES bytes three times "
                          "(the reference kernel for scaling HBM byte counters)")
@@ -121,23 +227,31 @@ def main():
     q.qsgs_profile_enable(False)
     # every timed step repeats the same three generations (deterministic), so the
     # per-step logs of the last one describe all of them
-    logs = [q.qsgs_read_step_log(b.ws, b.ws_bytes, stream=stream) for b in bufs]
-    runs = [(c.name, infos[k * len(cases) + i], logs[i][0], logs[i][1])
+    logs = [q.qsgs_read_step_log(b.ws, b.ws_bytes, stream=stream) +
+            q.qsgs_read_step_work(b.ws, b.ws_bytes, stream=stream) for b in bufs]
+    runs = [(c.name, infos[k * len(cases) + i], logs[i])
             for k in range(args.steps) for i, c in enumerate(cases)]
 
-    grown = sum(info["solid_count"] - info["n_seeds"] for _, info, _, _ in runs)
+    grown = sum(info["solid_count"] - info["n_seeds"] for _, info, _ in runs)
     value = grown / elapsed
-    # algorithmic bytes of the timed sweep launches (every pass of every generation)
-    passes = [sweep_pass_bytes(lf, ln, info["n_seeds"], info["front_size"])
-              for _, info, lf, ln in runs]
+    # algorithmic ops and bytes of the timed sweep launches (every pass of every
+    # generation)
+    ops = [sweep_pass_ops(lg[0], lg[3], lg[4], info["front_size"]) for _, info, lg in runs]
+    passes = [sweep_pass_bytes(lg[0], lg[1], info["n_seeds"], info["front_size"])
+              for _, info, lg in runs]
     launches = sum(len(x) for x in passes)
+    assert launches == sum(len(x) for x in ops) == int(prof["grow_launches"]), (launches, prof)
     sbytes = sum(sum(x) for x in passes)
-    assert launches == int(prof["grow_launches"]), (launches, prof)
+    sops = sum(sum(x) for x in ops)
     sweep_avg_ms = prof["grow_ms"] / max(launches, 1)
-    sweep_gbs = (sbytes / launches) / (sweep_avg_ms * 1e-3) / 1e9 if launches else 0.0
+    sweep_s = sweep_avg_ms * 1e-3
+    sweep_tops = (sops / launches) / sweep_s / 1e12 if launches else 0.0
+    sweep_gbs = (sbytes / launches) / sweep_s / 1e9 if launches else 0.0
+    traffic = measured_traffic(launches_per_step=launches / args.steps)
 
     per_case = {}
-    for name, info, lf, ln in runs:
+    for name, info, lg in runs:
+        lf = lg[0]
         per_case.setdefault(name, {"steps": info["step"], "seeds": info["n_seeds"],
                                    "solid": info["solid_count"], "status": info["status"],
                                    "max_front": int(np.max(lf)) if len(lf) else 0})
@@ -160,15 +274,23 @@ def main():
                                "G_ref 0.01/0.0025/0.000625, diamond spacing s=20, key 1; "
                                "one step = the three generations end to end",
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": sweep_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": sweep_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep", "avg_launch_ms": sweep_avg_ms,
-                     "launches": launches, "bytes_per_launch": sbytes / max(launches, 1)},
+        "roofline": {"bound": "alu", "achieved": sweep_tops, "peak": ALU_PEAK_TOPS,
+                     "unit": "Tops/s (int32)", "frac": sweep_tops / ALU_PEAK_TOPS,
+                     "traffic": traffic, "kernel": "k_sweep",
+                     "avg_launch_ms": sweep_avg_ms, "launches": launches,
+                     "ops_per_launch": sops / max(launches, 1),
+                     "hbm_algorithmic": {"achieved": sweep_gbs, "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s", "frac": sweep_gbs / HBM_PEAK_GBS,
+                                         "bytes_per_launch": sbytes / max(launches, 1)}},
         "detail": {"sweep_ms_total": prof["grow_ms"], "seed_ms_total": prof["seed_ms"],
                    "growth_only_voxels_per_s": grown / (prof["grow_ms"] * 1e-3),
                    "n_over_t_per_realization": cases[0].n * 3 * args.steps / elapsed,
                    "realizations": per_case},
     }
+    if not args.no_batch:
+        out["detail"]["batched"] = batched_vs_plain(q, torch)
+    if not args.no_serve:
+        out["detail"]["serving"] = served_vs_plain(args.serve_requests, args.serve_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cases[1], args.cpu_steps)
     print(json.dumps(out))

@@ -170,6 +170,14 @@ qsgs_status qsgs_generate_batch(int32_t count, const qsgs_dims* dims, const qsgs
 int64_t qsgs_read_step_log(const void* d_ws, size_t ws_bytes, int32_t index, int64_t* front,
                            int64_t* grown, int64_t* count, int64_t max_entries, void* stream);
 
+/* The work of each logged step (same entries and return value as qsgs_read_step_log; any
+ * array may be NULL): draws[t] = number of draws of step t, one per front voxel and
+ * in-domain void neighbour (Sec. 2.3 step 3), blocks[t] = Philox blocks of the high
+ * halves, one per eight draws of a front voxel (the draw rule above).  These are the
+ * integer work of the growth sweep.  Synchronises `stream`. */
+int64_t qsgs_read_step_work(const void* d_ws, size_t ws_bytes, int32_t index, int64_t* draws,
+                            int64_t* blocks, int64_t max_entries, void* stream);
+
 /* Continuous-batching server.  Generation requests of different sizes are queued on
  * the host; each tick admits queued requests in arrival order while a slot is free and
  * their footprint -- grid (qsgs_grid_bytes) plus two lists (8 N bytes each) --

@@ -83,7 +83,7 @@ def lib():
         _lib.orc_step_fullfield.argtypes = [i32, i32, i32, vp, u32, vp, u64]
         _lib.orc_step_fullfield.restype = i64
         _lib.orc_generate.argtypes = [i32, i32, i32, P(_Params), vp, P(_Result), vp, vp, vp, vp,
-                                      i32]
+                                      vp, vp, i32]
         _lib.orc_generate.restype = i32
     return _lib
 
@@ -191,6 +191,8 @@ class OracleRun:
     log_front: np.ndarray | None = None
     log_new: np.ndarray | None = None
     log_count: np.ndarray | None = None
+    log_draws: np.ndarray | None = None
+    log_blocks: np.ndarray | None = None
 
 
 def generate(dims, solid_fraction: float, seed_prob: float, g_ref, spacing: int, key: int,
@@ -204,11 +206,12 @@ def generate(dims, solid_fraction: float, seed_prob: float, g_ref, spacing: int,
     lf = np.zeros(max(log_cap, 1), dtype=np.int64) if log_cap else None
     ln = np.zeros(max(log_cap, 1), dtype=np.int64) if log_cap else None
     lc = np.zeros(max(log_cap, 1), dtype=np.int64) if log_cap else None
+    ld = np.zeros(max(log_cap, 1), dtype=np.int64) if log_cap else None
+    lb = np.zeros(max(log_cap, 1), dtype=np.int64) if log_cap else None
     lib().orc_generate(nx, ny, nz, ctypes.byref(p), _ptr(grid), ctypes.byref(res), _ptr(b),
-                       _ptr(lf), _ptr(ln), _ptr(lc), int(log_cap))
+                       _ptr(lf), _ptr(ln), _ptr(lc), _ptr(ld), _ptr(lb), int(log_cap))
     m = min(res.steps, log_cap)
+    cut = (lambda a: a[:m].copy() if a is not None else None)
     return OracleRun(grid, res.n_candidates, res.n_seeds, res.solid_count, res.target_count,
-                     res.front_size, res.steps, res.status, b,
-                     lf[:m].copy() if lf is not None else None,
-                     ln[:m].copy() if ln is not None else None,
-                     lc[:m].copy() if lc is not None else None)
+                     res.front_size, res.steps, res.status, b, cut(lf), cut(ln), cut(lc),
+                     cut(ld), cut(lb))

@@ -347,10 +347,14 @@ int64_t orc_step_fullfield(int32_t nx, int32_t ny, int32_t nz, uint8_t* grid, ui
 /* while phi_a < phi_s and A is not empty (Sec. 2.3 step 5, Algorithm 3).    */
 /* Readings: no trimming of the last step's overshoot; an empty front with   */
 /* count < S* ends the run as "exhausted"; a step cap ends it as "max steps". */
+/* The step log also records the step's work: draws = one per (front cell,   */
+/* void neighbour) pair (Sec. 2.3 step 3), blocks = Philox blocks of the     */
+/* high halves, one per eight ranks of a front cell (the draw rule).         */
 /* ------------------------------------------------------------------------ */
 int32_t orc_generate(int32_t nx, int32_t ny, int32_t nz, const orc_params* p, uint8_t* grid,
                      orc_result* res, int32_t* birth, int64_t* log_front, int64_t* log_new,
-                     int64_t* log_count, int32_t log_cap) {
+                     int64_t* log_count, int64_t* log_draws, int64_t* log_blocks,
+                     int32_t log_cap) {
   const int64_t n = (int64_t)nx * ny * nz;
   const int64_t s_star = orc_target_count(p->solid_fraction, n);
   const uint64_t t_seed = orc_prob_threshold(p->seed_prob);
@@ -383,6 +387,15 @@ int32_t orc_generate(int32_t nx, int32_t ny, int32_t nz, const orc_params* p, ui
       if (log_front) log_front[t] = nA;
       if (log_new) log_new[t] = n_new;
       if (log_count) log_count[t] = cnt;
+      /* the masks of the step's sources, as orc_step_liets took them */
+      int64_t draws = 0, blocks = 0;
+      for (int64_t i = 0; i < nA; ++i) {
+        int c = popcount32(mask[i]);
+        draws += c;
+        blocks += (c + 7) / 8;
+      }
+      if (log_draws) log_draws[t] = draws;
+      if (log_blocks) log_blocks[t] = blocks;
     }
     if (birth)
       for (int64_t k = 0; k < n_new; ++k) birth[added[k]] = t + 1;

@@ -74,6 +74,7 @@ SIGNATURES = {
     "qsgs_batch_workspace_bytes": (_SZ, [_I32, _VP, _VP]),
     "qsgs_generate_batch": (ctypes.c_int, [_I32, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
     "qsgs_read_step_log": (_I64, [_VP, _SZ, _I32, _VP, _VP, _VP, _I64, _VP]),
+    "qsgs_read_step_work": (_I64, [_VP, _SZ, _I32, _VP, _VP, _I64, _VP]),
     "qsgs_server_reserved_bytes": (_SZ, [_I32]),
     "qsgs_server_create": (ctypes.c_int, [_VP, _SZ, _I32, _I32, _VP, _P(_VP)]),
     "qsgs_server_submit": (ctypes.c_int, [_VP, _I64, _P(qsgs_dims), _P(qsgs_params)]),
@@ -202,6 +203,18 @@ def qsgs_read_step_log(ws, ws_bytes: int, index: int = 0, max_entries: int = 655
                                   _stream(stream))
     n = _check(int(n))
     return front[:n].copy(), grown[:n].copy(), count[:n].copy()
+
+
+def qsgs_read_step_work(ws, ws_bytes: int, index: int = 0, max_entries: int = 65536,
+                        stream=None):
+    """Per-step (draws, Philox high blocks) of a generation's growth sweep."""
+    import numpy as np
+    draws = np.zeros(max_entries, np.int64)
+    blocks = np.zeros(max_entries, np.int64)
+    n = load().qsgs_read_step_work(_ptr(ws), int(ws_bytes), int(index), draws.ctypes.data,
+                                   blocks.ctypes.data, int(max_entries), _stream(stream))
+    n = _check(int(n))
+    return draws[:n].copy(), blocks[:n].copy()
 
 
 def qsgs_batch_workspace_bytes(dims_list, params_list) -> int:

@@ -223,9 +223,14 @@ qsgs_status qsgs_generate_batch(int32_t count, const qsgs_dims* dims, const qsgs
   return generate_impl(count, dims, params, d_grids, d_ws, ws_bytes, infos, (hipStream_t)stream);
 }
 
-int64_t qsgs_read_step_log(const void* d_ws, size_t ws_bytes, int32_t index, int64_t* front,
-                           int64_t* grown, int64_t* count, int64_t max_entries, void* stream) {
-  last_error().clear();
+}  // extern "C"
+
+namespace {
+
+// Reads up to max_entries per-step log entries (kLogWords words each) of realization
+// `index` of a generation workspace; returns the number of entries or an error.
+int64_t read_log(const void* d_ws, size_t ws_bytes, int32_t index, int64_t max_entries,
+                 void* stream, std::vector<uint64_t>* out) {
   if (!d_ws) return fail(QSGS_ERR_INVALID, "d_ws is NULL");
   if (ws_bytes < sizeof(WsHeader)) return fail(QSGS_ERR_WORKSPACE, "workspace too small");
   hipStream_t s = (hipStream_t)stream;
@@ -242,14 +247,39 @@ int64_t qsgs_read_step_log(const void* d_ws, size_t ws_bytes, int32_t index, int
   QSGS_HIP(hipStreamSynchronize(s));
   const int64_t n = std::min<int64_t>({(int64_t)c.step, max_entries, (int64_t)h.log_cap});
   if (n <= 0) return 0;
-  std::vector<uint64_t> buf(3 * (size_t)n);
-  QSGS_HIP(hipMemcpyAsync(buf.data(), base + h.logs + sizeof(uint64_t) * 3 * h.log_cap * index,
-                          sizeof(uint64_t) * buf.size(), hipMemcpyDeviceToHost, s));
+  out->resize(kLogWords * (size_t)n);
+  QSGS_HIP(hipMemcpyAsync(out->data(),
+                          base + h.logs + sizeof(uint64_t) * kLogWords * h.log_cap * index,
+                          sizeof(uint64_t) * out->size(), hipMemcpyDeviceToHost, s));
   QSGS_HIP(hipStreamSynchronize(s));
+  return n;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t qsgs_read_step_log(const void* d_ws, size_t ws_bytes, int32_t index, int64_t* front,
+                           int64_t* grown, int64_t* count, int64_t max_entries, void* stream) {
+  last_error().clear();
+  std::vector<uint64_t> buf;
+  const int64_t n = read_log(d_ws, ws_bytes, index, max_entries, stream, &buf);
   for (int64_t t = 0; t < n; ++t) {
-    if (front) front[t] = (int64_t)buf[3 * t];
-    if (grown) grown[t] = (int64_t)buf[3 * t + 1];
-    if (count) count[t] = (int64_t)buf[3 * t + 2];
+    if (front) front[t] = (int64_t)buf[kLogWords * t];
+    if (grown) grown[t] = (int64_t)buf[kLogWords * t + 1];
+    if (count) count[t] = (int64_t)buf[kLogWords * t + 2];
+  }
+  return n;
+}
+
+int64_t qsgs_read_step_work(const void* d_ws, size_t ws_bytes, int32_t index, int64_t* draws,
+                            int64_t* blocks, int64_t max_entries, void* stream) {
+  last_error().clear();
+  std::vector<uint64_t> buf;
+  const int64_t n = read_log(d_ws, ws_bytes, index, max_entries, stream, &buf);
+  for (int64_t t = 0; t < n; ++t) {
+    if (draws) draws[t] = (int64_t)buf[kLogWords * t + 3];
+    if (blocks) blocks[t] = (int64_t)buf[kLogWords * t + 4];
   }
   return n;
 }

@@ -200,7 +200,7 @@ struct WsHeader {
 struct PersistLayout {
   size_t hdr = 0, bctl = 0, reals = 0, off = 0, live = 0, logs = 0, total = 0;
   size_t seg[2] = {0, 0}, segchunk[2] = {0, 0}, rseg[2] = {0, 0}, wgoff[2] = {0, 0};
-  size_t wgkept = 0, wggrown = 0, tailfill = 0;
+  size_t wgkept = 0, wggrown = 0, wgdraws = 0, wgblocks = 0, tailfill = 0;
   uint32_t log_cap = 0, seg_cap = 0;
 };
 
@@ -218,7 +218,7 @@ inline PersistLayout persist_layout(size_t count, uint32_t log_cap) {
   L.reals = take(sizeof(Real) * count);
   L.off = take(sizeof(uint64_t) * (count + 1));
   L.live = take(sizeof(uint32_t) * kMaxRounds);
-  L.logs = take(sizeof(uint64_t) * 3 * (size_t)log_cap * count);
+  L.logs = take(sizeof(uint64_t) * kLogWords * (size_t)log_cap * count);
   L.seg_cap = kMaxSweepGrid + 2 * (uint32_t)count + 8;
   for (int q = 0; q < 2; ++q) {
     L.seg[q] = take(sizeof(SegEntry) * L.seg_cap);
@@ -228,6 +228,8 @@ inline PersistLayout persist_layout(size_t count, uint32_t log_cap) {
   }
   L.wgkept = take(sizeof(uint32_t) * kMaxSweepGrid);
   L.wggrown = take(sizeof(uint32_t) * kMaxSweepGrid);
+  L.wgdraws = take(sizeof(uint32_t) * kMaxSweepGrid);
+  L.wgblocks = take(sizeof(uint32_t) * kMaxSweepGrid);
   L.tailfill = take(sizeof(uint32_t) * count);
   L.total = off;
   return L;
@@ -361,6 +363,8 @@ struct Engine {
     args.seg_cap = L.seg_cap;
     args.wgkept = at<uint32_t>(base, L.wgkept);
     args.wggrown = at<uint32_t>(base, L.wggrown);
+    args.wgdraws = at<uint32_t>(base, L.wgdraws);
+    args.wgblocks = at<uint32_t>(base, L.wgblocks);
     args.tailfill = at<uint32_t>(base, L.tailfill);
     const uint32_t want = std::max<uint32_t>(tune.grow_grid, 2 * (uint32_t)count);
     sweep_grid = std::min<uint32_t>(kMaxSweepGrid, (want + kNumXcd - 1) / kNumXcd * kNumXcd);
@@ -380,7 +384,7 @@ struct Engine {
 
   uint64_t* log_of(size_t r) const {
     if (P.log_cap == 0) return nullptr;
-    return at<uint64_t>(ws, P.logs) + (size_t)3 * P.log_cap * r;
+    return at<uint64_t>(ws, P.logs) + (size_t)kLogWords * P.log_cap * r;
   }
 
   // Fills record r for a new realization (to be seeded).  For the fused sweep,

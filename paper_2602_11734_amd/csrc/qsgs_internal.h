@@ -54,6 +54,10 @@ struct Tiles {
   FastDiv div_ntx, div_nty;
 };
 
+// Per-step log of a realization: |F_t|, voxels grown in step t, the solid count at the
+// start of step t, the step's draws and its high-half Philox blocks.
+constexpr uint32_t kLogWords = 5;
+
 // Loop status codes on the device (the public values plus an internal overflow code).
 constexpr int32_t kStatusDone = 1, kStatusExhausted = 2, kStatusMaxSteps = 3,
                   kStatusOverflow = 100;
@@ -180,6 +184,8 @@ struct BatchArgs {
   uint32_t seg_cap;     // entries of each segment table
   uint32_t* wgkept;     // front voxels found per logical workgroup of the current pass
   uint32_t* wggrown;    // voxels grown per logical workgroup of the current pass
+  uint32_t* wgdraws;    // draws per logical workgroup of the current pass
+  uint32_t* wgblocks;   // high-half Philox blocks per logical workgroup of the current pass
   uint32_t* tailfill;   // per realization: entries spilled into the tail half
 };
 

@@ -375,15 +375,32 @@ __global__ __launch_bounds__(kMaxBlock) void k_luby_round(BatchArgs A, uint32_t 
 }
 
 // Accepted candidates become seeds: 1 in the grid, appended to the realization's
-// seed list (which reuses its candidate list).
+// seed list (which reuses its candidate list).  The accepted lanes of a wavefront are
+// grouped by realization, one atomic per group.
 __global__ __launch_bounds__(kMaxBlock) void k_collect_seeds(BatchArgs A) {
   const uint32_t n = A.bctl->n_sorted;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (A.status[i] != kAccepted) continue;
-    Real& R = A.reals[A.sorted_r[i]];
-    const int32_t v = A.sorted_v[i];
-    R.grid[v] = kSolid;
-    R.cand[atomicAdd(&R.ctl.n_seeds, 1u)] = v;
+  const uint32_t lane = lane_id();
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    const bool acc = i < n && A.status[i] == kAccepted;
+    const uint32_t r = acc ? A.sorted_r[i] : 0xFFFFFFFFu;
+    uint64_t pending = __ballot(acc);
+    while (pending) {
+      const uint32_t leader = (uint32_t)__builtin_ctzll(pending);
+      const uint32_t rl = uniform(__shfl(r, (int)leader, kWave));
+      const bool mine = acc && r == rl;
+      const uint64_t m = __ballot(mine);
+      uint32_t slot = 0;
+      if (lane == leader) slot = atomicAdd(&A.reals[rl].ctl.n_seeds, (uint32_t)__popcll(m));
+      slot = __shfl(slot, (int)leader, kWave) + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (mine) {
+        Real& R = A.reals[rl];
+        const int32_t v = A.sorted_v[i];
+        R.grid[v] = kSolid;
+        R.cand[slot] = v;
+      }
+      pending &= ~m;
+    }
   }
 }
 
@@ -686,9 +703,12 @@ __global__ void k_step_end(BatchArgs A) {
   const uint32_t t = (uint32_t)c.step;
   const uint32_t grown = c.new_count;
   if (R.log && t < R.log_cap) {
-    R.log[3 * (uint64_t)t + 0] = c.front_size;
-    R.log[3 * (uint64_t)t + 1] = grown;
-    R.log[3 * (uint64_t)t + 2] = c.cnt;
+    uint64_t* e = R.log + kLogWords * (uint64_t)t;
+    e[0] = c.front_size;
+    e[1] = grown;
+    e[2] = c.cnt;
+    e[3] = 0;  // the step-by-step path does not count its work
+    e[4] = 0;
   }
   c.cnt += grown;
   c.last_new = grown;
@@ -879,9 +899,9 @@ __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
 }
 
 // End of a pass for realization r: kept = |F_t|, out = tiles listed for the next
-// pass, grown = voxels grown in the pass.
+// pass, grown = voxels grown in the pass, draws and blocks = its work.
 __device__ void sweep_end(const BatchArgs& A, uint32_t r, uint32_t kept, uint32_t out,
-                          uint32_t grown) {
+                          uint32_t grown, uint64_t draws, uint64_t blocks) {
   Real& R = A.reals[r];
   Ctl& c = R.ctl;
   const uint32_t bad = atomic_load(&c.overflow) | atomic_load(&c.bad_entry);
@@ -896,9 +916,12 @@ __device__ void sweep_end(const BatchArgs& A, uint32_t r, uint32_t kept, uint32_
   if (c.mode == kModeRun && kept > 0) {
     const uint32_t t = (uint32_t)c.step;
     if (R.log && t < R.log_cap) {
-      R.log[3 * (uint64_t)t + 0] = kept;
-      R.log[3 * (uint64_t)t + 1] = grown;
-      R.log[3 * (uint64_t)t + 2] = c.cnt;
+      uint64_t* e = R.log + kLogWords * (uint64_t)t;
+      e[0] = kept;
+      e[1] = grown;
+      e[2] = c.cnt;
+      e[3] = draws;
+      e[4] = blocks;
     }
     c.cnt += grown;
     c.last_new = grown;
@@ -936,9 +959,10 @@ struct TileImage {
   uint64_t V[kHaloRows];   // in-domain and void at the step's start (0 or the mark)
   uint64_t L, R;           // bit h: voxel x0 - 1 (L) / x0 + 64 (R) of halo row h void
   uint64_t S[kTileRows];   // solid (interior rows)
-  uint16_t q[kTileVoxels];   // front voxels: interior row << 6 | x - x0
-  uint32_t vm[kTileVoxels];  // their void masks (direction order)
-  uint16_t ord[kTileVoxels]; // queue order by void count (similar work per round)
+  uint32_t W[kTileVoxels];   // per queued front voxel: void mask (direction order) | x << 26
+  uint16_t qo[kTileVoxels];  // the queue (interior row << 6 | x - x0), then its order by
+                             // void count (similar work per round)
+  uint8_t row[kTileVoxels];  // interior row of each queued voxel
   uint32_t hist[32];         // void-count histogram, then bucket cursors
 };
 
@@ -990,13 +1014,16 @@ __device__ __forceinline__ void wave_sync() {
 size_t sweep_lds_bytes(uint32_t block) { return sizeof(TileImage) * (block / kWave); }
 
 // Each wavefront sweeps whole tiles on its own (no workgroup barrier per tile); the
-// workgroup resolves its share of list entries into LDS a block at a time.
-__global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
+// workgroup resolves its share of list entries into LDS 64 at a time.
+// At most 96 VGPRs: five waves per SIMD, the occupancy the per-wave LDS images
+// (< 8 KB each) allow at the default 256-thread workgroup.
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5)))
+void k_sweep(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char sweep_lds[];
-  __shared__ uint32_t s_tiles[kMaxBlock];
+  __shared__ uint32_t s_tiles[kWave];
   __shared__ int32_t s_doff[26];
   __shared__ uint32_t s_dhi[26];
-  __shared__ uint32_t s_fill, s_commit, s_kept, s_grown;
+  __shared__ uint32_t s_fill, s_commit, s_kept, s_grown, s_draws, s_blocks;
   const uint32_t G = gridDim.x;
   const uint32_t p = uniform(A.bctl->plan);
   const SweepPlan& P = A.plan[p];
@@ -1011,6 +1038,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
     s_commit = 0;
     s_kept = 0;
     s_grown = 0;
+    s_draws = 0;
+    s_blocks = 0;
   }
   uint32_t r = 0, k = 0, part_base = 0;
   if (beta < nwg) {
@@ -1051,10 +1080,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
     }
     const int32_t* __restrict__ lin = uniform(c.cur) ? R.f1 : R.f0;
     int32_t* __restrict__ lout = uniform(c.cur) ? R.f0 : R.f1;
-    uint32_t kept_w = 0, grown_w = 0;
-    for (uint32_t base = e_lo; base < e_hi; base += blockDim.x) {
+    uint32_t kept_w = 0, grown_w = 0, draws_l = 0, blocks_l = 0;
+    for (uint32_t base = e_lo; base < e_hi; base += kWave) {
       __syncthreads();  // the previous block of entries is consumed
-      {
+      if (threadIdx.x < (uint32_t)kWave) {
         const uint32_t e = base + threadIdx.x;
         if (e < e_hi) {  // segment of entry e: largest s with segchunk[s] <= e
           uint32_t lo = sb, hi = se;
@@ -1066,7 +1095,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
         }
       }
       __syncthreads();
-      const uint32_t nb = min((uint32_t)blockDim.x, e_hi - base);
+      const uint32_t nb = min((uint32_t)kWave, e_hi - base);
       for (uint32_t j = wib; j < nb; j += wpb) {
         const uint32_t u = uniform(s_tiles[j]);
         if (u >= tl.n) {
@@ -1168,7 +1197,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
               (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)F, i);
           const uint32_t pi = (uint32_t)__builtin_amdgcn_readlane(excl, i);
           if ((Fi >> lane) & 1ull)
-            T.q[pi + (uint32_t)__popcll(Fi & below)] = (uint16_t)((uint32_t)i << 6 | lane);
+            T.qo[pi + (uint32_t)__popcll(Fi & below)] = (uint16_t)((uint32_t)i << 6 | lane);
         }
         wave_sync();
         // 4. void masks of the queue, then a counting sort of the queue by void count
@@ -1176,10 +1205,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
         if (lane < 32u) T.hist[lane] = 0;
         wave_sync();
         for (uint32_t qi = lane; qi < nq; qi += kWave) {
-          const uint32_t ent = T.q[qi];
+          const uint32_t ent = T.qo[qi];
           const int i = (int)(ent >> 6), xl = (int)(ent & 63u);
           const uint32_t vm = tile_void_mask(T, xl, i % kTileY, i / kTileY);
-          T.vm[qi] = vm;
+          T.W[qi] = vm | (uint32_t)xl << 26;
+          T.row[qi] = (uint8_t)i;
           atomicAdd(&T.hist[__builtin_popcount(vm)], 1u);
         }
         wave_sync();
@@ -1194,17 +1224,21 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
           if (lane < 32u) T.hist[lane] = hin - hc;
         }
         wave_sync();
+        // (the queue has been read: its slots now take the order)
         for (uint32_t qi = lane; qi < nq; qi += kWave)
-          T.ord[atomicAdd(&T.hist[__builtin_popcount(T.vm[qi])], 1u)] = (uint16_t)qi;
+          T.qo[atomicAdd(&T.hist[__builtin_popcount(T.W[qi] & 0x3FFFFFFu)], 1u)] = (uint16_t)qi;
         wave_sync();
         // 5. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1))
         uint32_t tm = 0, grown = 0;
         for (uint32_t k = lane; k < nq; k += kWave) {
-          const uint32_t qi = T.ord[k];
-          const uint32_t ent = T.q[qi];
-          const int i = (int)(ent >> 6), xl = (int)(ent & 63u);
+          const uint32_t qi = T.qo[k];
+          const uint32_t w = T.W[qi];
+          const int i = T.row[qi], xl = (int)(w >> 26);
           const int jy = i % kTileY, jz = i / kTileY;
-          const uint32_t vm = T.vm[qi];
+          const uint32_t vm = w & 0x3FFFFFFu;
+          const uint32_t nv = (uint32_t)__builtin_popcount(vm);
+          draws_l += nv;
+          blocks_l += (nv + 7u) >> 3;
           const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
                              (uint32_t)(z0 + jz) * g.nxy;
           uint32_t claims = grow_draws(grid, k0, k1, DirOffsetTable{s_doff},
@@ -1245,9 +1279,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
         }
       }
     }
+    const uint32_t draws_w = wave_sum(draws_l), blocks_w = wave_sum(blocks_l);
     if (lane == 0) {
       if (kept_w) atomicAdd(&s_kept, kept_w);
       if (grown_w) atomicAdd(&s_grown, grown_w);
+      if (draws_w) atomicAdd(&s_draws, draws_w);
+      if (blocks_w) atomicAdd(&s_blocks, blocks_w);
     }
   }
   __syncthreads();
@@ -1255,6 +1292,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(BatchArgs A) {
     Q.seg[P.wgoff[r] + r + k] = SegEntry{r, part_base, s_commit, 0u};
     A.wgkept[beta] = s_kept;
     A.wggrown[beta] = s_grown;
+    A.wgdraws[beta] = s_draws;
+    A.wgblocks[beta] = s_blocks;
   }
 }
 
@@ -1266,12 +1305,16 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
   __shared__ uint32_t acc_kept[kMaxBatch];
   __shared__ uint32_t acc_out[kMaxBatch];
   __shared__ uint32_t acc_grown[kMaxBatch];
+  __shared__ unsigned long long acc_draws[kMaxBatch];
+  __shared__ unsigned long long acc_blocks[kMaxBatch];
   const uint32_t p = A.bctl->plan;
   const SweepPlan& P = A.plan[p];
   const SweepPlan& Q = A.plan[p ^ 1u];
   for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) {
     acc_kept[r] = 0;
     acc_grown[r] = 0;
+    acc_draws[r] = 0;
+    acc_blocks[r] = 0;
     acc_out[r] = A.tailfill[r];
   }
   if (threadIdx.x == 0) A.bctl->running = 0;
@@ -1285,6 +1328,8 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
     }
     atomicAdd(&acc_kept[a], A.wgkept[w]);
     atomicAdd(&acc_grown[a], A.wggrown[w]);
+    atomicAdd(&acc_draws[a], (unsigned long long)A.wgdraws[w]);
+    atomicAdd(&acc_blocks[a], (unsigned long long)A.wgblocks[w]);
     atomicAdd(&acc_out[a], Q.seg[w + a].fill);
   }
   __syncthreads();
@@ -1293,7 +1338,8 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
     Q.seg[w1 + r] = SegEntry{r, A.reals[r].tl.n, A.tailfill[r], 0u};
     A.tailfill[r] = 0;
     Q.rseg[r] = w0 + r;
-    if (sweep_active(A.reals[r])) sweep_end(A, r, acc_kept[r], acc_out[r], acc_grown[r]);
+    if (sweep_active(A.reals[r]))
+      sweep_end(A, r, acc_kept[r], acc_out[r], acc_grown[r], acc_draws[r], acc_blocks[r]);
   }
   if (threadIdx.x == 0) Q.rseg[A.count] = nwg + A.count;
   __syncthreads();

@@ -3,7 +3,8 @@
 Calls only the CPU oracle (``oracle/``) on the inputs stated in ``workloads.py``; the
 GPU tests compare the library's outputs with these stored values.  Each entry holds
 the SHA-256 of the final grid (N bytes, C order), the counts, the terminal status and
-the per-step series |F_t|, |New_t| and the solid count at the start of each step.
+the per-step series |F_t|, |New_t|, the solid count at the start of each step and the
+step's work (draws, high-half Philox blocks).
 
     python tests/golden/make_goldens.py [--jobs 8] [--only c2,c3]
 """
@@ -40,6 +41,7 @@ def run_case(case_dict: dict) -> dict:
         "status": r.status,
         "log_front": [int(x) for x in r.log_front], "log_new": [int(x) for x in r.log_new],
         "log_count": [int(x) for x in r.log_count],
+        "log_draws": [int(x) for x in r.log_draws], "log_blocks": [int(x) for x in r.log_blocks],
         "oracle_seconds": round(time.time() - t0, 2),
     }
 

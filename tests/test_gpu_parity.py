@@ -42,7 +42,8 @@ def run_gpu(q, case):
     params = q.params_of(case)
     grid, info, buf = q.generate(case.dims, params)
     torch.cuda.synchronize()
-    logs = q.qsgs_read_step_log(buf.ws, buf.ws_bytes)
+    logs = q.qsgs_read_step_log(buf.ws, buf.ws_bytes) + q.qsgs_read_step_work(buf.ws,
+                                                                               buf.ws_bytes)
     return grid.cpu().numpy(), info, logs
 
 
@@ -56,7 +57,7 @@ SMALL = workloads.small_cases() + workloads.config1()
 
 @pytest.mark.parametrize("case", SMALL, ids=[c.name for c in SMALL])
 def test_generate_matches_oracle(q, orc, case):
-    got, info, (lf, ln, lc) = run_gpu(q, case)
+    got, info, (lf, ln, lc, ld, lb) = run_gpu(q, case)
     ref = run_oracle(orc, case)
     assert info["status"] == ref.status
     assert info["n_candidates"] == ref.n_candidates
@@ -68,6 +69,8 @@ def test_generate_matches_oracle(q, orc, case):
     assert np.array_equal(lf, ref.log_front)
     assert np.array_equal(ln, ref.log_new)
     assert np.array_equal(lc, ref.log_count)
+    assert np.array_equal(ld, ref.log_draws)
+    assert np.array_equal(lb, ref.log_blocks)
     assert np.array_equal(got, ref.grid)
 
 
@@ -202,7 +205,7 @@ def _golden_check(q, entry):
     import torch
     c = entry["case"]
     case = workloads.Case(**{**c, "dims": tuple(c["dims"]), "g_ref": tuple(c["g_ref"])})
-    got, info, (lf, ln, lc) = run_gpu(q, case)
+    got, info, (lf, ln, lc, ld, lb) = run_gpu(q, case)
     assert info["status"] == entry["status"]
     assert info["n_candidates"] == entry["n_candidates"]
     assert info["n_seeds"] == entry["n_seeds"]
@@ -212,6 +215,8 @@ def _golden_check(q, entry):
     assert list(lf) == entry["log_front"]
     assert list(ln) == entry["log_new"]
     assert list(lc) == entry["log_count"]
+    assert list(ld) == entry["log_draws"]
+    assert list(lb) == entry["log_blocks"]
     assert hashlib.sha256(got.tobytes()).hexdigest() == entry["grid_sha256"]
     del got
     torch.cuda.empty_cache()
@@ -250,6 +255,9 @@ def test_batch_matches_oracle(q, orc):
         assert np.array_equal(lf, ref.log_front[: len(lf)]) and len(lf) == min(ref.steps, 4096)
         assert np.array_equal(ln, ref.log_new[: len(ln)])
         assert np.array_equal(lc, ref.log_count[: len(lc)])
+        ld, lb = q.qsgs_read_step_work(ws, wsb, index=k)
+        assert np.array_equal(ld, ref.log_draws[: len(ld)])
+        assert np.array_equal(lb, ref.log_blocks[: len(lb)])
 
 
 def test_batch_reuses_workspace(q, orc):

@@ -115,3 +115,38 @@ def test_single_voxel_domain(orc):
     assert run.status == orc.DONE and run.solid_count == 1 and run.steps == 0
     run = orc.generate((1, 1, 1), 1.0, 0.0, (0.5, 0.5, 0.5), 5, key=0, log_cap=4)
     assert run.status == orc.EXHAUSTED and run.solid_count == 0
+
+
+def _void_neighbour_counts(solid):
+    """For every voxel, the number of in-domain void neighbours among its 26
+    (array shifts over a zero-padded copy: out-of-domain cells count as solid)."""
+    nz, ny, nx = solid.shape
+    pad = np.ones((nz + 2, ny + 2, nx + 2), dtype=np.int32)
+    pad[1:-1, 1:-1, 1:-1] = solid
+    void = 1 - pad
+    cnt = np.zeros(solid.shape, dtype=np.int32)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == dy == dz == 0:
+                    continue
+                cnt += void[1 + dz:1 + dz + nz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+    return cnt
+
+
+@pytest.mark.parametrize("dims,spacing,key", [((23, 17, 11), 3, 5), ((40, 9, 30), 6, 2)])
+def test_step_work_log_matches_front_counts(orc, dims, spacing, key):
+    """The per-step work log: the front F_t is the solid voxels with a void neighbour,
+    draws_t sums their void-neighbour counts and blocks_t sums ceil(count / 8), all
+    recomputed from G_t (rebuilt from the birth map) with array shifts."""
+    nx, ny, nz = dims
+    run = orc.generate(dims, 0.7, 0.01, (0.1, 0.03, 0.01), spacing, key, birth=True,
+                       log_cap=10000)
+    assert run.steps > 2
+    for t in range(run.steps):
+        solid = ((run.birth >= 0) & (run.birth <= t)).astype(np.int32)
+        nv = _void_neighbour_counts(solid)
+        front = (solid == 1) & (nv > 0)
+        assert int(front.sum()) == run.log_front[t]
+        assert int(nv[front].sum()) == run.log_draws[t]
+        assert int(((nv[front] + 7) // 8).sum()) == run.log_blocks[t]
