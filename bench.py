@@ -60,12 +60,12 @@ def sweep_pass_bytes(log_front, log_new, n_seeds, final_front):
     return out
 
 
-KERNEL_SOURCES = ("qsgs_kernels.hip", "qsgs_device.h", "qsgs_internal.h")
+KERNEL_SOURCES = ("qsgs_kernels.hip", "qsgs_device.h", "qsgs_internal.h", "qsgs_host.h")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_sweep_400cube_hbm_traffic.md")
 
 
 def kernel_source_hash() -> str:
-    """First 16 hex digits of the SHA-256 of the sweep kernel's sources."""
+    """First 16 hex digits of the SHA-256 of the sweep kernel's sources and launch set-up."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2602_11734_amd", "csrc", f), "rb") as fh:

@@ -221,7 +221,8 @@ void qsgs_server_destroy(qsgs_server* server);
  * issued between two host reads of the loop state (`steps_per_sync`, 0 = adaptive).
  * The shape never changes a result: every output is a function of the inputs only.
  * qsgs_set_tuning applies process-wide to calls that start afterwards (NULL restores
- * the defaults: 256 x 2048 everywhere, adaptive); QSGS_ERR_INVALID for a bad shape. */
+ * the defaults: 256 threads; 2560 workgroups for growth, 2048 for prune and seeding;
+ * adaptive); QSGS_ERR_INVALID for a bad shape. */
 typedef struct {
   int32_t grow_block, grow_grid;
   int32_t prune_block, prune_grid;

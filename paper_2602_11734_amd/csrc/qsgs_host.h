@@ -280,7 +280,7 @@ inline SeedLayout seed_layout(const std::vector<Spec>& specs, bool with_cand = t
 // Launch shape of the item kernels (block = threads per workgroup, a multiple of 64 up
 // to 512; grid = workgroups, a multiple of 8) and the steps issued between host reads.
 struct Tuning {
-  uint32_t grow_block = kBlock, grow_grid = 2048;
+  uint32_t grow_block = kBlock, grow_grid = 2560;  // two rounds of resident sweep workgroups
   uint32_t prune_block = kBlock, prune_grid = 2048;
   uint32_t seed_block = kBlock, seed_grid = 2048;
   int32_t steps_per_sync = 0;  // 0: adaptive
