@@ -163,13 +163,15 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched vs plain realizations/s measurement")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served vs plain request-stream measurement")
     ap.add_argument("--serve-requests", type=int, default=300)
-    ap.add_argument("--serve-rate", type=float, default=150.0, help="arrivals per second")
+    ap.add_argument("--serve-rate", type=float, default=150.0,
+                    help="arrivals per second of the moderate-load run (an overload run at "
+                         "20x the rate follows)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy kernel over BYTES bytes three times "
                          "(the reference kernel for scaling HBM byte counters)")
@@ -290,7 +292,9 @@ def main():
     if not args.no_batch:
         out["detail"]["batched"] = batched_vs_plain(q, torch)
     if not args.no_serve:
-        out["detail"]["serving"] = served_vs_plain(args.serve_requests, args.serve_rate)
+        out["detail"]["serving"] = {
+            "moderate_load": served_vs_plain(args.serve_requests, args.serve_rate),
+            "overload": served_vs_plain(args.serve_requests, 20 * args.serve_rate)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cases[1], args.cpu_steps)
     print(json.dumps(out))
