@@ -141,6 +141,34 @@ def batched_vs_plain(q, torch):
             "speedup": t_plain / t_batch, "identical_outputs": same}
 
 
+def list_vs_full_field(q, torch, case):
+    """The paper's central comparison on this GPU: the list-indexed sweep (LIETS) against
+    the full-field form (every tile every step) on one 400^3 realization; outputs
+    compared byte for byte."""
+    out = {"workload": case.name}
+    grids = {}
+    for form, full in (("list_indexed", False), ("full_field", True)):
+        p = q.params_of(case, full_field=full)
+        b = q.alloc(case.dims, p)
+        q.qsgs_generate(case.dims, p, b.grid, b.ws, b.ws_bytes)  # warm-up
+        torch.cuda.synchronize()
+        q.qsgs_profile_enable(True)
+        q.qsgs_profile_read(reset=True)
+        t0 = time.perf_counter()
+        st, info = q.qsgs_generate(case.dims, p, b.grid, b.ws, b.ws_bytes)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = q.qsgs_profile_read(reset=True)
+        q.qsgs_profile_enable(False)
+        out[form] = {"generation_ms": wall * 1e3, "sweep_ms": prof["grow_ms"],
+                     "voxels_grown_per_s": (info.solid_count - info.n_seeds) / wall}
+        grids[form] = b.grid[:case.n].clone()
+        del b
+    out["sweep_speedup"] = out["full_field"]["sweep_ms"] / out["list_indexed"]["sweep_ms"]
+    out["identical_outputs"] = bool(torch.equal(grids["list_indexed"], grids["full_field"]))
+    return out
+
+
 def served_vs_plain(n_requests: int, rate: float):
     """Poisson request stream (mixed sizes): continuous batching against the plain
     one-at-a-time path on the same arrivals; p50/p99 latency and realizations/s."""
@@ -289,6 +317,9 @@ def main():
                    "n_over_t_per_realization": cases[0].n * 3 * args.steps / elapsed,
                    "realizations": per_case},
     }
+    out["detail"]["list_vs_full_field"] = [
+        list_vs_full_field(q, torch, cases[1]),
+        list_vs_full_field(q, torch, workloads.config4_singletons()[3])]
     if not args.no_batch:
         out["detail"]["batched"] = batched_vs_plain(q, torch)
     if not args.no_serve:

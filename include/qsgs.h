@@ -70,6 +70,12 @@ typedef struct {
   int32_t  spacing;       /* s >= 0: minimum pairwise L1 seed distance; s <= 1 = none       */
   int32_t  max_steps;     /* growth step cap; <= 0 selects 2^20                             */
   uint64_t key;           /* Philox key of the realization                                  */
+  int32_t  full_field;    /* whole-generation calls only: 0 = list-indexed sweep (LIETS,    */
+                          /* Alg. 3: only tiles that may hold the front are visited);        */
+                          /* 1 = full-field sweep (Alg. 2: every tile, every step).  Results  */
+                          /* are identical; the full-field form is the baseline for the      */
+                          /* list-indexed one.  Ignored by qsgs_seed / qsgs_grow_step.         */
+  int32_t  reserved;      /* must be 0                                                      */
 } qsgs_params;
 
 typedef struct {

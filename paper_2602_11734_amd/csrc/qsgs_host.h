@@ -119,6 +119,9 @@ inline qsgs_status check_params(const qsgs_params* p) {
   for (int c = 0; c < 3; ++c)
     if (!is_prob(p->g_ref[c])) return fail(QSGS_ERR_INVALID, "g_ref[%d] must be in [0, 1]", c);
   if (p->spacing < 0) return fail(QSGS_ERR_INVALID, "spacing must be >= 0");
+  if (p->full_field != 0 && p->full_field != 1)
+    return fail(QSGS_ERR_INVALID, "full_field must be 0 or 1");
+  if (p->reserved != 0) return fail(QSGS_ERR_INVALID, "reserved must be 0");
   return QSGS_OK;
 }
 
@@ -418,6 +421,7 @@ struct Engine {
     init_record(r, sp, p, grid, at<int32_t>(sweep, 0), at<int32_t>(sweep, lb),
                 2 * make_tiles(sp.g).n);
     reals[r].stamp = at<uint32_t>(sweep, 2 * lb);
+    reals[r].full = (uint32_t)p->full_field;
   }
 
   qsgs_status upload_header() {
@@ -581,6 +585,13 @@ struct Engine {
     QSGS_TRY(offsets(kItemsSeeds));
     hipLaunchKernelGGL(k_seed_tiles, dim3(tune.seed_grid), dim3(tune.seed_block), 0, s, args);
     QSGS_LAUNCHED("k_seed_tiles");
+    bool any_full = false;
+    for (const Real& R : reals) any_full = any_full || (R.phase == kPhaseSeed && R.full);
+    if (any_full) {
+      QSGS_TRY(offsets(kItemsVoxels));
+      hipLaunchKernelGGL(k_full_tiles, dim3(tune.seed_grid), dim3(tune.seed_block), 0, s, args);
+      QSGS_LAUNCHED("k_full_tiles");
+    }
     hipLaunchKernelGGL(k_sweep_prepare, dim3(1), dim3(1024), 0, s, args);
     QSGS_LAUNCHED("k_sweep_prepare");
     return QSGS_OK;

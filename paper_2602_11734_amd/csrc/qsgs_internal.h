@@ -113,6 +113,7 @@ struct Real {
   int32_t* f1;
   uint32_t* stamp;      // fused sweep: per tile, 1 + the last pass whose list holds it
   Tiles tl;
+  uint32_t full;        // fused sweep over every tile every step (full-field form)
   int32_t* cand;        // candidates, then the seed list (N entries)
   uint64_t* log;        // per-step log (3 words per step) or null
   uint32_t log_cap;
@@ -207,6 +208,7 @@ __global__ void k_prune(BatchArgs A);
 __global__ void k_step_end(BatchArgs A);
 __global__ void k_rollback(uint8_t* grid, uint32_t n);
 __global__ void k_seed_tiles(BatchArgs A);
+__global__ void k_full_tiles(BatchArgs A);
 __global__ void k_sweep_prepare(BatchArgs A);
 __global__ void k_sweep(BatchArgs A);  // dynamic LDS: sweep_lds_bytes(blockDim.x)
 size_t sweep_lds_bytes(uint32_t block);

@@ -404,11 +404,24 @@ __global__ __launch_bounds__(kMaxBlock) void k_collect_seeds(BatchArgs A) {
   }
 }
 
+// A full-field realization lists every tile, in both list buffers (written by the
+// items of its voxel range: tiles <= N).
+__global__ __launch_bounds__(kMaxBlock) void k_full_tiles(BatchArgs A) {
+  for_each_chunk(A, kItemsVoxels, [&](uint32_t r, uint32_t i) {
+    Real& R = A.reals[r];
+    if (!R.full || i >= R.tl.n) return;
+    R.f0[i] = (int32_t)i;
+    R.f1[i] = (int32_t)i;
+    if (i == 0) R.ctl.n_list = R.tl.n;
+  });
+}
+
 // The fused sweep's first list: the tiles holding a seed, each once (stamp 1 = listed
 // for pass 0), appended to list buffer 0 with one atomic per wavefront.
 __global__ __launch_bounds__(kMaxBlock) void k_seed_tiles(BatchArgs A) {
   for_each_chunk(A, kItemsSeeds, [&](uint32_t r, uint32_t i) {
     Real& R = A.reals[r];
+    if (R.full) return;  // (uniform per wavefront)
     bool fresh = false;
     uint32_t u = 0;
     if (i < R.ctl.n_seeds) {
@@ -1185,6 +1198,7 @@ void k_sweep(BatchArgs A) {
         const uint32_t nq = uniform(__shfl(incl, kTileRows - 1, kWave));
         kept_w += nq;
         if (!run || nq == 0) continue;
+        const bool full = R.full != 0;
         // 3. compact the front voxels into the queue (row i's prefix and mask are
         // broadcast from lane i)
         const uint32_t excl = incl - cnt;
@@ -1256,6 +1270,7 @@ void k_sweep(BatchArgs A) {
           }
         }
         grown_w += wave_sum(grown);
+        if (full) continue;  // the full-field form lists every tile anyway
         // 6. list the tiles that may hold F_{t+1} for the next pass, each once: this
         // tile (it has front voxels) and every tile that received a claim
         const uint32_t tmask = wave_or(tm) | 1u << 13;
@@ -1289,7 +1304,11 @@ void k_sweep(BatchArgs A) {
   }
   __syncthreads();
   if (beta < nwg && threadIdx.x == 0) {
-    Q.seg[P.wgoff[r] + r + k] = SegEntry{r, part_base, s_commit, 0u};
+    // the full-field form keeps every tile listed: each part of the identity list is full
+    const uint32_t tn = A.reals[r].tl.n, Gr = P.wgoff[r + 1] - P.wgoff[r];
+    const uint32_t fill =
+        A.reals[r].full ? (uint32_t)((uint64_t)tn * (k + 1) / Gr) - part_base : s_commit;
+    Q.seg[P.wgoff[r] + r + k] = SegEntry{r, part_base, fill, 0u};
     A.wgkept[beta] = s_kept;
     A.wggrown[beta] = s_grown;
     A.wgdraws[beta] = s_draws;

@@ -70,6 +70,20 @@ def test_invalid_params_rejected_before_launch(q, bad):
     assert q.qsgs_last_error()
 
 
+def test_sweep_form_flag_checked(q):
+    p = q.make_params(0.7, 0.01, (0.1, 0.05, 0.01), 3, 1, full_field=True)
+    assert q.qsgs_workspace_bytes((8, 8, 8), p) > 0
+    p.full_field = 2
+    assert q.qsgs_workspace_bytes((8, 8, 8), p) == 0
+    p.full_field = 0
+    p.reserved = 7
+    assert q.qsgs_workspace_bytes((8, 8, 8), p) == 0
+    info = q.qsgs_info()
+    st = q.load().qsgs_generate(ctypes.byref(q.make_dims((8, 8, 8))), ctypes.byref(p), 256,
+                                256, 1 << 20, ctypes.byref(info), None)
+    assert st == q.ERR_INVALID and "reserved" in q.qsgs_last_error()
+
+
 def test_invalid_dims_and_pointers(q):
     p = q.make_params(0.7, 0.01, (0.1, 0.05, 0.01), 3, 1)
     info = q.qsgs_info()

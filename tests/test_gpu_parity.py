@@ -74,6 +74,26 @@ def test_generate_matches_oracle(q, orc, case):
     assert np.array_equal(got, ref.grid)
 
 
+@pytest.mark.parametrize("case", SMALL[::3] + workloads.config1(),
+                         ids=[c.name for c in SMALL[::3] + workloads.config1()])
+def test_full_field_sweep_matches_oracle(q, orc, case):
+    """The full-field form (every tile swept every step, Alg. 2) reaches the same
+    result, logs and work counts as the list-indexed form and the oracle."""
+    import torch
+    say("GPU generate (full field)", case.name, case.dims, "key", case.key)
+    params = q.params_of(case, full_field=True)
+    grid, info, buf = q.generate(case.dims, params)
+    torch.cuda.synchronize()
+    lf, ln, lc = q.qsgs_read_step_log(buf.ws, buf.ws_bytes)
+    ld, lb = q.qsgs_read_step_work(buf.ws, buf.ws_bytes)
+    ref = run_oracle(orc, case)
+    assert info["status"] == ref.status and info["step"] == ref.steps
+    assert info["solid_count"] == ref.solid_count and info["front_size"] == ref.front_size
+    assert np.array_equal(lf, ref.log_front) and np.array_equal(ln, ref.log_new)
+    assert np.array_equal(ld, ref.log_draws) and np.array_equal(lb, ref.log_blocks)
+    assert np.array_equal(grid.cpu().numpy(), ref.grid)
+
+
 def test_generate_is_deterministic(q):
     import torch
     case = workloads.small_cases()[0]
@@ -235,7 +255,8 @@ def test_batch_matches_oracle(q, orc):
     equals the oracle's run of that realization alone."""
     import torch
     cases = workloads.small_cases() + workloads.config1()
-    params = [q.params_of(c) for c in cases]
+    # every third realization runs the full-field form: both forms share the launches
+    params = [q.params_of(c, full_field=(k % 3 == 1)) for k, c in enumerate(cases)]
     dims = [c.dims for c in cases]
     grids = [torch.empty(q.qsgs_grid_bytes(d), dtype=torch.uint8, device="cuda") for d in dims]
     wsb = q.qsgs_batch_workspace_bytes(dims, params)
