@@ -965,6 +965,78 @@ __device__ __forceinline__ uint32_t wave_prefix(uint32_t cnt, uint32_t* total) {
   return incl - cnt;
 }
 
+// Directions (26-bit masks) whose step leaves the voxel's tile on each side.
+constexpr uint32_t dir_mask_where(int field, int val) {
+  uint32_t m = 0;
+  for (int d = 0; d < 26; ++d)
+    if ((int)((pack_direction_field(field) >> (2 * d)) & 3u) == val) m |= 1u << d;
+  return m;
+}
+constexpr uint32_t kDxNeg = dir_mask_where(0, 0), kDxPos = dir_mask_where(0, 2);
+constexpr uint32_t kDyNeg = dir_mask_where(1, 0), kDyPos = dir_mask_where(1, 2);
+constexpr uint32_t kDzNeg = dir_mask_where(2, 0), kDzPos = dir_mask_where(2, 2);
+
+// The draw rule of grow_draws for the tile sweep, shaped for few instructions per rank:
+// a rank goes further only when its high half is at or below its threshold's; a
+// passing rank's claim atomic is issued at once and its old word checked after the
+// block (ranks that did not claim keep an all-ones word, which never counts); the
+// directions of passing ranks are returned in *passed (for the tiles they reach).
+// Returns the number of voxels this thread claimed first.
+// `lds_key` holds the key again for the rare tie path: read through a volatile LDS load,
+// the low-half block cannot be hoisted out of that path and computed for every block.
+__device__ __forceinline__ uint32_t sweep_draws(uint8_t* __restrict__ grid, uint32_t k0,
+                                                uint32_t k1, const uint32_t* lds_key,
+                                                const int32_t* doff, const uint32_t* dhi,
+                                                uint32_t a, uint32_t t, uint32_t voidm,
+                                                DrawThresholds th, uint32_t mark,
+                                                uint32_t* passed) {
+  const uint32_t lf = th.lo_face, le = th.lo_edge, lc = th.lo_corner;
+  uint32_t grown = 0, dirs = 0;
+  uint32_t m = voidm;
+  for (uint32_t blk = 0; m; ++blk) {
+    const U4 H = philox10(a, t, blk, kTagGrowHi, k0, k1);
+    uint32_t old[8], shift[8];
+    bool have_lo = false;
+    U4 L{0, 0, 0, 0};
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) {
+      old[sl] = 0xFFFFFFFFu;
+      shift[sl] = 0;
+      if (m) {
+        const int d = __builtin_ctz(m);
+        m &= m - 1u;
+        const uint32_t w = sl < 2 ? H.x : (sl < 4 ? H.y : (sl < 6 ? H.z : H.w));
+        const uint32_t h = (sl & 1) ? (w >> 16) : (w & 0xFFFFu);
+        const uint32_t hi = dhi[d];
+        if (h <= hi) {
+          bool pass = h < hi;
+          if (h == hi) {  // high halves tie (rare): decide on the low half
+            if (!have_lo) {
+              const uint32_t kl0 = *(const volatile uint32_t*)&lds_key[0];
+              const uint32_t kl1 = *(const volatile uint32_t*)&lds_key[1];
+              L = philox10(a, t, blk, kTagGrowLo, kl0, kl1);
+              have_lo = true;
+            }
+            const uint32_t wl = sl < 2 ? L.x : (sl < 4 ? L.y : (sl < 6 ? L.z : L.w));
+            const uint32_t l = (sl & 1) ? (wl >> 16) : (wl & 0xFFFFu);
+            pass = l < (((kCornerDirs >> d) & 1u) ? lc : (((kEdgeDirs >> d) & 1u) ? le : lf));
+          }
+          if (pass) {
+            const uint32_t q = (uint32_t)((int32_t)a + doff[d]);
+            shift[sl] = (q & 3u) * 8u;
+            old[sl] = atomicOr((uint32_t*)(grid + (q & ~3u)), mark << shift[sl]);
+            dirs |= 1u << d;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) grown += ((old[sl] >> shift[sl]) & 0xFFu) == kVoid;
+  }
+  *passed = dirs;
+  return grown;
+}
+
 // LDS image of one tile at the step's start.  Halo row h = hy + 6 hz (hy, hz in 0..5)
 // covers y = y0 - 1 + hy, z = z0 - 1 + hz; interior row i = jy + 4 jz is halo row
 // (jy + 1) + 6 (jz + 1).  Bit i of a row mask is voxel x0 + i.
@@ -1036,6 +1108,7 @@ void k_sweep(BatchArgs A) {
   __shared__ uint32_t s_tiles[kWave];
   __shared__ int32_t s_doff[26];
   __shared__ uint32_t s_dhi[26];
+  __shared__ uint32_t s_key[2];
   __shared__ uint32_t s_fill, s_commit, s_kept, s_grown, s_draws, s_blocks;
   const uint32_t G = gridDim.x;
   const uint32_t p = uniform(A.bctl->plan);
@@ -1073,6 +1146,10 @@ void k_sweep(BatchArgs A) {
     if (threadIdx.x < 26u) s_doff[threadIdx.x] = dir_offset(g, (int)threadIdx.x);  // read after
                                                                                  // the first barrier
     const uint32_t k0 = uniform(R.k0), k1 = uniform(R.k1);
+    if (threadIdx.x == 0) {  // read after the first barrier
+      s_key[0] = k0;
+      s_key[1] = k1;
+    }
     const uint32_t sb = uniform(P.rseg[r]), se = uniform(P.rseg[r + 1]);
     const uint32_t e0 = uniform(P.segchunk[sb]);
     const uint64_t ne = uniform(P.segchunk[se]) - e0;
@@ -1255,12 +1332,17 @@ void k_sweep(BatchArgs A) {
           blocks_l += (nv + 7u) >> 3;
           const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
                              (uint32_t)(z0 + jz) * g.nxy;
-          uint32_t claims = grow_draws(grid, k0, k1, DirOffsetTable{s_doff},
-                                       DirThresholdTable{s_dhi}, a, t, vm, 0u, th, (uint8_t)mark);
-          grown += (uint32_t)__builtin_popcount(claims);
-          while (claims) {
-            const int d = __builtin_ctz(claims);
-            claims &= claims - 1u;
+          uint32_t passed = 0;
+          grown += sweep_draws(grid, k0, k1, s_key, s_doff, s_dhi, a, t, vm, th, mark, &passed);
+          // passing ranks whose target leaves this tile list the target's tile (this
+          // tile is listed anyway); first claim or not, the target was void
+          const uint32_t leave = (xl == 0 ? kDxNeg : 0u) | (xl == kTileX - 1 ? kDxPos : 0u) |
+                                 (jy == 0 ? kDyNeg : 0u) | (jy == kTileY - 1 ? kDyPos : 0u) |
+                                 (jz == 0 ? kDzNeg : 0u) | (jz == kTileZ - 1 ? kDzPos : 0u);
+          uint32_t out = passed & leave;
+          while (out) {
+            const int d = __builtin_ctz(out);
+            out &= out - 1u;
             const int xn = xl + dir_field(kDirDX, d) - 1, yn = jy + dir_field(kDirDY, d) - 1,
                       zn = jz + dir_field(kDirDZ, d) - 1;
             const int ox = xn < 0 ? 0 : (xn >= kTileX ? 2 : 1);
