@@ -1041,8 +1041,11 @@ __device__ __forceinline__ uint32_t sweep_draws(uint8_t* __restrict__ grid, uint
 // covers y = y0 - 1 + hy, z = z0 - 1 + hz; interior row i = jy + 4 jz is halo row
 // (jy + 1) + 6 (jz + 1).  Bit i of a row mask is voxel x0 + i.
 struct TileImage {
-  uint64_t V[kHaloRows];   // in-domain and void at the step's start (0 or the mark)
-  uint64_t L, R;           // bit h: voxel x0 - 1 (L) / x0 + 64 (R) of halo row h void
+  // Halo row h as a 66-bit window of "in-domain and void at the step's start" (byte 0
+  // or the mark): bit i of lo = voxel x0 - 1 + i (i < 64), bits 1, 2 of hi = voxels
+  // x0 + 63, x0 + 64 (hi is kept shifted left by one).
+  uint64_t lo[kHaloRows];
+  uint8_t hi[kHaloRows];
   uint64_t S[kTileRows];   // solid (interior rows)
   uint32_t W[kTileVoxels];   // per queued front voxel: void mask (direction order) | x << 26
   uint16_t qo[kTileVoxels];  // the queue (interior row << 6 | x - x0), then its order by
@@ -1051,29 +1054,22 @@ struct TileImage {
   uint32_t hist[32];         // void-count histogram, then bucket cursors
 };
 
-// The 26-bit void mask (direction order) of front voxel (xl, jy, jz) of the image.
+// The 26-bit void mask (direction order) of front voxel (xl, jy, jz) of the image: the
+// three bits x - 1, x, x + 1 of each of the nine neighbouring rows are bits xl..xl + 2
+// of the row's window, concatenated in row order with the centre bit dropped.
 __device__ __forceinline__ uint32_t tile_void_mask(const TileImage& T, int xl, int jy, int jz) {
-  uint32_t vm = 0;
-  int d = 0;
+  const uint32_t hs = 63u - (uint32_t)xl;
+  uint32_t acc = 0;
 #pragma unroll
   for (int kz = 0; kz < 3; ++kz)
 #pragma unroll
     for (int ky = 0; ky < 3; ++ky) {
       const int h = (jy + ky) + (kTileY + 2) * (jz + kz);
-      const uint64_t V = T.V[h];
-      const uint32_t left = xl == 0 ? (uint32_t)(T.L >> h) & 1u : (uint32_t)(V >> (xl - 1)) & 1u;
-      const uint32_t right =
-          xl == kTileX - 1 ? (uint32_t)(T.R >> h) & 1u : (uint32_t)(V >> (xl + 1)) & 1u;
-      if (kz == 1 && ky == 1) {
-        vm |= (left | right << 1) << d;
-        d += 2;
-      } else {
-        const uint32_t mid = (uint32_t)(V >> xl) & 1u;
-        vm |= (left | mid << 1 | right << 2) << d;
-        d += 3;
-      }
+      const uint32_t w =
+          (uint32_t)(T.lo[h] >> xl) | (uint32_t)((uint64_t)T.hi[h] << hs);
+      acc |= (w & 7u) << (3 * (ky + 3 * kz));
     }
-  return vm;
+  return (acc & 0x1FFFu) | ((acc >> 1) & 0x3FFE000u);
 }
 
 __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
@@ -1202,6 +1198,7 @@ void k_sweep(BatchArgs A) {
         // flight at a time (off-domain lanes read byte 0 and are masked); fold the
         // previous step's marks.  The halo columns x0 - 1 and x0 + 64 of all 36 rows are
         // read by 36 lanes at once.
+        uint64_t lm, rm;  // bit h: voxel x0 - 1 / x0 + 64 of halo row h void (uniform)
         {
           const int h = (int)lane;
           const int32_t y = y0 - 1 + h % (kTileY + 2), z = z0 - 1 + h / (kTileY + 2);
@@ -1212,10 +1209,8 @@ void k_sweep(BatchArgs A) {
           const uint32_t br = inr ? grid[row + x0 + kTileX] : 0xFFu;
           const uint64_t Lm = __ballot(bl == kVoid || bl == mark);
           const uint64_t Rm = __ballot(br == kVoid || br == mark);
-          if (lane == 0) {
-            T.L = Lm;
-            T.R = Rm;
-          }
+          lm = Lm;
+          rm = Rm;
         }
         for (int hz = 0; hz < kTileZ + 2; ++hz) {
           const int32_t z = z0 - 1 + hz;
@@ -1246,7 +1241,10 @@ void k_sweep(BatchArgs A) {
               }
               if (lane == 0) T.S[(hy - 1) + kTileY * (hz - 1)] = Sm;
             }
-            if (lane == 0) T.V[h] = V;
+            if (lane == 0) {
+              T.lo[h] = V << 1 | ((lm >> h) & 1ull);
+              T.hi[h] = (uint8_t)(((uint32_t)(V >> 63) | (uint32_t)((rm >> h) & 1ull) << 1) << 1);
+            }
           }
         }
         wave_sync();
@@ -1260,8 +1258,9 @@ void k_sweep(BatchArgs A) {
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky) {
               const int h = (jy + ky) + (kTileY + 2) * (jz + kz);
-              const uint64_t V = T.V[h];
-              D |= V | (V << 1) | (V >> 1) | ((T.L >> h) & 1ull) | (((T.R >> h) & 1ull) << 63);
+              const uint64_t lo = T.lo[h], hi = (uint64_t)(T.hi[h] >> 1);
+              // x - 1 neighbours: lo; x: V; x + 1 neighbours: window shifted down by two
+              D |= lo | (lo >> 1) | (hi << 63) | (lo >> 2) | (hi << 62);
             }
           F = T.S[lane] & D;
         }
