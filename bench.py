@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the list-indexed vs full-field comparison")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched vs plain realizations/s measurement")
     ap.add_argument("--no-serve", action="store_true",
@@ -317,9 +319,10 @@ def main():
                    "n_over_t_per_realization": cases[0].n * 3 * args.steps / elapsed,
                    "realizations": per_case},
     }
-    out["detail"]["list_vs_full_field"] = [
-        list_vs_full_field(q, torch, cases[1]),
-        list_vs_full_field(q, torch, workloads.config4_singletons()[3])]
+    if not args.no_compare:
+        out["detail"]["list_vs_full_field"] = [
+            list_vs_full_field(q, torch, cases[1]),
+            list_vs_full_field(q, torch, workloads.config4_singletons()[3])]
     if not args.no_batch:
         out["detail"]["batched"] = batched_vs_plain(q, torch)
     if not args.no_serve:

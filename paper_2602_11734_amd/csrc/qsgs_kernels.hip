@@ -1420,17 +1420,47 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
   if (threadIdx.x == 0) A.bctl->running = 0;
   __syncthreads();
   const uint32_t nwg = P.wgoff[A.count];
-  for (uint32_t w = threadIdx.x; w < nwg; w += blockDim.x) {
-    uint32_t a = 0, b = A.count;  // realization of logical workgroup w
-    while (b - a > 1) {
-      const uint32_t mid = (a + b) >> 1;
-      if (P.wgoff[mid] <= w) a = mid; else b = mid;
+  // workgroups are ordered by realization: a wavefront whose 64 entries belong to one
+  // realization sums them first and adds once
+  for (uint32_t base = threadIdx.x & ~(uint32_t)(kWave - 1); base < nwg; base += blockDim.x) {
+    const uint32_t w = base + lane_id();
+    const bool in = w < nwg;
+    uint32_t a = 0;
+    uint32_t kept = 0, grown = 0, draws = 0, blocks = 0, out = 0;
+    if (in) {
+      uint32_t lo = 0, hi = A.count;  // realization of logical workgroup w
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (P.wgoff[mid] <= w) lo = mid; else hi = mid;
+      }
+      a = lo;
+      kept = A.wgkept[w];
+      grown = A.wggrown[w];
+      draws = A.wgdraws[w];
+      blocks = A.wgblocks[w];
+      out = Q.seg[w + a].fill;
     }
-    atomicAdd(&acc_kept[a], A.wgkept[w]);
-    atomicAdd(&acc_grown[a], A.wggrown[w]);
-    atomicAdd(&acc_draws[a], (unsigned long long)A.wgdraws[w]);
-    atomicAdd(&acc_blocks[a], (unsigned long long)A.wgblocks[w]);
-    atomicAdd(&acc_out[a], Q.seg[w + a].fill);
+    const uint32_t a0 = __shfl(a, 0, kWave);
+    if (__ballot(in && a != a0) == 0) {  // one realization: per-wave sums
+      kept = wave_sum(kept);
+      grown = wave_sum(grown);
+      draws = wave_sum(draws);
+      blocks = wave_sum(blocks);
+      out = wave_sum(out);
+      if (lane_id() == 0) {
+        atomicAdd(&acc_kept[a0], kept);
+        atomicAdd(&acc_grown[a0], grown);
+        atomicAdd(&acc_draws[a0], (unsigned long long)draws);
+        atomicAdd(&acc_blocks[a0], (unsigned long long)blocks);
+        atomicAdd(&acc_out[a0], out);
+      }
+    } else if (in) {
+      atomicAdd(&acc_kept[a], kept);
+      atomicAdd(&acc_grown[a], grown);
+      atomicAdd(&acc_draws[a], (unsigned long long)draws);
+      atomicAdd(&acc_blocks[a], (unsigned long long)blocks);
+      atomicAdd(&acc_out[a], out);
+    }
   }
   __syncthreads();
   for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) {
