@@ -503,6 +503,8 @@ struct Engine {
         for (uint32_t k = 0; k < kRoundsPerCheck; ++k, ++round) {
           hipLaunchKernelGGL(k_luby_round, sg, sb, 0, s, args, round);
           QSGS_LAUNCHED("k_luby_round");
+          hipLaunchKernelGGL(k_luby_kill, sg, sb, 0, s, args);
+          QSGS_LAUNCHED("k_luby_kill");
         }
         uint32_t live = 0;
         QSGS_HIP(hipMemcpyAsync(&live, args.live + round - 1, sizeof live, hipMemcpyDeviceToHost,

@@ -62,8 +62,9 @@ constexpr uint32_t kLogWords = 5;
 constexpr int32_t kStatusDone = 1, kStatusExhausted = 2, kStatusMaxSteps = 3,
                   kStatusOverflow = 100;
 
-// Seed candidate states during the spacing rounds.
-constexpr uint8_t kLive = 0, kAccepted = 1, kDead = 2;
+// Seed candidate states during the spacing rounds (kAcceptedNew: accepted in the
+// current round, its conflicting candidates not yet marked dead).
+constexpr uint8_t kLive = 0, kAccepted = 1, kDead = 2, kAcceptedNew = 3;
 
 constexpr uint32_t kMaxSweepGrid = 8192;  // workgroups of a fused sweep launch (at most)
 constexpr uint32_t kMaxBatch = 4096;      // realizations per batch / server slots
@@ -199,6 +200,7 @@ __global__ void k_seed_draw(BatchArgs A);
 __global__ void k_bucket_count(BatchArgs A);
 __global__ void k_bucket_scatter(BatchArgs A, uint32_t total_buckets);
 __global__ void k_luby_round(BatchArgs A, uint32_t round);
+__global__ void k_luby_kill(BatchArgs A);
 __global__ void k_collect_seeds(BatchArgs A);
 __global__ void k_front_init(BatchArgs A);
 __global__ void k_loop_init(BatchArgs A);

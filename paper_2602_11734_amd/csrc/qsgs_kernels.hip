@@ -317,11 +317,60 @@ __global__ __launch_bounds__(kMaxBlock) void k_bucket_scatter(BatchArgs A, uint3
   });
 }
 
-// One priority round over all bucket-sorted candidates.  A live candidate that sees
-// an accepted conflicting candidate dies; one whose key (priority, v) is below every
-// live conflicting candidate's key is accepted.  Statuses only move forward, and a
-// stale read can only delay a decision, never change it, so in-place updates
-// reproduce the greedy acceptance in ascending key order.
+// Conflicting candidates of candidate i (L1 distance 1..radius) in the 27 buckets
+// around it; buckets whose nearest point lies beyond the radius are skipped.  visit(j, w)
+// returns false to stop the scan early.
+template <typename Visit>
+__device__ __forceinline__ void for_each_conflict(const BatchArgs& A, const Real& R, uint32_t i,
+                                                  uint32_t v, Visit&& visit) {
+  const Buckets bk = R.bk;
+  uint32_t x, y, z;
+  coords_of(R.g, v, x, y, z);
+  const int32_t bx = (int32_t)bk.edge.div(x), by = (int32_t)bk.edge.div(y),
+                bz = (int32_t)bk.edge.div(z);
+  // L1 distance from the candidate to bucket c along one axis (bucket c covers
+  // [c E, (c + 1) E - 1])
+  const int32_t E = (int32_t)bk.edge.d;
+  auto gap = [E](int32_t c, int32_t b0, int32_t p) -> int32_t {
+    return c < b0 ? p - ((c + 1) * E - 1) : (c > b0 ? c * E - p : 0);
+  };
+  for (int32_t cz = max(bz - 1, 0); cz <= min(bz + 1, (int32_t)bk.nbz - 1); ++cz)
+    for (int32_t cy = max(by - 1, 0); cy <= min(by + 1, (int32_t)bk.nby - 1); ++cy) {
+      const int32_t gzy = gap(cz, bz, (int32_t)z) + gap(cy, by, (int32_t)y);
+      if (gzy > bk.radius) continue;
+      for (int32_t cx = max(bx - 1, 0); cx <= min(bx + 1, (int32_t)bk.nbx - 1); ++cx) {
+        if (gzy + gap(cx, bx, (int32_t)x) > bk.radius) continue;
+        const uint32_t b = R.boff + (uint32_t)cx + bk.nbx * ((uint32_t)cy + bk.nby * (uint32_t)cz);
+        const uint32_t e = A.counts[b + 1];
+        // eight candidates' loads in flight at a time (the scan is latency-bound)
+        for (uint32_t j0 = A.counts[b]; j0 < e; j0 += 8) {
+          uint32_t wv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) wv[u] = j0 + u < e ? (uint32_t)A.sorted_v[j0 + u] : 0u;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const uint32_t j = j0 + u;
+            if (j >= e || j == i) continue;
+            const uint32_t w = wv[u];
+            uint32_t wx, wy, wz;
+            coords_of(R.g, w, wx, wy, wz);
+            const int32_t dist = abs((int32_t)wx - (int32_t)x) + abs((int32_t)wy - (int32_t)y) +
+                                 abs((int32_t)wz - (int32_t)z);
+            if (dist > bk.radius) continue;
+            if (!visit(j, w)) return;
+          }
+        }
+      }
+    }
+}
+
+// One priority round over all bucket-sorted candidates, in two launches.  Decide: a
+// live candidate whose key (priority, v) is below the key of every conflicting
+// candidate that is still live (or accepted in this round) is accepted; the scan stops
+// at the first conflicting candidate with a smaller key.  Kill: every candidate
+// accepted in this round marks its live conflicting candidates dead.  A candidate is
+// accepted exactly when no conflicting candidate with a smaller key is still in play,
+// so the rounds reproduce the greedy acceptance in ascending key order.
 __global__ __launch_bounds__(kMaxBlock) void k_luby_round(BatchArgs A, uint32_t round) {
   const uint32_t n = A.bctl->n_sorted;
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
@@ -329,48 +378,39 @@ __global__ __launch_bounds__(kMaxBlock) void k_luby_round(BatchArgs A, uint32_t 
     bool still_live = false;
     if (i < n && A.status[i] == kLive) {
       const Real& R = A.reals[A.sorted_r[i]];
-      const Buckets bk = R.bk;
       const uint32_t v = (uint32_t)A.sorted_v[i];
       const uint64_t p = A.sorted_prio[i];
-      uint32_t x, y, z;
-      coords_of(R.g, v, x, y, z);
-      const int32_t bx = (int32_t)bk.edge.div(x), by = (int32_t)bk.edge.div(y),
-                    bz = (int32_t)bk.edge.div(z);
-      bool killed = false, minimal = true;
-      for (int32_t cz = max(bz - 1, 0); cz <= min(bz + 1, (int32_t)bk.nbz - 1) && !killed; ++cz)
-        for (int32_t cy = max(by - 1, 0); cy <= min(by + 1, (int32_t)bk.nby - 1) && !killed; ++cy)
-          for (int32_t cx = max(bx - 1, 0); cx <= min(bx + 1, (int32_t)bk.nbx - 1) && !killed;
-               ++cx) {
-            const uint32_t b =
-                R.boff + (uint32_t)cx + bk.nbx * ((uint32_t)cy + bk.nby * (uint32_t)cz);
-            const uint32_t e = A.counts[b + 1];
-            for (uint32_t j = A.counts[b]; j < e; ++j) {
-              if (j == i) continue;
-              const uint32_t w = (uint32_t)A.sorted_v[j];
-              uint32_t wx, wy, wz;
-              coords_of(R.g, w, wx, wy, wz);
-              const int32_t dist = abs((int32_t)wx - (int32_t)x) + abs((int32_t)wy - (int32_t)y) +
-                                   abs((int32_t)wz - (int32_t)z);
-              if (dist > bk.radius) continue;
-              const uint8_t st = A.status[j];
-              if (st == kAccepted) {
-                killed = true;
-                break;
-              }
-              if (st == kLive) {
-                const uint64_t q = A.sorted_prio[j];
-                if (q < p || (q == p && w < v)) minimal = false;
-              }
-            }
+      bool minimal = true;
+      for_each_conflict(A, R, i, v, [&](uint32_t j, uint32_t w) {
+        const uint8_t st = A.status[j];
+        if (st == kLive || st == kAcceptedNew) {
+          const uint64_t q = A.sorted_prio[j];
+          if (q < p || (q == p && w < v)) {
+            minimal = false;
+            return false;
           }
-      if (killed)
-        A.status[i] = kDead;
-      else if (minimal)
-        A.status[i] = kAccepted;
+        }
+        return true;
+      });
+      if (minimal)
+        A.status[i] = kAcceptedNew;
       else
         still_live = true;
     }
     wave_append_flag(still_live, &A.live[round]);
+  }
+}
+
+__global__ __launch_bounds__(kMaxBlock) void k_luby_kill(BatchArgs A) {
+  const uint32_t n = A.bctl->n_sorted;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (A.status[i] != kAcceptedNew) continue;
+    const Real& R = A.reals[A.sorted_r[i]];
+    for_each_conflict(A, R, i, (uint32_t)A.sorted_v[i], [&](uint32_t j, uint32_t) {
+      if (A.status[j] == kLive) A.status[j] = kDead;
+      return true;
+    });
+    A.status[i] = kAccepted;
   }
 }
 
