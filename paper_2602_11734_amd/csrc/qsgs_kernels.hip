@@ -1354,9 +1354,11 @@ void k_sweep(BatchArgs A) {
           if (lane < 32u) T.hist[lane] = hin - hc;
         }
         wave_sync();
-        // (the queue has been read: its slots now take the order)
+        // (the queue has been read: its slots now take the order, heaviest first, so that
+        // a tile's last, partial round holds the lightest voxels)
         for (uint32_t qi = lane; qi < nq; qi += kWave)
-          T.qo[atomicAdd(&T.hist[__builtin_popcount(T.W[qi] & 0x3FFFFFFu)], 1u)] = (uint16_t)qi;
+          T.qo[nq - 1u - atomicAdd(&T.hist[__builtin_popcount(T.W[qi] & 0x3FFFFFFu)], 1u)] =
+              (uint16_t)qi;
         wave_sync();
         // 5. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1))
         uint32_t tm = 0, grown = 0;
