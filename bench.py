@@ -169,6 +169,51 @@ def list_vs_full_field(q, torch, case):
     return out
 
 
+def voxel_list_step_api(q, torch, case):
+    """The paper's literal list-indexed loop through the step API: F_t kept as a voxel
+    list, one qsgs_grow_step (grow, then prune of F_t + New_t) per step, the host reading
+    the loop state after every step.  Compared with qsgs_generate's tile-indexed sweep on
+    the same realization; outputs compared byte for byte."""
+    p = q.params_of(case)
+    n = case.n
+    grid = torch.empty(q.qsgs_grid_bytes(case.dims), dtype=torch.uint8, device="cuda")
+    fa = torch.empty(n, dtype=torch.int32, device="cuda")
+    fb = torch.empty(n, dtype=torch.int32, device="cuda")
+    wsb = q.qsgs_workspace_bytes(case.dims, p)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    swsb = q.qsgs_step_workspace_bytes()
+    sws = torch.empty(swsb, dtype=torch.uint8, device="cuda")
+
+    def run():
+        st, info = q.qsgs_seed(case.dims, p, grid, fa, n, ws, wsb)
+        bufs = (fa, fb)
+        k = 0
+        while st == 0:
+            st, info = q.qsgs_grow_step(case.dims, p, grid, bufs[k], bufs[k ^ 1], n, sws, swsb,
+                                        info)
+            k ^= 1
+        return info
+
+    run()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    steps_grid = grid[:n].clone()
+    b = q.alloc(case.dims, p)
+    q.qsgs_generate(case.dims, p, b.grid, b.ws, b.ws_bytes)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q.qsgs_generate(case.dims, p, b.grid, b.ws, b.ws_bytes)
+    torch.cuda.synchronize()
+    wall_gen = time.perf_counter() - t0
+    return {"workload": case.name, "steps": info.step,
+            "voxel_list_ms": wall * 1e3, "tile_sweep_ms": wall_gen * 1e3,
+            "speedup": wall / wall_gen,
+            "identical_outputs": bool(torch.equal(steps_grid, b.grid[:n]))}
+
+
 def served_vs_plain(n_requests: int, rate: float):
     """Poisson request stream (mixed sizes): continuous batching against the plain
     one-at-a-time path on the same arrivals; p50/p99 latency and realizations/s."""
@@ -320,6 +365,7 @@ def main():
                    "realizations": per_case},
     }
     if not args.no_compare:
+        out["detail"]["voxel_list_vs_tiles"] = voxel_list_step_api(q, torch, cases[1])
         out["detail"]["list_vs_full_field"] = [
             list_vs_full_field(q, torch, cases[1]),
             list_vs_full_field(q, torch, workloads.config4_singletons()[3])]
