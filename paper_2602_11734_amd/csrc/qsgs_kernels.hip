@@ -317,100 +317,113 @@ __global__ __launch_bounds__(kMaxBlock) void k_bucket_scatter(BatchArgs A, uint3
   });
 }
 
-// Conflicting candidates of candidate i (L1 distance 1..radius) in the 27 buckets
-// around it; buckets whose nearest point lies beyond the radius are skipped.  visit(j, w)
-// returns false to stop the scan early.
+// Conflicting candidates of candidate i (L1 distance 1..radius) in neighbouring bucket
+// k (0..26: offsets (k % 3 - 1, k / 3 % 3 - 1, k / 9 - 1)) of i's bucket; a bucket outside
+// the grid or whose nearest point lies beyond the radius is skipped.  visit(j, w) returns
+// false to stop early.  Eight candidates' loads are in flight at a time.
 template <typename Visit>
-__device__ __forceinline__ void for_each_conflict(const BatchArgs& A, const Real& R, uint32_t i,
-                                                  uint32_t v, Visit&& visit) {
+__device__ __forceinline__ void scan_bucket(const BatchArgs& A, const Real& R, uint32_t i,
+                                            uint32_t v, uint32_t k, Visit&& visit) {
   const Buckets bk = R.bk;
   uint32_t x, y, z;
   coords_of(R.g, v, x, y, z);
   const int32_t bx = (int32_t)bk.edge.div(x), by = (int32_t)bk.edge.div(y),
                 bz = (int32_t)bk.edge.div(z);
+  const int32_t cx = bx + (int32_t)(k % 3) - 1, cy = by + (int32_t)(k / 3 % 3) - 1,
+                cz = bz + (int32_t)(k / 9) - 1;
+  if (cx < 0 || cy < 0 || cz < 0 || cx >= (int32_t)bk.nbx || cy >= (int32_t)bk.nby ||
+      cz >= (int32_t)bk.nbz)
+    return;
   // L1 distance from the candidate to bucket c along one axis (bucket c covers
   // [c E, (c + 1) E - 1])
   const int32_t E = (int32_t)bk.edge.d;
   auto gap = [E](int32_t c, int32_t b0, int32_t p) -> int32_t {
     return c < b0 ? p - ((c + 1) * E - 1) : (c > b0 ? c * E - p : 0);
   };
-  for (int32_t cz = max(bz - 1, 0); cz <= min(bz + 1, (int32_t)bk.nbz - 1); ++cz)
-    for (int32_t cy = max(by - 1, 0); cy <= min(by + 1, (int32_t)bk.nby - 1); ++cy) {
-      const int32_t gzy = gap(cz, bz, (int32_t)z) + gap(cy, by, (int32_t)y);
-      if (gzy > bk.radius) continue;
-      for (int32_t cx = max(bx - 1, 0); cx <= min(bx + 1, (int32_t)bk.nbx - 1); ++cx) {
-        if (gzy + gap(cx, bx, (int32_t)x) > bk.radius) continue;
-        const uint32_t b = R.boff + (uint32_t)cx + bk.nbx * ((uint32_t)cy + bk.nby * (uint32_t)cz);
-        const uint32_t e = A.counts[b + 1];
-        // eight candidates' loads in flight at a time (the scan is latency-bound)
-        for (uint32_t j0 = A.counts[b]; j0 < e; j0 += 8) {
-          uint32_t wv[8];
+  if (gap(cx, bx, (int32_t)x) + gap(cy, by, (int32_t)y) + gap(cz, bz, (int32_t)z) > bk.radius)
+    return;
+  const uint32_t b = R.boff + (uint32_t)cx + bk.nbx * ((uint32_t)cy + bk.nby * (uint32_t)cz);
+  const uint32_t e = A.counts[b + 1];
+  for (uint32_t j0 = A.counts[b]; j0 < e; j0 += 8) {
+    uint32_t wv[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) wv[u] = j0 + u < e ? (uint32_t)A.sorted_v[j0 + u] : 0u;
+    for (int u = 0; u < 8; ++u) wv[u] = j0 + u < e ? (uint32_t)A.sorted_v[j0 + u] : 0u;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const uint32_t j = j0 + u;
-            if (j >= e || j == i) continue;
-            const uint32_t w = wv[u];
-            uint32_t wx, wy, wz;
-            coords_of(R.g, w, wx, wy, wz);
-            const int32_t dist = abs((int32_t)wx - (int32_t)x) + abs((int32_t)wy - (int32_t)y) +
-                                 abs((int32_t)wz - (int32_t)z);
-            if (dist > bk.radius) continue;
-            if (!visit(j, w)) return;
-          }
-        }
-      }
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t j = j0 + u;
+      if (j >= e || j == i) continue;
+      const uint32_t w = wv[u];
+      uint32_t wx, wy, wz;
+      coords_of(R.g, w, wx, wy, wz);
+      const int32_t dist = abs((int32_t)wx - (int32_t)x) + abs((int32_t)wy - (int32_t)y) +
+                           abs((int32_t)wz - (int32_t)z);
+      if (dist > bk.radius) continue;
+      if (!visit(j, w)) return;
     }
+  }
 }
 
 // One priority round over all bucket-sorted candidates, in two launches.  Decide: a
 // live candidate whose key (priority, v) is below the key of every conflicting
-// candidate that is still live (or accepted in this round) is accepted; the scan stops
-// at the first conflicting candidate with a smaller key.  Kill: every candidate
-// accepted in this round marks its live conflicting candidates dead.  A candidate is
-// accepted exactly when no conflicting candidate with a smaller key is still in play,
-// so the rounds reproduce the greedy acceptance in ascending key order.
+// candidate that is still live (or accepted in this round) is accepted.  Kill: every
+// candidate accepted in this round marks its live conflicting candidates dead.  A
+// candidate is accepted exactly when no conflicting candidate with a smaller key is
+// still in play, so the rounds reproduce the greedy acceptance in ascending key order.
+// Each candidate takes half a wavefront: lane k < 27 of the half scans neighbouring
+// bucket k (a lane stops at its first smaller key), and a ballot combines the lanes.
+// Any candidate left live sets the round's flag (the host stops when it stays 0).
 __global__ __launch_bounds__(kMaxBlock) void k_luby_round(BatchArgs A, uint32_t round) {
   const uint32_t n = A.bctl->n_sorted;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-    const uint32_t i = base + threadIdx.x;
-    bool still_live = false;
-    if (i < n && A.status[i] == kLive) {
+  const uint32_t lane = lane_id(), half = lane >> 5, k = lane & 31u;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
+  for (uint32_t base = 2 * wave; base < n; base += 2 * nwaves) {
+    const uint32_t i = base + half;
+    const bool live = i < n && A.status[i] == kLive;
+    bool smaller = false;
+    if (live && k < 27u) {
       const Real& R = A.reals[A.sorted_r[i]];
       const uint32_t v = (uint32_t)A.sorted_v[i];
       const uint64_t p = A.sorted_prio[i];
-      bool minimal = true;
-      for_each_conflict(A, R, i, v, [&](uint32_t j, uint32_t w) {
+      scan_bucket(A, R, i, v, k, [&](uint32_t j, uint32_t w) {
         const uint8_t st = A.status[j];
         if (st == kLive || st == kAcceptedNew) {
           const uint64_t q = A.sorted_prio[j];
           if (q < p || (q == p && w < v)) {
-            minimal = false;
+            smaller = true;
             return false;
           }
         }
         return true;
       });
-      if (minimal)
-        A.status[i] = kAcceptedNew;
-      else
-        still_live = true;
     }
-    wave_append_flag(still_live, &A.live[round]);
+    const uint64_t bal = __ballot(smaller);
+    const bool beaten = ((bal >> (32u * half)) & 0xFFFFFFFFull) != 0;
+    if (live && k == 0) {
+      if (beaten)
+        A.live[round] = 1u;
+      else
+        A.status[i] = kAcceptedNew;
+    }
   }
 }
 
 __global__ __launch_bounds__(kMaxBlock) void k_luby_kill(BatchArgs A) {
   const uint32_t n = A.bctl->n_sorted;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (A.status[i] != kAcceptedNew) continue;
-    const Real& R = A.reals[A.sorted_r[i]];
-    for_each_conflict(A, R, i, (uint32_t)A.sorted_v[i], [&](uint32_t j, uint32_t) {
-      if (A.status[j] == kLive) A.status[j] = kDead;
-      return true;
-    });
-    A.status[i] = kAccepted;
+  const uint32_t lane = lane_id(), half = lane >> 5, k = lane & 31u;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const uint32_t nwaves = gridDim.x * blockDim.x / kWave;
+  for (uint32_t base = 2 * wave; base < n; base += 2 * nwaves) {
+    const uint32_t i = base + half;
+    const bool fresh = i < n && A.status[i] == kAcceptedNew;
+    if (fresh && k < 27u) {
+      const Real& R = A.reals[A.sorted_r[i]];
+      scan_bucket(A, R, i, (uint32_t)A.sorted_v[i], k, [&](uint32_t j, uint32_t) {
+        if (A.status[j] == kLive) A.status[j] = kDead;
+        return true;
+      });
+    }
+    if (fresh && k == 0) A.status[i] = kAccepted;
   }
 }
 
