@@ -1029,7 +1029,8 @@ constexpr uint32_t kDxNeg = dir_mask_where(0, 0), kDxPos = dir_mask_where(0, 2);
 constexpr uint32_t kDyNeg = dir_mask_where(1, 0), kDyPos = dir_mask_where(1, 2);
 constexpr uint32_t kDzNeg = dir_mask_where(2, 0), kDzPos = dir_mask_where(2, 2);
 
-// The draw rule of grow_draws for the tile sweep, shaped for few instructions per rank:
+// The draw rule of grow_draws for the tile sweep, for one block `blk` of a voxel whose
+// void mask has had the ranks of its earlier blocks removed (m: ranks 8 blk onward):
 // a rank goes further only when its high half is at or below its threshold's; a
 // passing rank's claim atomic is issued at once and its old word checked after the
 // block (ranks that did not claim keep an all-ones word, which never counts); the
@@ -1037,58 +1038,69 @@ constexpr uint32_t kDzNeg = dir_mask_where(2, 0), kDzPos = dir_mask_where(2, 2);
 // Returns the number of voxels this thread claimed first.
 // `lds_key` holds the key again for the rare tie path: read through a volatile LDS load,
 // the low-half block cannot be hoisted out of that path and computed for every block.
-__device__ __forceinline__ uint32_t sweep_draws(uint8_t* __restrict__ grid, uint32_t k0,
+__device__ __forceinline__ uint32_t sweep_block(uint8_t* __restrict__ grid, uint32_t k0,
                                                 uint32_t k1, const uint32_t* lds_key,
                                                 const int32_t* doff, const uint32_t* dhi,
-                                                uint32_t a, uint32_t t, uint32_t voidm,
-                                                DrawThresholds th, uint32_t mark,
+                                                uint32_t a, uint32_t t, uint32_t blk,
+                                                uint32_t m, DrawThresholds th, uint32_t mark,
                                                 uint32_t* passed) {
   const uint32_t lf = th.lo_face, le = th.lo_edge, lc = th.lo_corner;
   uint32_t grown = 0, dirs = 0;
-  uint32_t m = voidm;
-  for (uint32_t blk = 0; m; ++blk) {
-    const U4 H = philox10(a, t, blk, kTagGrowHi, k0, k1);
-    uint32_t old[8], shift[8];
-    bool have_lo = false;
-    U4 L{0, 0, 0, 0};
+  const U4 H = philox10(a, t, blk, kTagGrowHi, k0, k1);
+  uint32_t old[8], bytes = 0;  // bytes: 2 bits per rank, the claimed byte in its word
+  bool have_lo = false;
+  U4 L{0, 0, 0, 0};
 #pragma unroll
-    for (int sl = 0; sl < 8; ++sl) {
-      old[sl] = 0xFFFFFFFFu;
-      shift[sl] = 0;
-      if (m) {
-        const int d = __builtin_ctz(m);
-        m &= m - 1u;
-        const uint32_t w = sl < 2 ? H.x : (sl < 4 ? H.y : (sl < 6 ? H.z : H.w));
-        const uint32_t h = (sl & 1) ? (w >> 16) : (w & 0xFFFFu);
-        const uint32_t hi = dhi[d];
-        if (h <= hi) {
-          bool pass = h < hi;
-          if (h == hi) {  // high halves tie (rare): decide on the low half
-            if (!have_lo) {
-              const uint32_t kl0 = *(const volatile uint32_t*)&lds_key[0];
-              const uint32_t kl1 = *(const volatile uint32_t*)&lds_key[1];
-              L = philox10(a, t, blk, kTagGrowLo, kl0, kl1);
-              have_lo = true;
-            }
-            const uint32_t wl = sl < 2 ? L.x : (sl < 4 ? L.y : (sl < 6 ? L.z : L.w));
-            const uint32_t l = (sl & 1) ? (wl >> 16) : (wl & 0xFFFFu);
-            pass = l < (((kCornerDirs >> d) & 1u) ? lc : (((kEdgeDirs >> d) & 1u) ? le : lf));
+  for (int sl = 0; sl < 8; ++sl) {
+    old[sl] = 0xFFFFFFFFu;
+    if (m) {
+      const int d = __builtin_ctz(m);
+      m &= m - 1u;
+      const uint32_t w = sl < 2 ? H.x : (sl < 4 ? H.y : (sl < 6 ? H.z : H.w));
+      const uint32_t h = (sl & 1) ? (w >> 16) : (w & 0xFFFFu);
+      const uint32_t hi = dhi[d];
+      if (h <= hi) {
+        bool pass = h < hi;
+        if (h == hi) {  // high halves tie (rare): decide on the low half
+          if (!have_lo) {
+            const uint32_t kl0 = *(const volatile uint32_t*)&lds_key[0];
+            const uint32_t kl1 = *(const volatile uint32_t*)&lds_key[1];
+            L = philox10(a, t, blk, kTagGrowLo, kl0, kl1);
+            have_lo = true;
           }
-          if (pass) {
-            const uint32_t q = (uint32_t)((int32_t)a + doff[d]);
-            shift[sl] = (q & 3u) * 8u;
-            old[sl] = atomicOr((uint32_t*)(grid + (q & ~3u)), mark << shift[sl]);
-            dirs |= 1u << d;
-          }
+          const uint32_t wl = sl < 2 ? L.x : (sl < 4 ? L.y : (sl < 6 ? L.z : L.w));
+          const uint32_t l = (sl & 1) ? (wl >> 16) : (wl & 0xFFFFu);
+          pass = l < (((kCornerDirs >> d) & 1u) ? lc : (((kEdgeDirs >> d) & 1u) ? le : lf));
+        }
+        if (pass) {
+          const uint32_t q = (uint32_t)((int32_t)a + doff[d]);
+          bytes |= (q & 3u) << (2 * sl);
+          old[sl] = atomicOr((uint32_t*)(grid + (q & ~3u)), mark << ((q & 3u) * 8u));
+          dirs |= 1u << d;
         }
       }
     }
-#pragma unroll
-    for (int sl = 0; sl < 8; ++sl) grown += ((old[sl] >> shift[sl]) & 0xFFu) == kVoid;
   }
+#pragma unroll
+  for (int sl = 0; sl < 8; ++sl)
+    grown += ((old[sl] >> (((bytes >> (2 * sl)) & 3u) * 8u)) & 0xFFu) == kVoid;
   *passed = dirs;
   return grown;
 }
+
+// Smallest of the eight 16-bit high halves of a block (two per word).
+__device__ __forceinline__ uint32_t min_half(const U4& H) {
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  const u16x2 a = __builtin_elementwise_min(__builtin_bit_cast(u16x2, H.x),
+                                            __builtin_bit_cast(u16x2, H.y));
+  const u16x2 b = __builtin_elementwise_min(__builtin_bit_cast(u16x2, H.z),
+                                            __builtin_bit_cast(u16x2, H.w));
+  const u16x2 c = __builtin_elementwise_min(a, b);
+  return min((uint32_t)c.x, (uint32_t)c.y);
+}
+
+// Capacity of a wavefront's list of candidate blocks (drained when a round could overflow it).
+constexpr uint32_t kCandCap = 256;
 
 // LDS image of one tile at the step's start.  Halo row h = hy + 6 hz (hy, hz in 0..5)
 // covers y = y0 - 1 + hy, z = z0 - 1 + hz; interior row i = jy + 4 jz is halo row
@@ -1102,10 +1114,19 @@ struct TileImage {
   uint64_t S[kTileRows];   // solid (interior rows)
   uint32_t W[kTileVoxels];   // per queued front voxel: void mask (direction order) | x << 26
   uint16_t qo[kTileVoxels];  // the queue (interior row << 6 | x - x0), then its order by
-                             // void count (similar work per round)
-  uint8_t row[kTileVoxels];  // interior row of each queued voxel
+                             // void count, heaviest first (queue slot | interior row << 10)
+  union {
+    uint8_t row[kTileVoxels];  // interior row of each queued voxel (until the order is made)
+    uint16_t cand[kCandCap];   // then: blocks that may hold a passing rank
+                               // (queue slot << 2 | block | interior row << 12)
+  };
   uint32_t hist[32];         // void-count histogram, then bucket cursors
 };
+
+static_assert(kCandCap <= kTileVoxels / 2, "the candidate list lives in the row bytes");
+// Four images (one workgroup of 256 threads) plus the workgroup's own LDS must stay
+// within a fifth of the compute unit's 160 KiB, so that five workgroups fit.
+static_assert(4 * sizeof(TileImage) + 1024 <= 160 * 1024 / 5, "tile image too large");
 
 // The 26-bit void mask (direction order) of front voxel (xl, jy, jz) of the image: the
 // three bits x - 1, x, x + 1 of each of the nine neighbouring rows are bits xl..xl + 2
@@ -1123,6 +1144,15 @@ __device__ __forceinline__ uint32_t tile_void_mask(const TileImage& T, int xl, i
       acc |= (w & 7u) << (3 * (ky + 3 * kz));
     }
   return (acc & 0x1FFFu) | ((acc >> 1) & 0x3FFE000u);
+}
+
+// z planes of halo rows whose loads a wavefront has in flight at once while staging.
+constexpr int kStagePlanes = 3;
+
+// Lane `lane` of v takes the wave-uniform value s; the other lanes keep theirs.
+__device__ __forceinline__ uint32_t write_lane(uint32_t v, uint32_t s, uint32_t lane) {
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(s), "i"(lane));
+  return v;
 }
 
 __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
@@ -1247,10 +1277,13 @@ void k_sweep(BatchArgs A) {
         const int32_t y0 = (int32_t)(q1 - iz * tl.nty) * kTileY;
         const int32_t z0 = (int32_t)iz * kTileZ;
         wave_sync();  // the previous tile's image is no longer read
-        // 1. stage the rows of the tile and its halo, one z plane (6 rows) of loads in
-        // flight at a time (off-domain lanes read byte 0 and are masked); fold the
-        // previous step's marks.  The halo columns x0 - 1 and x0 + 64 of all 36 rows are
+        // 1. stage the rows of the tile and its halo, kStagePlanes z planes of row loads in
+        // flight at a time (off-domain rows read row 0, off-domain lanes are masked);
+        // fold the previous step's marks.  The halo columns x0 - 1 and x0 + 64 of all 36 rows are
         // read by 36 lanes at once.
+        // (global loads: a flat load would also hold up every wait on LDS)
+        const __attribute__((address_space(1))) uint8_t* ggrid =
+            (const __attribute__((address_space(1))) uint8_t*)grid;
         uint64_t lm, rm;  // bit h: voxel x0 - 1 / x0 + 64 of halo row h void (uniform)
         {
           const int h = (int)lane;
@@ -1258,48 +1291,72 @@ void k_sweep(BatchArgs A) {
           const bool rin = h < kHaloRows && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
           const int32_t row = rin ? y * g.nx + z * (int32_t)g.nxy : 0;
           const bool inl = rin && x0 > 0, inr = rin && x0 + kTileX < g.nx;
-          const uint32_t bl = inl ? grid[row + x0 - 1] : 0xFFu;
-          const uint32_t br = inr ? grid[row + x0 + kTileX] : 0xFFu;
+          const uint32_t bl = inl ? ggrid[row + x0 - 1] : 0xFFu;
+          const uint32_t br = inr ? ggrid[row + x0 + kTileX] : 0xFFu;
           const uint64_t Lm = __ballot(bl == kVoid || bl == mark);
           const uint64_t Rm = __ballot(br == kVoid || br == mark);
           lm = Lm;
           rm = Rm;
         }
-        for (int hz = 0; hz < kTileZ + 2; ++hz) {
-          const int32_t z = z0 - 1 + hz;
-          const bool zin = z >= 0 && z < g.nz;
-          uint32_t bv[kTileY + 2];
-          int32_t rowv[kTileY + 2];
+        // Each row's mask is two compares ballotted into scalar registers, parked in
+        // lane h of rv (an interior row's solid mask in lane i of rs); lanes < 36 write
+        // the image once at the end.
+        const uint64_t xin = __ballot(x0 + (int32_t)lane < g.nx);  // lanes inside in x
+        const uint32_t vx = (uint32_t)x0 + lane;
+        // lanes past the row's end read its last byte (masked), so every read is in the grid
+        const uint32_t vxc = min(vx, (uint32_t)g.nx - 1u);
+        uint32_t rv_lo = 0, rv_hi = 0, rs_lo = 0, rs_hi = 0;
+        // halo row (hy, hz): its offset in the grid (row 0 when outside the domain)
+        auto row_base = [&](int hy, int hz, bool& rin) -> uint32_t {
+          const int32_t y = y0 - 1 + hy, z = z0 - 1 + hz;
+          rin = y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+          return rin ? (uint32_t)(y * g.nx + z * (int32_t)g.nxy) : 0u;
+        };
 #pragma unroll
-          for (int hy = 0; hy < kTileY + 2; ++hy) {
-            const int32_t y = y0 - 1 + hy;
-            const bool rin = zin && y >= 0 && y < g.ny;
-            const int32_t row = rin ? y * g.nx + z * (int32_t)g.nxy : 0;
-            const int32_t x = x0 + (int32_t)lane;
-            const bool in = rin && x < g.nx;
-            rowv[hy] = in ? row + x : -1;
-            bv[hy] = grid[in ? row + x : 0];
-          }
+        for (int hz0 = 0; hz0 < kTileZ + 2; hz0 += kStagePlanes) {
+          uint32_t bv[kStagePlanes][kTileY + 2];
 #pragma unroll
-          for (int hy = 0; hy < kTileY + 2; ++hy) {
-            const bool in = rowv[hy] >= 0;
-            const bool vd = in && (bv[hy] == kVoid || bv[hy] == mark);
-            const uint64_t V = __ballot(vd);
-            const int h = hy + (kTileY + 2) * hz;
-            if (hy >= 1 && hy <= kTileY && hz >= 1 && hz <= kTileZ) {
-              const uint64_t Sm = __ballot(in && !vd);
-              if (in && bv[hy] == pmark) {  // grown in the previous step: fold to 1
-                const uint32_t q = (uint32_t)rowv[hy];
-                atomicXor((uint32_t*)(grid + (q & ~3u)), (pmark ^ kSolid) << ((q & 3u) * 8u));
+          for (int dz = 0; dz < kStagePlanes; ++dz)
+#pragma unroll
+            for (int hy = 0; hy < kTileY + 2; ++hy) {
+              bool rin;
+              bv[dz][hy] = ggrid[row_base(hy, hz0 + dz, rin) + vxc];
+            }
+#pragma unroll
+          for (int dz = 0; dz < kStagePlanes; ++dz)
+#pragma unroll
+            for (int hy = 0; hy < kTileY + 2; ++hy) {
+              const int hz = hz0 + dz;
+              bool rin;
+              const uint32_t rowb = row_base(hy, hz, rin);
+              const uint64_t rmask = rin ? xin : 0ull;
+              const uint32_t b = bv[dz][hy];
+              const uint64_t V = (__ballot(b == kVoid) | __ballot(b == mark)) & rmask;
+              const uint32_t h = (uint32_t)(hy + (kTileY + 2) * hz);
+              rv_lo = write_lane(rv_lo, (uint32_t)V, h);
+              rv_hi = write_lane(rv_hi, (uint32_t)(V >> 32), h);
+              if (hy >= 1 && hy <= kTileY && hz >= 1 && hz <= kTileZ) {
+                const uint32_t i = (uint32_t)((hy - 1) + kTileY * (hz - 1));
+                const uint64_t Sm = rmask & ~V;
+                rs_lo = write_lane(rs_lo, (uint32_t)Sm, i);
+                rs_hi = write_lane(rs_hi, (uint32_t)(Sm >> 32), i);
+                const uint64_t Pm = __ballot(b == pmark) & rmask;
+                if (Pm) {  // grown in the previous step: fold to 1
+                  if ((Pm >> lane) & 1ull) {
+                    const uint32_t q = rowb + vx;
+                    atomicXor((uint32_t*)(grid + (q & ~3u)), (pmark ^ kSolid) << ((q & 3u) * 8u));
+                  }
+                }
               }
-              if (lane == 0) T.S[(hy - 1) + kTileY * (hz - 1)] = Sm;
             }
-            if (lane == 0) {
-              T.lo[h] = V << 1 | ((lm >> h) & 1ull);
-              T.hi[h] = (uint8_t)(((uint32_t)(V >> 63) | (uint32_t)((rm >> h) & 1ull) << 1) << 1);
-            }
-          }
         }
+        if (lane < (uint32_t)kHaloRows) {
+          const uint64_t V = (uint64_t)rv_hi << 32 | rv_lo;
+          T.lo[lane] = V << 1 | ((lm >> lane) & 1ull);
+          T.hi[lane] =
+              (uint8_t)(((uint32_t)(V >> 63) | (uint32_t)((rm >> lane) & 1ull) << 1) << 1);
+        }
+        if (lane < (uint32_t)kTileRows) T.S[lane] = (uint64_t)rs_hi << 32 | rs_lo;
         wave_sync();
         // 2. front rows (solid with a void neighbour) and their prefix
         uint64_t F = 0;
@@ -1371,40 +1428,83 @@ void k_sweep(BatchArgs A) {
         // a tile's last, partial round holds the lightest voxels)
         for (uint32_t qi = lane; qi < nq; qi += kWave)
           T.qo[nq - 1u - atomicAdd(&T.hist[__builtin_popcount(T.W[qi] & 0x3FFFFFFu)], 1u)] =
-              (uint16_t)qi;
+              (uint16_t)(qi | (uint32_t)T.row[qi] << 10);
         wave_sync();
-        // 5. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1))
-        uint32_t tm = 0, grown = 0;
-        for (uint32_t k = lane; k < nq; k += kWave) {
-          const uint32_t qi = T.qo[k];
-          const uint32_t w = T.W[qi];
-          const int i = T.row[qi], xl = (int)(w >> 26);
-          const int jy = i % kTileY, jz = i / kTileY;
-          const uint32_t vm = w & 0x3FFFFFFu;
-          const uint32_t nv = (uint32_t)__builtin_popcount(vm);
-          draws_l += nv;
-          blocks_l += (nv + 7u) >> 3;
-          const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
-                             (uint32_t)(z0 + jz) * g.nxy;
-          uint32_t passed = 0;
-          grown += sweep_draws(grid, k0, k1, s_key, s_doff, s_dhi, a, t, vm, th, mark, &passed);
-          // passing ranks whose target leaves this tile list the target's tile (this
-          // tile is listed anyway); first claim or not, the target was void
-          const uint32_t leave = (xl == 0 ? kDxNeg : 0u) | (xl == kTileX - 1 ? kDxPos : 0u) |
-                                 (jy == 0 ? kDyNeg : 0u) | (jy == kTileY - 1 ? kDyPos : 0u) |
-                                 (jz == 0 ? kDzNeg : 0u) | (jz == kTileZ - 1 ? kDzPos : 0u);
-          uint32_t out = passed & leave;
-          while (out) {
-            const int d = __builtin_ctz(out);
-            out &= out - 1u;
-            const int xn = xl + dir_field(kDirDX, d) - 1, yn = jy + dir_field(kDirDY, d) - 1,
-                      zn = jz + dir_field(kDirDZ, d) - 1;
-            const int ox = xn < 0 ? 0 : (xn >= kTileX ? 2 : 1);
-            const int oy = yn < 0 ? 0 : (yn >= kTileY ? 2 : 1);
-            const int oz = zn < 0 ? 0 : (zn >= kTileZ ? 2 : 1);
-            tm |= 1u << (ox + 3 * oy + 9 * oz);
+        // 5. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1)), in two
+        // phases.  A: every block of high halves is drawn and kept only if one of its
+        // half-words is at or below the largest high-half threshold (no rank of it can
+        // pass otherwise); kept blocks go to the LDS list.  B: each listed block is drawn
+        // again and its ranks are decided exactly and claimed, 64 blocks per round.
+        uint32_t tm = 0, grown = 0, ncand = 0;
+        const uint32_t hmax = max(th.hi_face, max(th.hi_edge, th.hi_corner));
+        auto drain = [&]() {
+          wave_sync();
+          for (uint32_t c0 = 0; c0 < ncand; c0 += kWave) {
+            if (c0 + lane < ncand) {
+              const uint32_t e = T.cand[c0 + lane];
+              const uint32_t qi = (e >> 2) & 1023u, blk = e & 3u;
+              const uint32_t w = T.W[qi];
+              const int i = (int)(e >> 12), xl = (int)(w >> 26);
+              const int jy = i % kTileY, jz = i / kTileY;
+              uint32_t m = w & 0x3FFFFFFu;
+              for (uint32_t r = 0; r < 8u * blk; ++r) m &= m - 1u;  // earlier blocks' ranks
+              const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
+                                 (uint32_t)(z0 + jz) * g.nxy;
+              uint32_t passed = 0;
+              grown += sweep_block(grid, k0, k1, s_key, s_doff, s_dhi, a, t, blk, m, th, mark,
+                                   &passed);
+              // passing ranks whose target leaves this tile list the target's tile (this
+              // tile is listed anyway); first claim or not, the target was void
+              const uint32_t leave = (xl == 0 ? kDxNeg : 0u) | (xl == kTileX - 1 ? kDxPos : 0u) |
+                                     (jy == 0 ? kDyNeg : 0u) | (jy == kTileY - 1 ? kDyPos : 0u) |
+                                     (jz == 0 ? kDzNeg : 0u) | (jz == kTileZ - 1 ? kDzPos : 0u);
+              uint32_t out = passed & leave;
+              while (out) {
+                const int d = __builtin_ctz(out);
+                out &= out - 1u;
+                const int xn = xl + dir_field(kDirDX, d) - 1, yn = jy + dir_field(kDirDY, d) - 1,
+                          zn = jz + dir_field(kDirDZ, d) - 1;
+                const int ox = xn < 0 ? 0 : (xn >= kTileX ? 2 : 1);
+                const int oy = yn < 0 ? 0 : (yn >= kTileY ? 2 : 1);
+                const int oz = zn < 0 ? 0 : (zn >= kTileZ ? 2 : 1);
+                tm |= 1u << (ox + 3 * oy + 9 * oz);
+              }
+            }
+          }
+          ncand = 0;
+          wave_sync();
+        };
+        for (uint32_t kb = 0; kb < nq; kb += kWave) {
+          const uint32_t k = kb + lane;
+          uint32_t qe = 0, nb = 0, a = 0;
+          if (k < nq) {
+            qe = T.qo[k];
+            const uint32_t w = T.W[qe & 1023u];
+            const int i = (int)(qe >> 10), xl = (int)(w >> 26);
+            const uint32_t nv = (uint32_t)__builtin_popcount(w & 0x3FFFFFFu);
+            nb = (nv + 7u) >> 3;
+            draws_l += nv;
+            blocks_l += nb;
+            a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + i % kTileY) * (uint32_t)g.nx +
+                (uint32_t)(z0 + i / kTileY) * g.nxy;
+          }
+          // the queue runs heaviest first, so the round's first lane has the most blocks
+          const uint32_t nbmax = uniform((uint32_t)__builtin_amdgcn_readfirstlane(nb));
+          for (uint32_t blk = 0; blk < nbmax; ++blk) {
+            bool keep = false;
+            if (blk < nb) keep = min_half(philox10(a, t, blk, kTagGrowHi, k0, k1)) <= hmax;
+            const uint64_t kept = __ballot(keep);
+            if (kept) {
+              if (keep)
+                T.cand[ncand + __builtin_amdgcn_mbcnt_hi((uint32_t)(kept >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u))] =
+                    (uint16_t)((qe & 1023u) << 2 | blk | (qe >> 10) << 12);
+              ncand += (uint32_t)__popcll(kept);
+              if (ncand > kCandCap - kWave) drain();
+            }
           }
         }
+        if (ncand) drain();
         grown_w += wave_sum(grown);
         if (full) continue;  // the full-field form lists every tile anyway
         // 6. list the tiles that may hold F_{t+1} for the next pass, each once: this
