@@ -1284,72 +1284,75 @@ void k_sweep(BatchArgs A) {
         // (global loads: a flat load would also hold up every wait on LDS)
         const __attribute__((address_space(1))) uint8_t* ggrid =
             (const __attribute__((address_space(1))) uint8_t*)grid;
-        uint64_t lm, rm;  // bit h: voxel x0 - 1 / x0 + 64 of halo row h void (uniform)
+        // Lane h < 36 finds whether halo row h lies in the domain (bit h of rows_in) and
+        // reads the row's voxels x0 - 1 and x0 + 64 (their ballots come after the rows).
+        // Every address is clamped into the grid; what lies outside it is masked.
+        auto yrow = [&](int32_t y) { return (uint32_t)min(max(y, 0), g.ny - 1) * (uint32_t)g.nx; };
+        auto zrow = [&](int32_t z) { return (uint32_t)min(max(z, 0), g.nz - 1) * g.nxy; };
+        bool inl, inr;
+        uint32_t bl, br;
+        uint64_t rows_in;
         {
           const int h = (int)lane;
           const int32_t y = y0 - 1 + h % (kTileY + 2), z = z0 - 1 + h / (kTileY + 2);
           const bool rin = h < kHaloRows && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
-          const int32_t row = rin ? y * g.nx + z * (int32_t)g.nxy : 0;
-          const bool inl = rin && x0 > 0, inr = rin && x0 + kTileX < g.nx;
-          const uint32_t bl = inl ? ggrid[row + x0 - 1] : 0xFFu;
-          const uint32_t br = inr ? ggrid[row + x0 + kTileX] : 0xFFu;
-          const uint64_t Lm = __ballot(bl == kVoid || bl == mark);
-          const uint64_t Rm = __ballot(br == kVoid || br == mark);
-          lm = Lm;
-          rm = Rm;
+          rows_in = __ballot(rin);
+          const uint32_t row = yrow(y) + zrow(z);
+          inl = rin && x0 > 0;
+          inr = rin && x0 + kTileX < g.nx;
+          bl = ggrid[row + (uint32_t)max(x0 - 1, 0)];
+          br = ggrid[row + (uint32_t)min(x0 + kTileX, g.nx - 1)];
         }
         // Each row's mask is two compares ballotted into scalar registers, parked in
         // lane h of rv (an interior row's solid mask in lane i of rs); lanes < 36 write
         // the image once at the end.
-        const uint64_t xin = __ballot(x0 + (int32_t)lane < g.nx);  // lanes inside in x
+        const bool lane_in = x0 + (int32_t)lane < g.nx;
+        const uint64_t xin = __ballot(lane_in);  // lanes inside in x
         const uint32_t vx = (uint32_t)x0 + lane;
         // lanes past the row's end read its last byte (masked), so every read is in the grid
         const uint32_t vxc = min(vx, (uint32_t)g.nx - 1u);
         uint32_t rv_lo = 0, rv_hi = 0, rs_lo = 0, rs_hi = 0;
-        // halo row (hy, hz): its offset in the grid (row 0 when outside the domain)
-        auto row_base = [&](int hy, int hz, bool& rin) -> uint32_t {
-          const int32_t y = y0 - 1 + hy, z = z0 - 1 + hz;
-          rin = y >= 0 && y < g.ny && z >= 0 && z < g.nz;
-          return rin ? (uint32_t)(y * g.nx + z * (int32_t)g.nxy) : 0u;
-        };
 #pragma unroll
         for (int hz0 = 0; hz0 < kTileZ + 2; hz0 += kStagePlanes) {
           uint32_t bv[kStagePlanes][kTileY + 2];
 #pragma unroll
           for (int dz = 0; dz < kStagePlanes; ++dz)
 #pragma unroll
-            for (int hy = 0; hy < kTileY + 2; ++hy) {
-              bool rin;
-              bv[dz][hy] = ggrid[row_base(hy, hz0 + dz, rin) + vxc];
-            }
+            for (int hy = 0; hy < kTileY + 2; ++hy)
+              bv[dz][hy] = ggrid[yrow(y0 - 1 + hy) + zrow(z0 - 1 + hz0 + dz) + vxc];
 #pragma unroll
           for (int dz = 0; dz < kStagePlanes; ++dz)
 #pragma unroll
             for (int hy = 0; hy < kTileY + 2; ++hy) {
               const int hz = hz0 + dz;
-              bool rin;
-              const uint32_t rowb = row_base(hy, hz, rin);
-              const uint64_t rmask = rin ? xin : 0ull;
+              const uint32_t h = (uint32_t)(hy + (kTileY + 2) * hz);
+              const uint64_t rmask = ((rows_in >> h) & 1ull) ? xin : 0ull;
               const uint32_t b = bv[dz][hy];
               const uint64_t V = (__ballot(b == kVoid) | __ballot(b == mark)) & rmask;
-              const uint32_t h = (uint32_t)(hy + (kTileY + 2) * hz);
               rv_lo = write_lane(rv_lo, (uint32_t)V, h);
               rv_hi = write_lane(rv_hi, (uint32_t)(V >> 32), h);
               if (hy >= 1 && hy <= kTileY && hz >= 1 && hz <= kTileZ) {
+                // (interior rows lie in the domain in y and z: rmask is xin)
                 const uint32_t i = (uint32_t)((hy - 1) + kTileY * (hz - 1));
                 const uint64_t Sm = rmask & ~V;
                 rs_lo = write_lane(rs_lo, (uint32_t)Sm, i);
                 rs_hi = write_lane(rs_hi, (uint32_t)(Sm >> 32), i);
                 const uint64_t Pm = __ballot(b == pmark) & rmask;
                 if (Pm) {  // grown in the previous step: fold to 1
-                  if ((Pm >> lane) & 1ull) {
-                    const uint32_t q = rowb + vx;
-                    atomicXor((uint32_t*)(grid + (q & ~3u)), (pmark ^ kSolid) << ((q & 3u) * 8u));
+                  if (b == pmark && lane_in) {
+                    const uint32_t q = yrow(y0 - 1 + hy) + zrow(z0 - 1 + hz) + vx;
+                    __hip_atomic_fetch_xor(
+                        (__attribute__((address_space(1))) uint32_t*)(grid + (q & ~3u)),
+                        (pmark ^ kSolid) << ((q & 3u) * 8u), __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_AGENT);
                   }
                 }
               }
             }
         }
+        // bit h: voxel x0 - 1 / x0 + 64 of halo row h void (uniform)
+        const uint64_t lm = __ballot(inl && (bl == kVoid || bl == mark));
+        const uint64_t rm = __ballot(inr && (br == kVoid || br == mark));
         if (lane < (uint32_t)kHaloRows) {
           const uint64_t V = (uint64_t)rv_hi << 32 | rv_lo;
           T.lo[lane] = V << 1 | ((lm >> lane) & 1ull);
