@@ -1250,6 +1250,27 @@ void k_sweep(BatchArgs A) {
     const int32_t* __restrict__ lin = uniform(c.cur) ? R.f1 : R.f0;
     int32_t* __restrict__ lout = uniform(c.cur) ? R.f0 : R.f1;
     uint32_t kept_w = 0, grown_w = 0, draws_l = 0, blocks_l = 0;
+    // A tile's stamp atomics are issued at the end of its turn; their old values are
+    // used once the next tile's first row loads are out (or after the last tile): the
+    // first raiser of a stamp appends the tile to its part of the next list.
+    uint32_t pend_un = 0, pend_old = 0;
+    bool pend = false;
+    auto append = [&]() {
+      if (pend && pend_old < t + 2u) {
+        const uint32_t pos = atomicAdd(&s_fill, 1u);
+        if (pos < part_cap) {
+          lout[part_base + pos] = (int32_t)pend_un;
+          atomicMax(&s_commit, pos + 1u);
+        } else {  // the part is full: spill into the tail half
+          const uint32_t tb = atomicAdd(&A.tailfill[r], 1u);
+          if (tb < tl.n)
+            lout[tl.n + tb] = (int32_t)pend_un;
+          else
+            atomicOr(&c.overflow, 1u);
+        }
+      }
+      pend = false;
+    };
     for (uint32_t base = e_lo; base < e_hi; base += kWave) {
       __syncthreads();  // the previous block of entries is consumed
       if (threadIdx.x < (uint32_t)kWave) {
@@ -1320,6 +1341,7 @@ void k_sweep(BatchArgs A) {
 #pragma unroll
             for (int hy = 0; hy < kTileY + 2; ++hy)
               bv[dz][hy] = ggrid[yrow(y0 - 1 + hy) + zrow(z0 - 1 + hz0 + dz) + vxc];
+          if (hz0 == 0) append();  // the previous tile's stamps
 #pragma unroll
           for (int dz = 0; dz < kStagePlanes; ++dz)
 #pragma unroll
@@ -1515,24 +1537,13 @@ void k_sweep(BatchArgs A) {
         const uint32_t tmask = wave_or(tm) | 1u << 13;
         if (lane < 27u && ((tmask >> lane) & 1u)) {
           const int ox = (int)lane % 3 - 1, oy = (int)(lane / 3) % 3 - 1, oz = (int)lane / 9 - 1;
-          const uint32_t un =
-              (uint32_t)((int32_t)u + ox + (int32_t)tl.ntx * (oy + (int32_t)tl.nty * oz));
-          if (atomicMax(&stamp[un], t + 2u) < t + 2u) {
-            const uint32_t pos = atomicAdd(&s_fill, 1u);
-            if (pos < part_cap) {
-              lout[part_base + pos] = (int32_t)un;
-              atomicMax(&s_commit, pos + 1u);
-            } else {  // the part is full: spill into the tail half
-              const uint32_t tb = atomicAdd(&A.tailfill[r], 1u);
-              if (tb < tl.n)
-                lout[tl.n + tb] = (int32_t)un;
-              else
-                atomicOr(&c.overflow, 1u);
-            }
-          }
+          pend_un = (uint32_t)((int32_t)u + ox + (int32_t)tl.ntx * (oy + (int32_t)tl.nty * oz));
+          pend_old = atomicMax(&stamp[pend_un], t + 2u);
+          pend = true;
         }
       }
     }
+    append();
     const uint32_t draws_w = wave_sum(draws_l), blocks_w = wave_sum(blocks_l);
     if (lane == 0) {
       if (kept_w) atomicAdd(&s_kept, kept_w);
