@@ -1088,6 +1088,17 @@ __device__ __forceinline__ uint32_t sweep_block(uint8_t* __restrict__ grid, uint
   return grown;
 }
 
+// m without its k lowest set bits (k < popcount(m) <= 26): a binary search for the lowest q
+// with k set bits below q + 1, on popcounts of prefixes.
+__device__ __forceinline__ uint32_t drop_low_ranks(uint32_t m, uint32_t k) {
+  if (k == 0) return m;
+  uint32_t q = 0;  // invariant: fewer than k set bits below q
+#pragma unroll
+  for (uint32_t s = 16; s; s >>= 1)
+    if ((uint32_t)__builtin_popcount(m & ((1u << (q + s)) - 1u)) < k) q += s;
+  return m & (~0u << (q + 1u));
+}
+
 // Smallest of the eight 16-bit high halves of a block (two per word).
 __device__ __forceinline__ uint32_t min_half(const U4& H) {
   typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -1413,16 +1424,15 @@ void k_sweep(BatchArgs A) {
         // 3. compact the front voxels into the queue (row i's prefix and mask are
         // broadcast from lane i)
         const uint32_t excl = incl - cnt;
-        const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll 4
         for (int i = 0; i < kTileRows; ++i) {
-          // (the builtin returns int: widen through uint32_t, never by sign extension)
-          const uint64_t Fi =
-              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)(F >> 32), i) << 32) |
-              (uint64_t)(uint32_t)__builtin_amdgcn_readlane((uint32_t)F, i);
+          const uint32_t flo = (uint32_t)__builtin_amdgcn_readlane((uint32_t)F, i);
+          const uint32_t fhi = (uint32_t)__builtin_amdgcn_readlane((uint32_t)(F >> 32), i);
           const uint32_t pi = (uint32_t)__builtin_amdgcn_readlane(excl, i);
-          if ((Fi >> lane) & 1ull)
-            T.qo[pi + (uint32_t)__popcll(Fi & below)] = (uint16_t)((uint32_t)i << 6 | lane);
+          // lanes below this one that hold a front voxel of row i
+          const uint32_t rank = __builtin_amdgcn_mbcnt_hi(fhi, __builtin_amdgcn_mbcnt_lo(flo, 0u));
+          if ((((uint64_t)fhi << 32 | flo) >> lane) & 1ull)
+            T.qo[pi + rank] = (uint16_t)((uint32_t)i << 6 | lane);
         }
         wave_sync();
         // 4. void masks of the queue, then a counting sort of the queue by void count
@@ -1471,8 +1481,7 @@ void k_sweep(BatchArgs A) {
               const uint32_t w = T.W[qi];
               const int i = (int)(e >> 12), xl = (int)(w >> 26);
               const int jy = i % kTileY, jz = i / kTileY;
-              uint32_t m = w & 0x3FFFFFFu;
-              for (uint32_t r = 0; r < 8u * blk; ++r) m &= m - 1u;  // earlier blocks' ranks
+              const uint32_t m = drop_low_ranks(w & 0x3FFFFFFu, 8u * blk);  // earlier blocks'
               const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
                                  (uint32_t)(z0 + jz) * g.nxy;
               uint32_t passed = 0;
