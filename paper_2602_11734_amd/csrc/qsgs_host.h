@@ -567,6 +567,13 @@ struct Engine {
     return QSGS_OK;
   }
 
+  // The batch control block and realization 0's loop state, with one synchronization.
+  qsgs_status read_bctl_ctl0(BatchCtl* hb, Ctl* hc) {
+    QSGS_HIP(hipMemcpyAsync(hb, args.bctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+    QSGS_HIP(hipMemcpyAsync(hc, &args.reals[0].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    QSGS_HIP(hipStreamSynchronize(s));
+    return QSGS_OK;
+  }
   qsgs_status read_ctl(size_t r, Ctl* h) {
     QSGS_HIP(hipMemcpyAsync(h, &args.reals[r].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     QSGS_HIP(hipStreamSynchronize(s));
@@ -623,28 +630,31 @@ struct Engine {
 
   // Fused-sweep loop until every record has stopped.  A realization takes steps + 1
   // passes (the last one only prunes and folds).  For a single realization the chunk
-  // length follows the remaining count over the last step's growth.
+  // length follows the remaining count over the last step's growth, plus the final pass
+  // (passes after the stop find nothing to do and cost two empty launches, less than a
+  // round trip to the host).
   qsgs_status run_sweep_loop() {
     const bool profiling = prof_on();
     std::vector<hipEvent_t> ev;
     BatchCtl b{};
-    QSGS_TRY(read_bctl(&b));
+    Ctl c{};
+    const bool single = tune.steps_per_sync <= 0 && reals.size() == 1;
+    auto read_state = [&]() { return single ? read_bctl_ctl0(&b, &c) : read_bctl(&b); };
+    QSGS_TRY(read_state());
     while (b.running > 0) {
       uint32_t chunk = tune.steps_per_sync > 0 ? (uint32_t)tune.steps_per_sync : 8u;
-      if (tune.steps_per_sync <= 0 && reals.size() == 1) {
-        Ctl c{};
-        QSGS_TRY(read_ctl(0, &c));
+      if (single) {
         chunk = 16;
         if (c.mode == kModeFinal)
           chunk = 1;
         else if (c.step > 0 && c.last_new > 0)
           chunk = (uint32_t)std::max<uint64_t>(
-              1, std::min<uint64_t>(16, (c.s_star - c.cnt) / c.last_new + 1));
+              1, std::min<uint64_t>(16, (c.s_star - c.cnt) / c.last_new + 2));
         else if (c.step > 0)
           chunk = 4;
       }
       for (uint32_t k = 0; k < chunk; ++k) QSGS_TRY(sweep_pass(profiling ? &ev : nullptr));
-      QSGS_TRY(read_bctl(&b));
+      QSGS_TRY(read_state());
     }
     if (profiling && !ev.empty()) {
       std::vector<Real> fin;

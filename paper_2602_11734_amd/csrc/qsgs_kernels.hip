@@ -845,14 +845,17 @@ __device__ uint32_t block_scan_u32(uint32_t n, Val val, Out out) {
     }
     if (lane == kWave - 1) wt[wv] = incl;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t acc = carry;
-      for (uint32_t w = 0; w < nw; ++w) {
-        const uint32_t t = wt[w];
-        wt[w] = acc;
-        acc += t;
+    if (wv == 0) {  // the first wave scans the wave totals (at most 16)
+      const uint32_t t = lane < nw ? wt[lane] : 0u;
+      uint32_t ti = t;
+#pragma unroll
+      for (int o = 1; o < 1024 / kWave; o <<= 1) {
+        const uint32_t u = __shfl_up(ti, o, kWave);
+        if (lane >= (uint32_t)o) ti += u;
       }
-      carry = acc;
+      const uint32_t c = carry;
+      if (lane < nw) wt[lane] = c + ti - t;
+      if (lane == nw - 1) carry = c + ti;
     }
     __syncthreads();
     if (i < n) out(i, wt[wv] + incl - v);
@@ -1599,45 +1602,53 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
   __syncthreads();
   const uint32_t nwg = P.wgoff[A.count];
   // workgroups are ordered by realization: a wavefront whose 64 entries belong to one
-  // realization sums them first and adds once
-  for (uint32_t base = threadIdx.x & ~(uint32_t)(kWave - 1); base < nwg; base += blockDim.x) {
-    const uint32_t w = base + lane_id();
-    const bool in = w < nwg;
-    uint32_t a = 0;
-    uint32_t kept = 0, grown = 0, draws = 0, blocks = 0, out = 0;
-    if (in) {
-      uint32_t lo = 0, hi = A.count;  // realization of logical workgroup w
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (P.wgoff[mid] <= w) lo = mid; else hi = mid;
+  // realization sums them first and adds once.  Each thread loads kU entries before
+  // reducing any, so their loads are in flight together.
+  constexpr int kU = 4;
+  for (uint32_t base = threadIdx.x & ~(uint32_t)(kWave - 1); base < nwg;
+       base += blockDim.x * kU) {
+    uint32_t a[kU], kept[kU], grown[kU], draws[kU], blocks[kU], out[kU];
+    bool in[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t w = base + u * blockDim.x + lane_id();
+      in[u] = w < nwg;
+      a[u] = kept[u] = grown[u] = draws[u] = blocks[u] = out[u] = 0;
+      if (in[u]) {
+        uint32_t lo = 0, hi = A.count;  // realization of logical workgroup w
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (P.wgoff[mid] <= w) lo = mid; else hi = mid;
+        }
+        a[u] = lo;
+        kept[u] = A.wgkept[w];
+        grown[u] = A.wggrown[w];
+        draws[u] = A.wgdraws[w];
+        blocks[u] = A.wgblocks[w];
+        out[u] = Q.seg[w + lo].fill;
       }
-      a = lo;
-      kept = A.wgkept[w];
-      grown = A.wggrown[w];
-      draws = A.wgdraws[w];
-      blocks = A.wgblocks[w];
-      out = Q.seg[w + a].fill;
     }
-    const uint32_t a0 = __shfl(a, 0, kWave);
-    if (__ballot(in && a != a0) == 0) {  // one realization: per-wave sums
-      kept = wave_sum(kept);
-      grown = wave_sum(grown);
-      draws = wave_sum(draws);
-      blocks = wave_sum(blocks);
-      out = wave_sum(out);
-      if (lane_id() == 0) {
-        atomicAdd(&acc_kept[a0], kept);
-        atomicAdd(&acc_grown[a0], grown);
-        atomicAdd(&acc_draws[a0], (unsigned long long)draws);
-        atomicAdd(&acc_blocks[a0], (unsigned long long)blocks);
-        atomicAdd(&acc_out[a0], out);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (__ballot(in[u]) == 0) break;  // (uniform) the entries end here
+      const uint32_t a0 = __shfl(a[u], 0, kWave);
+      if (__ballot(in[u] && a[u] != a0) == 0) {  // one realization: per-wave sums
+        const uint32_t sk = wave_sum(kept[u]), sg = wave_sum(grown[u]),
+                       sd = wave_sum(draws[u]), sb = wave_sum(blocks[u]), so = wave_sum(out[u]);
+        if (lane_id() == 0) {
+          atomicAdd(&acc_kept[a0], sk);
+          atomicAdd(&acc_grown[a0], sg);
+          atomicAdd(&acc_draws[a0], (unsigned long long)sd);
+          atomicAdd(&acc_blocks[a0], (unsigned long long)sb);
+          atomicAdd(&acc_out[a0], so);
+        }
+      } else if (in[u]) {
+        atomicAdd(&acc_kept[a[u]], kept[u]);
+        atomicAdd(&acc_grown[a[u]], grown[u]);
+        atomicAdd(&acc_draws[a[u]], (unsigned long long)draws[u]);
+        atomicAdd(&acc_blocks[a[u]], (unsigned long long)blocks[u]);
+        atomicAdd(&acc_out[a[u]], out[u]);
       }
-    } else if (in) {
-      atomicAdd(&acc_kept[a], kept);
-      atomicAdd(&acc_grown[a], grown);
-      atomicAdd(&acc_draws[a], (unsigned long long)draws);
-      atomicAdd(&acc_blocks[a], (unsigned long long)blocks);
-      atomicAdd(&acc_out[a], out);
     }
   }
   __syncthreads();
