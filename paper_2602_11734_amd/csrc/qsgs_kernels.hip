@@ -1202,7 +1202,7 @@ void k_sweep(BatchArgs A) {
   __shared__ int32_t s_doff[26];
   __shared__ uint32_t s_dhi[26];
   __shared__ uint32_t s_key[2];
-  __shared__ uint32_t s_fill, s_commit, s_kept, s_grown, s_draws, s_blocks;
+  __shared__ uint32_t s_fill, s_commit, s_kept, s_grown, s_draws, s_blocks, s_next;
   const uint32_t G = gridDim.x;
   const uint32_t p = uniform(A.bctl->plan);
   const SweepPlan& P = A.plan[p];
@@ -1210,7 +1210,7 @@ void k_sweep(BatchArgs A) {
   // logical workgroup index: XCD x (workgroups b with b % 8 == x) holds [x G/8, (x+1) G/8)
   const uint32_t beta = (blockIdx.x % kNumXcd) * (G / kNumXcd) + blockIdx.x / kNumXcd;
   const uint32_t nwg = uniform(P.wgoff[A.count]);
-  const uint32_t lane = lane_id(), wib = uniform(threadIdx.x / kWave), wpb = blockDim.x / kWave;
+  const uint32_t lane = lane_id(), wib = uniform(threadIdx.x / kWave);
   TileImage& T = reinterpret_cast<TileImage*>(sweep_lds)[wib];
   if (threadIdx.x == 0) {
     s_fill = 0;
@@ -1298,9 +1298,15 @@ void k_sweep(BatchArgs A) {
           s_tiles[threadIdx.x] = (uint32_t)lin[P.seg[lo].base + e - P.segchunk[lo]];
         }
       }
+      if (threadIdx.x == 0) s_next = 0;
       __syncthreads();
       const uint32_t nb = min((uint32_t)kWave, e_hi - base);
-      for (uint32_t j = wib; j < nb; j += wpb) {
+      // each wavefront takes the block's next tile when it is done with one
+      for (;;) {
+        uint32_t jn = 0;
+        if (lane == 0) jn = atomicAdd(&s_next, 1u);
+        const uint32_t j = uniform((uint32_t)__builtin_amdgcn_readfirstlane(jn));
+        if (j >= nb) break;
         const uint32_t u = uniform(s_tiles[j]);
         if (u >= tl.n) {
           if (lane == 0) atomicOr(&c.bad_entry, 1u);
