@@ -1288,15 +1288,38 @@ void k_sweep(BatchArgs A) {
     for (uint32_t base = e_lo; base < e_hi; base += kWave) {
       __syncthreads();  // the previous block of entries is consumed
       if (threadIdx.x < (uint32_t)kWave) {
-        const uint32_t e = base + threadIdx.x;
-        if (e < e_hi) {  // segment of entry e: largest s with segchunk[s] <= e
-          uint32_t lo = sb, hi = se;
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (P.segchunk[mid] <= e) lo = mid; else hi = mid;
-          }
-          s_tiles[threadIdx.x] = (uint32_t)lin[P.seg[lo].base + e - P.segchunk[lo]];
+        // segment of the block's first entry (largest s with segchunk[s] <= base): a
+        // 64-way search, each round narrowing the range 64-fold with one load per lane
+        uint32_t lo = sb, hi = se;  // segchunk[lo] <= base < segchunk[hi]
+        while (hi - lo > 1) {
+          const uint32_t step = (hi - lo + kWave - 1) / kWave;
+          const uint32_t c = lo + lane * step;
+          const uint64_t ok = __ballot(c < hi && P.segchunk[c] <= base);
+          const uint32_t last = 63u - (uint32_t)__builtin_clzll(ok);  // lane 0 probes lo
+          lo = lo + last * step;
+          hi = min(hi, lo + step);
         }
+        // the block's entries run through segments lo, lo + 1, ...: each lane takes the
+        // last segment whose start is at or below its entry (empty segments share their
+        // successor's start; the walk reads the starts 64 at a time until one passes the
+        // block's last entry)
+        const uint32_t e = base + lane;
+        const uint32_t last_e = min(e_hi, base + (uint32_t)kWave) - 1u;
+        uint32_t sgi = lo;
+        for (uint32_t s0 = lo + 1u; s0 < se; s0 += kWave) {  // (uniform)
+          const uint32_t nxt = s0 + lane < se ? P.segchunk[s0 + lane] : 0xFFFFFFFFu;
+          bool past = false;
+          for (uint32_t i = 0; i < (uint32_t)kWave; ++i) {
+            const uint32_t b = (uint32_t)__builtin_amdgcn_readlane(nxt, i);
+            if (b > last_e) {
+              past = true;
+              break;
+            }
+            if (b <= e) sgi = s0 + i;
+          }
+          if (past) break;
+        }
+        if (e < e_hi) s_tiles[lane] = (uint32_t)lin[P.seg[sgi].base + e - P.segchunk[sgi]];
       }
       if (threadIdx.x == 0) s_next = 0;
       __syncthreads();
