@@ -226,9 +226,11 @@ void qsgs_server_destroy(qsgs_server* server);
  * multiple of 8 so that each of the 8 XCDs gets an equal share), plus the growth steps
  * issued between two host reads of the loop state (`steps_per_sync`, 0 = adaptive).
  * The shape never changes a result: every output is a function of the inputs only.
- * qsgs_set_tuning applies process-wide to calls that start afterwards (NULL restores
- * the defaults: 256 threads; 2560 workgroups for growth, 2048 for prune and seeding;
- * adaptive); QSGS_ERR_INVALID for a bad shape. */
+ * grow_grid = 0 sizes the growth sweep to one round of the workgroups the device holds
+ * at once (1280 of 256 threads on an MI355X: 256 compute units x 5); the step API's
+ * growth kernel then takes 2048.  qsgs_set_tuning applies process-wide to calls that
+ * start afterwards (NULL restores the defaults: 256 threads; growth grid 0, 2048 for
+ * prune and seeding; adaptive); QSGS_ERR_INVALID for a bad shape. */
 typedef struct {
   int32_t grow_block, grow_grid;
   int32_t prune_block, prune_grid;

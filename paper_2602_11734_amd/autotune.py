@@ -18,7 +18,7 @@ from . import (QsgsError, params_of, qsgs_generate_batch, qsgs_batch_workspace_b
                qsgs_tuning)
 
 SWEEP_BLOCKS = (128, 256, 512)
-SWEEP_GRIDS = (1280, 2560, 3840, 5120)
+SWEEP_GRIDS = (0, 2560, 3840, 5120)  # 0: one round of resident workgroups
 SEED_SHAPES = ((256, 2048), (512, 4096))
 
 
@@ -71,7 +71,8 @@ def autotune(cases, repeats: int = 2, use_cache: bool = True, verbose: bool = Fa
         for sb, sg in SEED_SHAPES:
             for b in SWEEP_BLOCKS:
                 for g in SWEEP_GRIDS:
-                    t = {"grow_block": b, "grow_grid": g, "prune_block": b, "prune_grid": g,
+                    t = {"grow_block": b, "grow_grid": g, "prune_block": b,
+                         "prune_grid": g or 2048,
                          "seed_block": sb, "seed_grid": sg, "steps_per_sync": 0}
                     qsgs_set_tuning(t)
                     _run(cases, grids, ws, wsb)  # warm-up
@@ -96,7 +97,7 @@ def autotune(cases, repeats: int = 2, use_cache: bool = True, verbose: bool = Fa
     wall, best, prof = min(results, key=lambda r: r[0])
     entry = {"tuning": best, "wall_ms": wall * 1e3, "candidates": len(results),
              "default_wall_ms": next(r[0] for r in results
-                                     if r[1]["grow_block"] == 256 and r[1]["grow_grid"] == 2560
+                                     if r[1]["grow_block"] == 256 and r[1]["grow_grid"] == 0
                                      and r[1]["seed_block"] == 256) * 1e3}
     qsgs_set_tuning(best)
     if use_cache:

@@ -296,6 +296,7 @@ qsgs_status qsgs_set_tuning(const qsgs_tuning* t) {
       if (blocks[k] < 64 || blocks[k] > (uint32_t)kMaxBlock || blocks[k] % 64)
         return fail(QSGS_ERR_INVALID, "block sizes must be multiples of 64 in [64, %d]",
                     kMaxBlock);
+      if (k == 0 && grids[k] == 0) continue;  // growth grid: one resident round
       if (grids[k] < 8 || grids[k] > kMaxSweepGrid || grids[k] % 8)
         return fail(QSGS_ERR_INVALID, "grid sizes must be multiples of 8 in [8, %u]",
                     kMaxSweepGrid);

@@ -283,11 +283,28 @@ inline SeedLayout seed_layout(const std::vector<Spec>& specs, bool with_cand = t
 // Launch shape of the item kernels (block = threads per workgroup, a multiple of 64 up
 // to 512; grid = workgroups, a multiple of 8) and the steps issued between host reads.
 struct Tuning {
-  uint32_t grow_block = kBlock, grow_grid = 2560;  // two rounds of resident sweep workgroups
+  uint32_t grow_block = kBlock, grow_grid = 0;  // 0: one round of resident sweep workgroups
   uint32_t prune_block = kBlock, prune_grid = 2048;
   uint32_t seed_block = kBlock, seed_grid = 2048;
   int32_t steps_per_sync = 0;  // 0: adaptive
 };
+
+// Workgroups of k_sweep (block threads each) that the current device holds at once:
+// one round of them takes every list share at the same time, and no share waits for a
+// slot.  2048 when the runtime cannot say.
+inline uint32_t resident_sweep_grid(uint32_t block) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep, (int)block,
+                                                   sweep_lds_bytes(block)) != hipSuccess ||
+      cus <= 0 || per_cu <= 0) {
+    (void)hipGetLastError();
+    return 2048;
+  }
+  const uint32_t n = (uint32_t)cus * (uint32_t)per_cu;
+  return std::max<uint32_t>(kNumXcd, n / kNumXcd * kNumXcd);
+}
 
 inline std::mutex& tuning_mu() {
   static std::mutex m;
@@ -369,7 +386,8 @@ struct Engine {
     args.wgdraws = at<uint32_t>(base, L.wgdraws);
     args.wgblocks = at<uint32_t>(base, L.wgblocks);
     args.tailfill = at<uint32_t>(base, L.tailfill);
-    const uint32_t want = std::max<uint32_t>(tune.grow_grid, 2 * (uint32_t)count);
+    const uint32_t g = tune.grow_grid ? tune.grow_grid : resident_sweep_grid(tune.grow_block);
+    const uint32_t want = std::max<uint32_t>(g, 2 * (uint32_t)count);
     sweep_grid = std::min<uint32_t>(kMaxSweepGrid, (want + kNumXcd - 1) / kNumXcd * kNumXcd);
   }
 
@@ -542,7 +560,8 @@ struct Engine {
       e3 = prof_event();
       QSGS_HIP(hipEventRecord(e0, s));
     }
-    hipLaunchKernelGGL(k_grow, dim3(tune.grow_grid), dim3(tune.grow_block), 0, s, args);
+    hipLaunchKernelGGL(k_grow, dim3(tune.grow_grid ? tune.grow_grid : 2048u),
+                       dim3(tune.grow_block), 0, s, args);
     QSGS_LAUNCHED("k_grow");
     if (ev) QSGS_HIP(hipEventRecord(e1, s));
     QSGS_TRY(offsets(kItemsPrune));
