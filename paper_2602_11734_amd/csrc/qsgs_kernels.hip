@@ -1163,6 +1163,16 @@ __device__ __forceinline__ uint32_t tile_void_mask(const TileImage& T, int xl, i
 // z planes of halo rows whose loads a wavefront has in flight at once while staging.
 constexpr int kStagePlanes = 3;
 
+// Sets the wave's issue priority (0..3; the builtin takes an immediate).
+__device__ __forceinline__ void set_wave_priority(uint32_t p) {
+  switch (p) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+  }
+}
+
 // Lane `lane` of v takes the wave-uniform value s; the other lanes keep theirs.
 __device__ __forceinline__ uint32_t write_lane(uint32_t v, uint32_t s, uint32_t lane) {
   asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(s), "i"(lane));
@@ -1330,6 +1340,11 @@ void k_sweep(BatchArgs A) {
         if (lane == 0) jn = atomicAdd(&s_next, 1u);
         const uint32_t j = uniform((uint32_t)__builtin_amdgcn_readfirstlane(jn));
         if (j >= nb) break;
+        // The compute unit's arbiter favours older waves: of its resident workgroups
+        // the last dispatched would finish long after the first.  A wave's priority
+        // falls as its workgroup's share is taken, so workgroups that are behind get
+        // issue slots first and all finish together.
+        set_wave_priority(3u - min(3u, 4u * j / nb));
         const uint32_t u = uniform(s_tiles[j]);
         if (u >= tl.n) {
           if (lane == 0) atomicOr(&c.bad_entry, 1u);
