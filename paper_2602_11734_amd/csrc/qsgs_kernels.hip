@@ -825,6 +825,18 @@ __global__ __launch_bounds__(kBlock) void k_rollback(uint8_t* grid, uint32_t n) 
 // and builds the next plan.
 // ---------------------------------------------------------------------------
 
+// Bitwise or / sum of a value over the 64 lanes of the wavefront (every lane gets it).
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
 // Block-wide exclusive scan of n values val(i), handing out(i, prefix); returns the
 // total.  Every thread of the block calls it; blockDim.x <= 1024.
 template <typename Val, typename Out>
@@ -885,6 +897,25 @@ __device__ void plan_assign(const BatchArgs& A, uint32_t q) {
   auto nch = [&](uint32_t r) -> uint32_t {
     return sweep_active(A.reals[r]) ? P.segchunk[P.rseg[r + 1]] - P.segchunk[P.rseg[r]] : 0u;
   };
+  if (A.count <= (uint32_t)kWave) {  // one wavefront: sums and prefix without barriers
+    if (threadIdx.x < (uint32_t)kWave) {
+      const uint32_t r = threadIdx.x;
+      const uint32_t n = r < A.count ? nch(r) : 0u;
+      const uint32_t total = wave_sum(n), busy = wave_sum(n > 0 ? 1u : 0u);
+      const uint64_t avail = (uint64_t)A.bctl->grid - busy;
+      const uint32_t g = n ? (uint32_t)max<uint64_t>(1, avail * n / total) : 0u;
+      uint32_t incl = g;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, kWave);
+        if (r >= (uint32_t)o) incl += v;
+      }
+      if (r < A.count) P.wgoff[r] = incl - g;
+      if (r == (A.count ? A.count - 1u : 0u)) P.wgoff[A.count] = A.count ? incl : 0u;
+    }
+    __syncthreads();
+    return;
+  }
   const uint32_t total = block_scan_u32(A.count, nch, [](uint32_t, uint32_t) {});
   const uint32_t busy = block_scan_u32(
       A.count, [&](uint32_t r) { return nch(r) > 0 ? 1u : 0u; }, [](uint32_t, uint32_t) {});
@@ -1179,16 +1210,6 @@ __device__ __forceinline__ uint32_t write_lane(uint32_t v, uint32_t s, uint32_t 
   return v;
 }
 
-__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
-  return v;
-}
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
 
 // Orders LDS accesses of the lanes of one wavefront (a wave executes in lockstep; this
 // keeps the compiler from moving LDS accesses across the point).

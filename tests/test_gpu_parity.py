@@ -281,6 +281,26 @@ def test_batch_matches_oracle(q, orc):
         assert np.array_equal(lb, ref.log_blocks[: len(lb)])
 
 
+def test_large_batch_matches_oracle(q, orc):
+    """A batch of more realizations than a wavefront (80): the step end plans it with
+    block-wide scans.  Every result equals the oracle's run of that realization alone."""
+    import torch
+    cases = workloads.many_small_cases()
+    params = [q.params_of(c) for c in cases]
+    dims = [c.dims for c in cases]
+    grids = [torch.empty(q.qsgs_grid_bytes(d), dtype=torch.uint8, device="cuda") for d in dims]
+    wsb = q.qsgs_batch_workspace_bytes(dims, params)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    say("GPU generate_batch of", len(cases))
+    st, infos = q.qsgs_generate_batch(dims, params, grids, ws, wsb)
+    torch.cuda.synchronize()
+    for c, g, info in zip(cases, grids, infos):
+        ref = run_oracle(orc, c)
+        nx, ny, nz = c.dims
+        assert info.status == ref.status and info.step == ref.steps, c.name
+        assert np.array_equal(g[: nx * ny * nz].view(nz, ny, nx).cpu().numpy(), ref.grid), c.name
+
+
 def test_batch_reuses_workspace(q, orc):
     """Two batches in a row on one workspace, the second smaller and with other keys."""
     import torch

@@ -115,6 +115,21 @@ def config5(n_requests: int = 1000, rate_per_s: float = 100.0, seed: int = 0) ->
             for i in range(n_requests)]
 
 
+def many_small_cases(n: int = 80, seed: int = 2602) -> list[Case]:
+    """More small realizations than one wavefront of the step-end planner handles at
+    once (edges U{6..28}, porosity U[0.1, 0.5], S_d U[0.002, 0.05], face U[0.02, 0.2],
+    s U{0..6}, keys 5000 + i)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        dims = tuple(int(v) for v in rng.integers(6, 29, size=3))
+        out.append(Case(f"many_{i:03d}", dims, round(1.0 - float(rng.uniform(0.1, 0.5)), 6),
+                        round(float(rng.uniform(0.002, 0.05)), 6),
+                        g_from_face(round(float(rng.uniform(0.02, 0.2)), 6)),
+                        int(rng.integers(0, 7)), 5000 + i))
+    return out
+
+
 def small_cases() -> list[Case]:
     """Small and ragged grids (several 256-entry tiles, odd extents) and the method's
     degenerate cases, for element-by-element parity with the oracle."""
