@@ -118,6 +118,7 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t cnt, uint32_t* counter)
 // Ballot variant for 0/1 counts.
 __device__ __forceinline__ uint32_t wave_append_flag(bool flag, uint32_t* counter) {
   const uint64_t mask = __ballot(flag);
+  if (mask == 0) return 0;  // (uniform) nothing to append
   const uint32_t lane = lane_id();
   const uint32_t total = (uint32_t)__popcll(mask);
   uint32_t base = 0;

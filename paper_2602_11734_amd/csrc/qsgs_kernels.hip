@@ -264,17 +264,41 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* data, uint32_
 // in the same pass; candidates are appended with one atomic per wavefront.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
+  // the record's fields, read once per realization (the byte stores below could alias
+  // the record, which would otherwise force a reload of every field per chunk)
+  // (pointers are made wave-uniform so that they sit in scalar registers: a vector copy
+  // would make each chunk wait for the previous chunk's stores)
+  typedef __attribute__((address_space(1))) uint8_t gbyte;
+  typedef __attribute__((address_space(1))) uint32_t gword;
+  uint32_t cr = 0xFFFFFFFFu, n = 0, k0 = 0, k1 = 0, tiles = 0;
+  uint64_t t_seed = 0;
+  gbyte* grid = nullptr;
+  gword* stamp = nullptr;
+  int32_t* cand_list = nullptr;
+  uint32_t* n_cand = nullptr;
   for_each_chunk(A, kItemsVoxels, [&](uint32_t r, uint32_t v) {
-    Real& R = A.reals[r];
-    bool cand = false;
-    if (v < R.g.n) {
-      const U4 w = philox10(v, 0u, 0u, kTagSeed, R.k0, R.k1);
-      cand = (uint64_t)w.x < R.t_seed;
-      R.grid[v] = kVoid;
-      if (R.stamp && v < R.tl.n) R.stamp[v] = 0;  // fused sweep: no tile listed yet
+    if (r != cr) {
+      Real& R = A.reals[r];
+      n = uniform(R.g.n);
+      k0 = uniform(R.k0);
+      k1 = uniform(R.k1);
+      t_seed = uniform64(R.t_seed);
+      grid = (gbyte*)uniform64((uint64_t)R.grid);
+      stamp = (gword*)uniform64((uint64_t)R.stamp);
+      tiles = uniform(R.tl.n);
+      cand_list = (int32_t*)uniform64((uint64_t)R.cand);
+      n_cand = &R.ctl.n_cand;
+      cr = r;
     }
-    const uint32_t pos = wave_append_flag(cand, &R.ctl.n_cand);
-    if (cand) R.cand[pos] = (int32_t)v;  // capacity N: cannot overflow
+    bool cand = false;
+    if (v < n) {
+      const U4 w = philox10(v, 0u, 0u, kTagSeed, k0, k1);
+      cand = (uint64_t)w.x < t_seed;
+      grid[v] = kVoid;
+      if (stamp && v < tiles) stamp[v] = 0;  // fused sweep: no tile listed yet
+    }
+    const uint32_t pos = wave_append_flag(cand, n_cand);
+    if (cand) cand_list[pos] = (int32_t)v;  // capacity N: cannot overflow
   });
 }
 
