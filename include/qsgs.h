@@ -186,10 +186,13 @@ int64_t qsgs_read_step_work(const void* d_ws, size_t ws_bytes, int32_t index, in
 
 /* Continuous-batching server.  Generation requests of different sizes are queued on
  * the host; each tick admits queued requests in arrival order while a slot is free and
- * their footprint -- grid (qsgs_grid_bytes) plus two lists (8 N bytes each) --
- * fits the free part of the caller's device arena (the HBM budget), seeds them (with
- * transient seeding scratch from the same arena), then advances every resident
- * realization by `steps_per_tick` growth steps in shared launches.  A finished
+ * their footprint -- grid (qsgs_grid_bytes) plus the sweep state (two tile lists and
+ * the tile stamps, about N / 100 bytes) -- fits the free part of the caller's device
+ * arena (the HBM budget), seeds them (with transient seeding scratch from the same
+ * arena), then advances every resident realization in shared launches by at least
+ * `steps_per_tick` growth steps, and by up to 16 while every resident request is
+ * expected (from its remaining count over its last growth) to need that many before it
+ * stops, so that few host round trips fall on a lightly loaded server.  A finished
  * request's grid stays in the arena until qsgs_server_take copies it out.  Each
  * result is bit-identical to qsgs_generate of the same request alone.  A server is
  * used from one thread; its stream orders all of its work.

@@ -82,12 +82,16 @@ struct qsgs_server {
   std::unordered_map<int64_t, Request> resident;
   std::deque<int64_t> ready;      // finished, grid not yet taken
   std::unordered_map<int64_t, Request> done;
+  std::vector<Real> recs;         // the records as the last tick left them
 
   static size_t front_bytes(const Geometry& g) { return sweep_state_bytes(g); }
   static size_t footprint(const Geometry& g) { return align_up(grid_bytes(g)) + front_bytes(g); }
 };
 
 namespace {
+
+// Upper bound of the passes one tick runs when every resident request is far from done.
+constexpr uint64_t kMaxPassesPerTick = 16;
 
 qsgs_status server_admit(qsgs_server* S, std::vector<size_t>* group) {
   // Admit in arrival order while a slot is free and grid + fronts fit.
@@ -218,11 +222,33 @@ qsgs_status qsgs_server_tick(qsgs_server* S, int32_t* n_resident, int32_t* n_que
   }
   if (scratch_bytes) S->heap.release(scratch_off, scratch_bytes);  // stream-ordered reuse
 
-  if (!S->resident.empty())
-    for (int32_t k = 0; k < S->steps_per_tick; ++k) QSGS_TRY(E.sweep_pass(nullptr));
+  // Passes this tick: at least steps_per_tick, and up to the fewest any resident request
+  // is expected to need before it stops (its remaining count over its last growth, plus
+  // the final pass; steps_per_tick for one without growth seen yet), so that a lone
+  // request does not pay a host round trip every few passes while a full table still
+  // retires requests promptly.
+  if (!S->resident.empty()) {
+    uint64_t passes = kMaxPassesPerTick;
+    for (size_t slot = 0; slot < S->slot_req.size(); ++slot) {
+      if (S->slot_req[slot] < 0) continue;
+      uint64_t need = (uint64_t)S->steps_per_tick;  // no growth seen yet
+      if (slot < S->recs.size() && S->recs[slot].phase == kPhaseGrow) {
+        const Ctl& c = S->recs[slot].ctl;
+        if (c.mode == kModeFinal)
+          need = 1;
+        else if (c.step > 0 && c.last_new > 0)
+          need = (c.s_star > c.cnt ? (c.s_star - c.cnt) : 0) / c.last_new + 2;
+        else if (c.step > 0)
+          need = kMaxPassesPerTick;  // growing without new voxels yet: not near its end
+      }
+      passes = std::min(passes, need);
+    }
+    passes = std::max<uint64_t>(passes, (uint64_t)S->steps_per_tick);
+    for (uint64_t k = 0; k < passes; ++k) QSGS_TRY(E.sweep_pass(nullptr));
+  }
 
   // Retire finished requests: their fronts return to the arena, the grid waits.
-  std::vector<Real> recs;
+  std::vector<Real>& recs = S->recs;
   QSGS_TRY(E.read_all(&recs));
   for (size_t slot = 0; slot < S->slot_req.size(); ++slot) {
     const int64_t id = S->slot_req[slot];

@@ -341,9 +341,11 @@ def test_server_results_equal_solo_runs(q, orc):
         ticks = 0
         max_resident = 0
         while len(results) < len(cases):
-            if pending and ticks % 2 == 0:  # staggered arrivals
-                rid, c = pending.pop(0)
-                q.qsgs_server_submit(srv, rid, c.dims, q.params_of(c))
+            # three requests arrive together (they share the device), the rest staggered
+            for _ in range(3 if ticks == 0 else (1 if ticks % 2 == 0 else 0)):
+                if pending:
+                    rid, c = pending.pop(0)
+                    q.qsgs_server_submit(srv, rid, c.dims, q.params_of(c))
             say("server tick", ticks)
             res, queued, nready = q.qsgs_server_tick(srv)
             max_resident = max(max_resident, res)
