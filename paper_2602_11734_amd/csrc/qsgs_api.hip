@@ -61,6 +61,7 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
     return fail(QSGS_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", G.total, ws_bytes);
   Engine E;
   E.bind(ws, G.P, (size_t)count, s);
+  E.stage = thread_pinned_stage(Engine::stage_bytes((size_t)count));
   std::vector<size_t> group;
   for (int32_t r = 0; r < count; ++r) {
     E.init_sweep_record((size_t)r, specs[r], &params[r], grids[r], at<void>(ws, G.sweep[r]));
@@ -143,6 +144,7 @@ qsgs_status qsgs_seed(const qsgs_dims* dims, const qsgs_params* params, uint8_t*
   hipStream_t s = (hipStream_t)stream;
   Engine E;
   E.bind(d_ws, G.P, 1, s);
+  E.stage = thread_pinned_stage(Engine::stage_bytes(1));
   E.init_record(0, specs[0], params, d_grid, d_front, nullptr,
                 (uint32_t)std::min<int64_t>(front_cap, (int64_t)UINT32_MAX));
   E.attach_scratch({0}, at<void>(d_ws, G.seed), G.S);
@@ -181,6 +183,7 @@ qsgs_status qsgs_grow_step(const qsgs_dims* dims, const qsgs_params* params, uin
   hipStream_t s = (hipStream_t)stream;
   Engine E;
   E.bind(d_ws, P, 1, s);
+  E.stage = thread_pinned_stage(Engine::stage_bytes(1));
   E.init_record(0, Spec{g, Buckets{}}, params, d_grid, d_front_in, d_front_out,
                 (uint32_t)std::min<int64_t>(front_cap, (int64_t)UINT32_MAX));
   Real& R = E.reals[0];

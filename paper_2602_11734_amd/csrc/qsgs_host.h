@@ -280,6 +280,29 @@ inline SeedLayout seed_layout(const std::vector<Spec>& specs, bool with_cand = t
   return L;
 }
 
+// Pinned host memory for an engine's small transfers: a pageable copy is staged by the
+// runtime and costs a host round trip each; from pinned memory copies are plain DMA and
+// several share one synchronization.  One buffer per thread for the calls that bind an
+// engine for their own duration (each of them synchronizes before it returns), grown
+// when a call needs more; nullptr when pinned memory cannot be had (the engine then
+// copies from pageable memory).
+inline char* thread_pinned_stage(size_t bytes) {
+  thread_local char* p = nullptr;
+  thread_local size_t n = 0;
+  if (bytes > n) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      return nullptr;
+    }
+    n = bytes;
+  }
+  return p;
+}
+
 // Launch shape of the item kernels (block = threads per workgroup, a multiple of 64 up
 // to 512; grid = workgroups, a multiple of 8) and the steps issued between host reads.
 struct Tuning {
@@ -360,6 +383,20 @@ struct Engine {
   Tuning tune;
   WsHeader hdr{};
   uint32_t sweep_grid = 2048;
+  // pinned staging (see thread_pinned_stage): uploads, then readbacks, each in its own
+  // region; nullptr for pageable copies
+  char* stage = nullptr;
+  static size_t stage_bytes(size_t count) {
+    return 4 * kStageSlot + 2 * align_up(sizeof(Real) * count) + kStageSlot;
+  }
+  static constexpr size_t kStageSlot = 256;
+  char* st_up_hdr() { return stage; }
+  char* st_up_ctl() { return stage + kStageSlot; }
+  char* st_up_reals() { return stage + 2 * kStageSlot; }
+  char* st_dn_bctl() { return st_up_reals() + align_up(sizeof(Real) * reals.size()); }
+  char* st_dn_ctl() { return st_dn_bctl() + kStageSlot; }
+  char* st_dn_reals() { return st_dn_ctl() + kStageSlot; }
+  char* st_dn_live() { return st_dn_reals() + align_up(sizeof(Real) * reals.size()); }
 
   // Binds the engine to a persistent region of `count` records at `base`.
   void bind(void* base, const PersistLayout& L, size_t count, hipStream_t stream) {
@@ -395,7 +432,9 @@ struct Engine {
   qsgs_status upload_control() {
     BatchCtl b{};
     b.grid = sweep_grid;
-    QSGS_HIP(hipMemcpyAsync(args.bctl, &b, sizeof b, hipMemcpyHostToDevice, s));
+    const void* src = &b;
+    if (stage) src = std::memcpy(st_up_ctl(), &b, sizeof b);
+    QSGS_HIP(hipMemcpyAsync(args.bctl, src, sizeof b, hipMemcpyHostToDevice, s));
     QSGS_HIP(hipMemsetAsync(args.tailfill, 0, sizeof(uint32_t) * reals.size(), s));
     QSGS_HIP(hipMemsetAsync(args.plan[0].rseg, 0, sizeof(uint32_t) * (reals.size() + 1), s));
     return QSGS_OK;
@@ -444,14 +483,19 @@ struct Engine {
 
   qsgs_status upload_header() {
     hdr = WsHeader{kMagic, (uint32_t)reals.size(), P.log_cap, P.reals, P.logs};
-    QSGS_HIP(hipMemcpyAsync(at<void>(ws, P.hdr), &hdr, sizeof hdr, hipMemcpyHostToDevice, s));
+    const void* src = &hdr;
+    if (stage) src = std::memcpy(st_up_hdr(), &hdr, sizeof hdr);
+    QSGS_HIP(hipMemcpyAsync(at<void>(ws, P.hdr), src, sizeof hdr, hipMemcpyHostToDevice, s));
     return QSGS_OK;
   }
 
   qsgs_status upload(size_t first, size_t n) {
     if (n == 0) return QSGS_OK;
-    QSGS_HIP(hipMemcpyAsync(args.reals + first, reals.data() + first, sizeof(Real) * n,
-                            hipMemcpyHostToDevice, s));
+    const void* src = reals.data() + first;
+    if (stage)
+      src = std::memcpy(st_up_reals() + sizeof(Real) * first, reals.data() + first,
+                        sizeof(Real) * n);
+    QSGS_HIP(hipMemcpyAsync(args.reals + first, src, sizeof(Real) * n, hipMemcpyHostToDevice, s));
     return QSGS_OK;
   }
 
@@ -525,9 +569,10 @@ struct Engine {
           QSGS_LAUNCHED("k_luby_kill");
         }
         uint32_t live = 0;
-        QSGS_HIP(hipMemcpyAsync(&live, args.live + round - 1, sizeof live, hipMemcpyDeviceToHost,
-                                s));
+        void* dst = stage ? (void*)st_dn_live() : (void*)&live;
+        QSGS_HIP(hipMemcpyAsync(dst, args.live + round - 1, sizeof live, hipMemcpyDeviceToHost, s));
         QSGS_HIP(hipStreamSynchronize(s));
+        if (stage) std::memcpy(&live, st_dn_live(), sizeof live);
         if (live == 0) break;
         if (round + kRoundsPerCheck > kMaxRounds)
           return fail(QSGS_ERR_DEVICE, "seed spacing did not settle in %u rounds", kMaxRounds);
@@ -581,29 +626,41 @@ struct Engine {
   }
 
   qsgs_status read_bctl(BatchCtl* h) {
-    QSGS_HIP(hipMemcpyAsync(h, args.bctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+    void* dst = stage ? (void*)st_dn_bctl() : (void*)h;
+    QSGS_HIP(hipMemcpyAsync(dst, args.bctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
     QSGS_HIP(hipStreamSynchronize(s));
+    if (stage) std::memcpy(h, st_dn_bctl(), sizeof(BatchCtl));
     return QSGS_OK;
   }
 
   // The batch control block and realization 0's loop state, with one synchronization.
   qsgs_status read_bctl_ctl0(BatchCtl* hb, Ctl* hc) {
-    QSGS_HIP(hipMemcpyAsync(hb, args.bctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
-    QSGS_HIP(hipMemcpyAsync(hc, &args.reals[0].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    void* db = stage ? (void*)st_dn_bctl() : (void*)hb;
+    void* dc = stage ? (void*)st_dn_ctl() : (void*)hc;
+    QSGS_HIP(hipMemcpyAsync(db, args.bctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+    QSGS_HIP(hipMemcpyAsync(dc, &args.reals[0].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     QSGS_HIP(hipStreamSynchronize(s));
+    if (stage) {
+      std::memcpy(hb, st_dn_bctl(), sizeof(BatchCtl));
+      std::memcpy(hc, st_dn_ctl(), sizeof(Ctl));
+    }
     return QSGS_OK;
   }
   qsgs_status read_ctl(size_t r, Ctl* h) {
-    QSGS_HIP(hipMemcpyAsync(h, &args.reals[r].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    void* dst = stage ? (void*)st_dn_ctl() : (void*)h;
+    QSGS_HIP(hipMemcpyAsync(dst, &args.reals[r].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     QSGS_HIP(hipStreamSynchronize(s));
+    if (stage) std::memcpy(h, st_dn_ctl(), sizeof(Ctl));
     return QSGS_OK;
   }
 
   qsgs_status read_all(std::vector<Real>* out) {
     out->resize(reals.size());
-    QSGS_HIP(hipMemcpyAsync(out->data(), args.reals, sizeof(Real) * reals.size(),
-                            hipMemcpyDeviceToHost, s));
+    void* dst = stage ? (void*)st_dn_reals() : (void*)out->data();
+    QSGS_HIP(hipMemcpyAsync(dst, args.reals, sizeof(Real) * reals.size(), hipMemcpyDeviceToHost,
+                            s));
     QSGS_HIP(hipStreamSynchronize(s));
+    if (stage) std::memcpy(out->data(), st_dn_reals(), sizeof(Real) * reals.size());
     return QSGS_OK;
   }
 

@@ -83,6 +83,7 @@ struct qsgs_server {
   std::deque<int64_t> ready;      // finished, grid not yet taken
   std::unordered_map<int64_t, Request> done;
   std::vector<Real> recs;         // the records as the last tick left them
+  char* stage = nullptr;          // the engine's pinned staging (owned by the server)
 
   static size_t front_bytes(const Geometry& g) { return sweep_state_bytes(g); }
   static size_t footprint(const Geometry& g) { return align_up(grid_bytes(g)) + front_bytes(g); }
@@ -145,12 +146,20 @@ qsgs_status qsgs_server_create(void* d_arena, size_t arena_bytes, int32_t max_sl
   S->arena_bytes = arena_bytes;
   S->steps_per_tick = steps_per_tick;
   S->eng.bind(d_arena, P, (size_t)max_slots, S->s);
+  if (hipHostMalloc((void**)&S->stage, Engine::stage_bytes((size_t)max_slots),
+                    hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    S->stage = nullptr;  // pageable copies
+  }
+  S->eng.stage = S->stage;
   S->heap.reset(P.total, arena_bytes);
   S->slot_req.assign((size_t)max_slots, -1);
   qsgs_status st = S->eng.upload_header();
   if (st == QSGS_OK) st = S->eng.upload_control();
   if (st == QSGS_OK) st = S->eng.upload(0, (size_t)max_slots);  // every slot empty
   if (st != QSGS_OK) {
+    (void)hipStreamSynchronize(S->s);  // the uploads read the staging buffer
+    if (S->stage) (void)hipHostFree(S->stage);
     delete S;
     return st;
   }
@@ -313,6 +322,7 @@ size_t qsgs_server_free_bytes(const qsgs_server* S) {
 void qsgs_server_destroy(qsgs_server* S) {
   if (!S) return;
   (void)hipStreamSynchronize(S->s);  // destroy cannot report; pending work must finish first
+  if (S->stage) (void)hipHostFree(S->stage);
   delete S;
 }
 
