@@ -1176,11 +1176,13 @@ constexpr uint32_t kCandCap = 256;
 // (jy + 1) + 6 (jz + 1).  Bit i of a row mask is voxel x0 + i.
 struct TileImage {
   // Halo row h as a 66-bit window of "in-domain and void at the step's start" (byte 0
-  // or the mark): bit i of lo = voxel x0 - 1 + i (i < 64), bits 1, 2 of hi = voxels
-  // x0 + 63, x0 + 64 (hi is kept shifted left by one).
-  uint64_t lo[kHaloRows];
-  uint8_t hi[kHaloRows];
-  uint64_t S[kTileRows];   // solid (interior rows)
+  // or the mark) in three words: bit i of the window (word i / 32, bit i % 32) is voxel
+  // x0 - 1 + i, i < 66.
+  uint32_t win[kHaloRows][3];
+  union {
+    uint64_t S[kTileRows];   // solid (interior rows), until the front rows are found
+    uint32_t hist[32];       // then: void-count histogram, then bucket cursors
+  };
   uint32_t W[kTileVoxels];   // per queued front voxel: void mask (direction order) | x << 26
   uint16_t qo[kTileVoxels];  // the queue (interior row << 6 | x - x0), then its order by
                              // void count, heaviest first (queue slot | interior row << 10)
@@ -1189,7 +1191,6 @@ struct TileImage {
     uint16_t cand[kCandCap];   // then: blocks that may hold a passing rank
                                // (queue slot << 2 | block | interior row << 12)
   };
-  uint32_t hist[32];         // void-count histogram, then bucket cursors
 };
 
 static_assert(kCandCap <= kTileVoxels / 2, "the candidate list lives in the row bytes");
@@ -1200,16 +1201,17 @@ static_assert(4 * sizeof(TileImage) + 1024 <= 160 * 1024 / 5, "tile image too la
 // The 26-bit void mask (direction order) of front voxel (xl, jy, jz) of the image: the
 // three bits x - 1, x, x + 1 of each of the nine neighbouring rows are bits xl..xl + 2
 // of the row's window, concatenated in row order with the centre bit dropped.
+// (Bits xl..xl + 2 lie in words xl / 32 and xl / 32 + 1 of the window: one funnel shift
+// of that word pair per row.)
 __device__ __forceinline__ uint32_t tile_void_mask(const TileImage& T, int xl, int jy, int jz) {
-  const uint32_t hs = 63u - (uint32_t)xl;
+  const uint32_t* w0 = &T.win[jy + (kTileY + 2) * jz][xl >> 5];
   uint32_t acc = 0;
 #pragma unroll
   for (int kz = 0; kz < 3; ++kz)
 #pragma unroll
     for (int ky = 0; ky < 3; ++ky) {
-      const int h = (jy + ky) + (kTileY + 2) * (jz + kz);
-      const uint32_t w =
-          (uint32_t)(T.lo[h] >> xl) | (uint32_t)((uint64_t)T.hi[h] << hs);
+      const uint32_t* wr = w0 + 3 * (ky + (kTileY + 2) * kz);
+      const uint32_t w = __builtin_amdgcn_alignbit(wr[1], wr[0], (uint32_t)xl);
       acc |= (w & 7u) << (3 * (ky + 3 * kz));
     }
   return (acc & 0x1FFFu) | ((acc >> 1) & 0x3FFE000u);
@@ -1479,10 +1481,9 @@ void k_sweep(BatchArgs A) {
         const uint64_t lm = __ballot(inl && (bl == kVoid || bl == mark));
         const uint64_t rm = __ballot(inr && (br == kVoid || br == mark));
         if (lane < (uint32_t)kHaloRows) {
-          const uint64_t V = (uint64_t)rv_hi << 32 | rv_lo;
-          T.lo[lane] = V << 1 | ((lm >> lane) & 1ull);
-          T.hi[lane] =
-              (uint8_t)(((uint32_t)(V >> 63) | (uint32_t)((rm >> lane) & 1ull) << 1) << 1);
+          T.win[lane][0] = rv_lo << 1 | (uint32_t)((lm >> lane) & 1ull);
+          T.win[lane][1] = __builtin_amdgcn_alignbit(rv_hi, rv_lo, 31u);
+          T.win[lane][2] = rv_hi >> 31 | (uint32_t)((rm >> lane) & 1ull) << 1;
         }
         if (lane < (uint32_t)kTileRows) T.S[lane] = (uint64_t)rs_hi << 32 | rs_lo;
         wave_sync();
@@ -1496,7 +1497,8 @@ void k_sweep(BatchArgs A) {
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky) {
               const int h = (jy + ky) + (kTileY + 2) * (jz + kz);
-              const uint64_t lo = T.lo[h], hi = (uint64_t)(T.hi[h] >> 1);
+              const uint64_t lo = (uint64_t)T.win[h][1] << 32 | T.win[h][0],
+                             hi = T.win[h][2];
               // x - 1 neighbours: lo; x: V; x + 1 neighbours: window shifted down by two
               D |= lo | (lo >> 1) | (hi << 63) | (lo >> 2) | (hi << 62);
             }
