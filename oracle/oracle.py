@@ -85,6 +85,8 @@ def lib():
         _lib.orc_generate.argtypes = [i32, i32, i32, P(_Params), vp, P(_Result), vp, vp, vp, vp,
                                       vp, vp, i32]
         _lib.orc_generate.restype = i32
+        _lib.orc_generate_phases.argtypes = [i32, i32, i32, i32, P(_Params), vp, P(_Result)]
+        _lib.orc_generate_phases.restype = i32
     return _lib
 
 
@@ -215,3 +217,35 @@ def generate(dims, solid_fraction: float, seed_prob: float, g_ref, spacing: int,
     return OracleRun(grid, res.n_candidates, res.n_seeds, res.solid_count, res.target_count,
                      res.front_size, res.steps, res.status, b, cut(lf), cut(ln), cut(lc),
                      cut(ld), cut(lb))
+
+
+@dataclass
+class PhaseResult:
+    n_candidates: int
+    n_seeds: int
+    count: int
+    target_count: int
+    front_size: int
+    steps: int
+    status: int
+
+
+def generate_phases(dims, phases) -> tuple[np.ndarray, list[PhaseResult]]:
+    """Independent growing phases in sequence (Sec. 2.1 steps 1-5).  ``phases`` is a
+    sequence of (solid_fraction, seed_prob, g_ref, spacing, key[, max_steps]) tuples,
+    phase n = index + 1; returns the label grid (0 = matrix, n = phase n) and one
+    result per phase."""
+    nx, ny, nz = dims
+    k = len(phases)
+    arr = (_Params * k)()
+    for i, ph in enumerate(phases):
+        sf, sd, g, sp, key = ph[:5]
+        ms = ph[5] if len(ph) > 5 else 0
+        arr[i] = _Params(float(sf), float(sd), (ctypes.c_double * 3)(*g), int(sp), int(ms),
+                         int(key))
+    res = (_Result * k)()
+    labels = np.zeros((nz, ny, nx), dtype=np.uint8)
+    lib().orc_generate_phases(nx, ny, nz, k, arr, _ptr(labels), res)
+    out = [PhaseResult(r.n_candidates, r.n_seeds, r.solid_count, r.target_count, r.front_size,
+                       r.steps, r.status) for r in res]
+    return labels, out

@@ -326,12 +326,14 @@ int64_t orc_step_fullfield(int32_t nx, int32_t ny, int32_t nz, uint8_t* grid, ui
       int32_t x, y, z;
       coords(nx, ny, a, &x, &y, &z);
       int64_t q = neighbour(nx, ny, nz, x, y, z, d);
-      if (q < 0 || grid[q] == 1) continue; /* shifted off the grid, or already solid */
-      /* rank of d among a's void-at-start neighbours (value 2 = grown this step) */
+      /* shifted off the grid, or not void at the iteration's start (solid, or a cell of
+       * another phase: value 2 = grown this step, still void at the start) */
+      if (q < 0 || (grid[q] != 0 && grid[q] != 2)) continue;
+      /* rank of d among a's void-at-start neighbours */
       int32_t j = 0;
       for (int32_t e = 0; e < d; ++e) {
         int64_t r = neighbour(nx, ny, nz, x, y, z, e);
-        if (r >= 0 && grid[r] != 1) ++j;
+        if (r >= 0 && (grid[r] == 0 || grid[r] == 2)) ++j;
       }
       if ((uint64_t)orc_growth_draw(key, (int32_t)a, t, j) < T[cls]) grid[q] = 2;
     }
@@ -341,6 +343,16 @@ int64_t orc_step_fullfield(int32_t nx, int32_t ny, int32_t nz, uint8_t* grid, ui
     if (grid[v] == 2) { grid[v] = 1; ++grown; }
   return grown;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Whole generation on a grid that holds 0 (void, open to the phase) and     */
+/* possibly cells of other phases (any value other than 0, 1 and 2): those   */
+/* are never cores, sources or targets.  Candidates on them are dropped.     */
+/* ------------------------------------------------------------------------ */
+static int32_t generate_on(int32_t nx, int32_t ny, int32_t nz, const orc_params* p,
+                           uint8_t* grid, orc_result* res, int32_t* birth, int64_t* log_front,
+                           int64_t* log_new, int64_t* log_count, int64_t* log_draws,
+                           int64_t* log_blocks, int32_t log_cap);
 
 /* ------------------------------------------------------------------------ */
 /* Whole generation: seeding, front construction, then list-indexed steps    */
@@ -355,6 +367,15 @@ int32_t orc_generate(int32_t nx, int32_t ny, int32_t nz, const orc_params* p, ui
                      orc_result* res, int32_t* birth, int64_t* log_front, int64_t* log_new,
                      int64_t* log_count, int64_t* log_draws, int64_t* log_blocks,
                      int32_t log_cap) {
+  memset(grid, 0, (size_t)nx * ny * nz);
+  return generate_on(nx, ny, nz, p, grid, res, birth, log_front, log_new, log_count, log_draws,
+                     log_blocks, log_cap);
+}
+
+static int32_t generate_on(int32_t nx, int32_t ny, int32_t nz, const orc_params* p,
+                           uint8_t* grid, orc_result* res, int32_t* birth, int64_t* log_front,
+                           int64_t* log_new, int64_t* log_count, int64_t* log_draws,
+                           int64_t* log_blocks, int32_t log_cap) {
   const int64_t n = (int64_t)nx * ny * nz;
   const int64_t s_star = orc_target_count(p->solid_fraction, n);
   const uint64_t t_seed = orc_prob_threshold(p->seed_prob);
@@ -362,17 +383,23 @@ int32_t orc_generate(int32_t nx, int32_t ny, int32_t nz, const orc_params* p, ui
   for (int c = 0; c < 3; ++c) t_ref[c] = orc_prob_threshold(p->g_ref[c]);
   const int32_t max_steps = p->max_steps > 0 ? p->max_steps : ORC_DEFAULT_MAX_STEPS;
 
-  memset(grid, 0, (size_t)n);
   int32_t* A = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   int32_t* A_next = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   int32_t* added = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   uint32_t* mask = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
   uint64_t* prio = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
 
-  int64_t n_cand = orc_seed_candidates(nx, ny, nz, p->key, t_seed, A, prio, n);
+  int64_t n_drawn = orc_seed_candidates(nx, ny, nz, p->key, t_seed, A, prio, n);
+  int64_t n_cand = 0; /* cores only on cells still open (Sec. 2.1 step 4) */
+  for (int64_t i = 0; i < n_drawn; ++i)
+    if (grid[A[i]] == 0) {
+      A[n_cand] = A[i];
+      prio[n_cand] = prio[i];
+      ++n_cand;
+    }
   int64_t n_seeds = orc_seed_select(nx, ny, nz, p->spacing, n_cand, A, prio, grid);
   if (birth)
-    for (int64_t v = 0; v < n; ++v) birth[v] = grid[v] ? 0 : -1;
+    for (int64_t v = 0; v < n; ++v) birth[v] = grid[v] == 1 ? 0 : -1;
 
   int64_t cnt = n_seeds;
   int64_t nA = orc_interface(nx, ny, nz, grid, A);
@@ -414,4 +441,31 @@ int32_t orc_generate(int32_t nx, int32_t ny, int32_t nz, const orc_params* p, ui
   res->status = cnt >= s_star ? ORC_DONE : (nA == 0 ? ORC_EXHAUSTED : ORC_MAXSTEPS);
   free(A); free(A_next); free(added); free(mask); free(prio);
   return res->status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multi-phase generation (Sec. 2.1 steps 1-5): the growing phases 1..K are  */
+/* generated one after another on the cells no earlier phase holds, each     */
+/* with its own core probability, growth probabilities, spacing, key and     */
+/* target fraction P^n of the whole domain (S*_n = ceil(P^n N), Eq. (1) with */
+/* the phase's own count).  Phases are independent: a phase grows only into */
+/* unassigned cells.  Cells left unassigned form the matrix phase (label 0). */
+/* While phase n grows, phase m < n is held as the value 3 + m, which the    */
+/* single-phase rules treat as neither void nor solid.                       */
+/* ------------------------------------------------------------------------ */
+int32_t orc_generate_phases(int32_t nx, int32_t ny, int32_t nz, int32_t n_phases,
+                            const orc_params* phases, uint8_t* labels, orc_result* results) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  memset(labels, 0, (size_t)n);
+  int32_t worst = ORC_DONE;
+  for (int32_t k = 0; k < n_phases; ++k) {
+    const int32_t st = generate_on(nx, ny, nz, &phases[k], labels, &results[k], NULL, NULL,
+                                   NULL, NULL, NULL, NULL, 0);
+    if (st > worst) worst = st;
+    for (int64_t v = 0; v < n; ++v)
+      if (labels[v] == 1) labels[v] = (uint8_t)(3 + (k + 1));
+  }
+  for (int64_t v = 0; v < n; ++v)
+    if (labels[v] >= 4) labels[v] = (uint8_t)(labels[v] - 3);
+  return worst;
 }

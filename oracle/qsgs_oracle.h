@@ -104,6 +104,14 @@ int32_t orc_generate(int32_t nx, int32_t ny, int32_t nz, const orc_params* p, ui
                      int64_t* log_count, int64_t* log_draws, int64_t* log_blocks,
                      int32_t log_cap);
 
+/* Multi-phase generation (Sec. 2.1 steps 1-5), independent phases in sequence:
+ * labels[v] = n for a cell of growing phase n (1..n_phases), 0 for the matrix phase.
+ * Phase n draws its cores only on cells no earlier phase holds and grows only into
+ * such cells; results[n - 1] reports it as orc_generate would (solid_count = the
+ * phase's cell count).  1 <= n_phases <= 252.  Returns the largest status. */
+int32_t orc_generate_phases(int32_t nx, int32_t ny, int32_t nz, int32_t n_phases,
+                            const orc_params* phases, uint8_t* labels, orc_result* results);
+
 #ifdef __cplusplus
 }
 #endif
