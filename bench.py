@@ -214,6 +214,39 @@ def voxel_list_step_api(q, torch, case):
             "identical_outputs": bool(torch.equal(steps_grid, b.grid[:n]))}
 
 
+def multiphase(q, torch):
+    """Three independent growing phases in sequence on one 400^3 label grid (Sec. 2.1
+    steps 1-5): wall time of qsgs_generate_phases and voxels grown per second over all
+    phases (each phase's final count minus its cores)."""
+    ps = workloads.phase_bench()
+    params = [q.params_of(c) for c in ps.phases]
+    gb = q.qsgs_grid_bytes(ps.dims)
+    wb = q.qsgs_phases_workspace_bytes(ps.dims, params)
+    labels = torch.empty(gb, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    q.qsgs_generate_phases(ps.dims, params, labels, ws, wb)  # warm-up
+    torch.cuda.synchronize()
+    q.qsgs_profile_enable(True)
+    q.qsgs_profile_read(reset=True)
+    t0 = time.perf_counter()
+    st, infos = q.qsgs_generate_phases(ps.dims, params, labels, ws, wb)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = q.qsgs_profile_read(reset=True)
+    q.qsgs_profile_enable(False)
+    grown = sum(i.solid_count - i.n_seeds for i in infos)
+    n = ps.dims[0] * ps.dims[1] * ps.dims[2]
+    counts = torch.bincount(labels[:n].to(torch.int64), minlength=len(params) + 1).tolist()
+    return {"workload": "400^3, three phases: P 0.50 / 0.15 / 0.05, S_d 5e-4 / 1e-4 / 2e-3, "
+                        "s 20 / 10 / 0, face 0.01 / 0.01 / 0.02 at 4:1:0.25, keys 1 / 2 / 3",
+            "generation_ms": wall * 1e3, "sweep_ms": prof["grow_ms"],
+            "voxels_grown_per_s": grown / wall,
+            "phases": [{"count": i.solid_count, "target": i.target_count, "steps": i.step,
+                        "status": q.STATUS_NAMES[i.status]} for i in infos],
+            "label_counts": counts,
+            "counts_match_labels": counts[1:] == [i.solid_count for i in infos]}
+
+
 def served_vs_plain(n_requests: int, rate: float):
     """Poisson request stream (mixed sizes): continuous batching against the plain
     one-at-a-time path on the same arrivals; p50/p99 latency and realizations/s."""
@@ -241,6 +274,8 @@ def main():
                     help="skip the list-indexed vs full-field comparison")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched vs plain realizations/s measurement")
+    ap.add_argument("--no-phases", action="store_true",
+                    help="skip the three-phase 400^3 generation")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served vs plain request-stream measurement")
     ap.add_argument("--serve-requests", type=int, default=300)
@@ -371,6 +406,8 @@ def main():
             list_vs_full_field(q, torch, workloads.config4_singletons()[3])]
     if not args.no_batch:
         out["detail"]["batched"] = batched_vs_plain(q, torch)
+    if not args.no_phases:
+        out["detail"]["multiphase"] = multiphase(q, torch)
     if not args.no_serve:
         out["detail"]["serving"] = {
             "moderate_load": served_vs_plain(args.serve_requests, args.serve_rate),

@@ -167,6 +167,30 @@ qsgs_status qsgs_generate_batch(int32_t count, const qsgs_dims* dims, const qsgs
                                 uint8_t* const* d_grids, void* d_ws, size_t ws_bytes,
                                 qsgs_info* infos, void* stream);
 
+/* Multi-phase generation (Sec. 2.1 steps 1-5): growing phases 1..n_phases are generated
+ * one after another on one label grid, each with its own parameters (core probability
+ * seed_prob, target fraction P^n = solid_fraction of the whole domain, growth
+ * probabilities, spacing, key, max_steps, full_field).  Phases are independent: phase n
+ * draws its cores only on cells no earlier phase holds and grows only into such cells
+ * (cells of other phases are neither sources nor targets); Eq. (1) uses the phase's own
+ * count and S*_n = ceil(P^n N).  Cells left unassigned form the matrix phase.  With one
+ * phase the result equals qsgs_generate.
+ *   n_phases  1..252.
+ *   phases    host array of n_phases parameter sets, phase n = index + 1.
+ *   d_labels  device, qsgs_grid_bytes(dims) bytes, 4-byte aligned; overwritten with
+ *             labels: n for a cell of phase n, 0 for the matrix (padding 0).
+ *   d_ws      device workspace, ws_bytes >= qsgs_phases_workspace_bytes(...).
+ *   infos     host array of n_phases results, as qsgs_generate reports them per phase
+ *             (solid_count = the phase's cell count when it stopped).
+ * Returns the largest per-phase status or an error (QSGS_ERR_INVALID: nothing launched;
+ * QSGS_ERR_WORKSPACE; QSGS_ERR_DEVICE).  On an error the labels are unspecified.  The
+ * per-step log of the workspace holds the last phase's steps.  Synchronises `stream`. */
+size_t qsgs_phases_workspace_bytes(const qsgs_dims* dims, int32_t n_phases,
+                                   const qsgs_params* phases);
+qsgs_status qsgs_generate_phases(const qsgs_dims* dims, int32_t n_phases,
+                                 const qsgs_params* phases, uint8_t* d_labels, void* d_ws,
+                                 size_t ws_bytes, qsgs_info* infos, void* stream);
+
 /* Copies the per-step log of realization `index` of the last qsgs_generate or
  * qsgs_generate_batch that used this workspace into host arrays (any may be NULL):
  * front[t] = |F_t|, grown[t] = |New_t|, count[t] = solid count at the start of step t,

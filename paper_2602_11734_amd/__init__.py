@@ -74,6 +74,9 @@ SIGNATURES = {
                                      _P(qsgs_info), _VP]),
     "qsgs_batch_workspace_bytes": (_SZ, [_I32, _VP, _VP]),
     "qsgs_generate_batch": (ctypes.c_int, [_I32, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
+    "qsgs_phases_workspace_bytes": (_SZ, [_P(qsgs_dims), _I32, _VP]),
+    "qsgs_generate_phases": (ctypes.c_int, [_P(qsgs_dims), _I32, _VP, _VP, _VP, _SZ, _VP,
+                                            _VP]),
     "qsgs_read_step_log": (_I64, [_VP, _SZ, _I32, _VP, _VP, _VP, _I64, _VP]),
     "qsgs_read_step_work": (_I64, [_VP, _SZ, _I32, _VP, _VP, _I64, _VP]),
     "qsgs_server_reserved_bytes": (_SZ, [_I32]),
@@ -236,6 +239,22 @@ def qsgs_generate_batch(dims_list, params_list, grids, ws, ws_bytes: int, stream
     return _check(st), list(infos)
 
 
+def qsgs_phases_workspace_bytes(dims, phases) -> int:
+    n = len(phases)
+    p = (qsgs_params * n)(*phases)
+    return int(load().qsgs_phases_workspace_bytes(ctypes.byref(make_dims(dims)), n, p))
+
+
+def qsgs_generate_phases(dims, phases, labels, ws, ws_bytes: int, stream=None):
+    """Multi-phase generation; returns (status, list of qsgs_info, one per phase)."""
+    n = len(phases)
+    p = (qsgs_params * n)(*phases)
+    infos = (qsgs_info * n)()
+    st = load().qsgs_generate_phases(ctypes.byref(make_dims(dims)), n, p, _ptr(labels),
+                                     _ptr(ws), int(ws_bytes), infos, _stream(stream))
+    return _check(st), list(infos)
+
+
 def qsgs_server_reserved_bytes(max_slots: int) -> int:
     return int(load().qsgs_server_reserved_bytes(int(max_slots)))
 
@@ -352,3 +371,24 @@ def generate(dims, params: qsgs_params, buffers: Buffers | None = None, stream=N
     d = info.as_dict()
     d["status_name"] = STATUS_NAMES[st]
     return buffers.view(), d, buffers
+
+
+def generate_phases(dims, phases, stream=None, device: str = "cuda"):
+    """Run qsgs_generate_phases; returns (label grid view [nz, ny, nx] uint8 on the
+    device: n for phase n, 0 for the matrix; list of per-phase info dicts)."""
+    import torch
+    dims = tuple(int(v) for v in dims)
+    gb = qsgs_grid_bytes(dims)
+    wb = qsgs_phases_workspace_bytes(dims, phases)
+    if gb == 0 or wb == 0:
+        raise QsgsError(ERR_INVALID, qsgs_last_error() or "invalid dims or phases")
+    labels = torch.empty(gb, dtype=torch.uint8, device=device)
+    ws = torch.empty(wb, dtype=torch.uint8, device=device)
+    _, infos = qsgs_generate_phases(dims, phases, labels, ws, wb, stream=stream)
+    out = []
+    for info in infos:
+        d = info.as_dict()
+        d["status_name"] = STATUS_NAMES[d["status"]]
+        out.append(d)
+    nx, ny, nz = dims
+    return labels[: nx * ny * nz].view(nz, ny, nx), out

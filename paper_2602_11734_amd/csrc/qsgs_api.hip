@@ -52,7 +52,7 @@ qsgs_status make_specs(int32_t count, const qsgs_dims* dims, const qsgs_params* 
 
 qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_params* params,
                           uint8_t* const* grids, void* ws, size_t ws_bytes, qsgs_info* infos,
-                          hipStream_t s) {
+                          hipStream_t s, bool walls = false) {
   std::vector<Spec> specs;
   QSGS_TRY(make_specs(count, dims, params, grids, &specs));
   if (!ws || !infos) return fail(QSGS_ERR_INVALID, "d_ws and info must not be NULL");
@@ -65,6 +65,7 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
   std::vector<size_t> group;
   for (int32_t r = 0; r < count; ++r) {
     E.init_sweep_record((size_t)r, specs[r], &params[r], grids[r], at<void>(ws, G.sweep[r]));
+    E.reals[r].walls = walls ? 1u : 0u;
     group.push_back((size_t)r);
   }
   E.attach_scratch(group, at<void>(ws, G.seed), G.S);
@@ -224,6 +225,66 @@ qsgs_status qsgs_generate_batch(int32_t count, const qsgs_dims* dims, const qsgs
                                 qsgs_info* infos, void* stream) {
   last_error().clear();
   return generate_impl(count, dims, params, d_grids, d_ws, ws_bytes, infos, (hipStream_t)stream);
+}
+
+// Multi-phase generation: phases grown in sequence on one label grid.  While phase k
+// grows, its cells are 1 (and the step marks 2 / 3), unassigned cells 0 and the cells of
+// phase m < k the value 3 + m, which the seeding and the sweep treat as walls.
+constexpr int32_t kMaxPhases = 252;
+constexpr uint32_t kWallBase = 3;
+
+size_t qsgs_phases_workspace_bytes(const qsgs_dims* dims, int32_t n_phases,
+                                   const qsgs_params* phases) {
+  if (!dims || !phases || n_phases < 1 || n_phases > kMaxPhases) return 0;
+  size_t m = 0;
+  for (int32_t k = 0; k < n_phases; ++k) {
+    const size_t b = qsgs_workspace_bytes(dims, &phases[k]);
+    if (b == 0) return 0;
+    m = std::max(m, b);
+  }
+  return m;
+}
+
+qsgs_status qsgs_generate_phases(const qsgs_dims* dims, int32_t n_phases,
+                                 const qsgs_params* phases, uint8_t* d_labels, void* d_ws,
+                                 size_t ws_bytes, qsgs_info* infos, void* stream) {
+  last_error().clear();
+  if (!dims || !phases || !d_labels || !d_ws || !infos)
+    return fail(QSGS_ERR_INVALID, "dims, phases, d_labels, d_ws and infos must not be NULL");
+  if (n_phases < 1 || n_phases > kMaxPhases)
+    return fail(QSGS_ERR_INVALID, "n_phases %d outside [1, %d]", n_phases, kMaxPhases);
+  Geometry g{};
+  QSGS_TRY(check_dims(dims, &g));
+  for (int32_t k = 0; k < n_phases; ++k) QSGS_TRY(check_params(&phases[k]));
+  if (reinterpret_cast<uintptr_t>(d_labels) % 4 != 0)
+    return fail(QSGS_ERR_INVALID, "d_labels must be 4-byte aligned");
+  const size_t need = qsgs_phases_workspace_bytes(dims, n_phases, phases);
+  if (ws_bytes < need)
+    return fail(QSGS_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", need, ws_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t gb = grid_bytes(g);
+  const uint32_t words = (uint32_t)(gb / 4);
+  const dim3 mg(std::min<uint32_t>(2048u, (words + 255u) / 256u)), mb(256);
+  QSGS_HIP(hipMemsetAsync(d_labels, 0, gb, s));
+  int32_t worst = QSGS_OK;
+  for (int32_t k = 0; k < n_phases; ++k) {
+    const qsgs_status st =
+        generate_impl(1, dims, &phases[k], &d_labels, d_ws, ws_bytes, &infos[k], s, true);
+    if (st < 0) return st;
+    worst = std::max(worst, (int32_t)st);
+    ByteMap m{};  // the phase's cells become walls for the phases after it
+    for (int b = 0; b < 256; ++b) m.lut[b] = (uint8_t)b;
+    m.lut[1] = (uint8_t)(kWallBase + 1 + k);
+    hipLaunchKernelGGL(k_map_bytes, mg, mb, 0, s, (uint32_t*)d_labels, words, m);
+    QSGS_LAUNCHED("k_map_bytes");
+  }
+  ByteMap m{};  // walls 3 + n -> label n
+  for (int b = 0; b < 256; ++b) m.lut[b] = (uint8_t)b;
+  for (int32_t k = 1; k <= n_phases; ++k) m.lut[kWallBase + k] = (uint8_t)k;
+  hipLaunchKernelGGL(k_map_bytes, mg, mb, 0, s, (uint32_t*)d_labels, words, m);
+  QSGS_LAUNCHED("k_map_bytes");
+  QSGS_HIP(hipStreamSynchronize(s));
+  return (qsgs_status)worst;
 }
 
 }  // extern "C"

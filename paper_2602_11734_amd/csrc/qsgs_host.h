@@ -319,7 +319,7 @@ inline uint32_t resident_sweep_grid(uint32_t block) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep, (int)block,
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<false>, (int)block,
                                                    sweep_lds_bytes(block)) != hipSuccess ||
       cus <= 0 || per_cu <= 0) {
     (void)hipGetLastError();
@@ -691,7 +691,10 @@ struct Engine {
       e1 = prof_event();
       QSGS_HIP(hipEventRecord(e0, s));
     }
-    hipLaunchKernelGGL(k_sweep, dim3(sweep_grid), dim3(tune.grow_block),
+    bool walls = false;
+    for (const Real& R : reals) walls = walls || R.walls != 0;
+    hipLaunchKernelGGL(walls ? k_sweep<true> : k_sweep<false>, dim3(sweep_grid),
+                       dim3(tune.grow_block),
                        sweep_lds_bytes(tune.grow_block), s, args);
     QSGS_LAUNCHED("k_sweep");
     if (ev) {

@@ -124,6 +124,8 @@ struct Real {
   uint64_t t_seed;
   int32_t spacing;
   uint32_t phase;
+  uint32_t walls;       // the grid holds other phases' cells (bytes >= 4): never cores,
+                        // sources or targets; seeding keeps the grid instead of clearing it
   Ctl ctl;
 };
 
@@ -212,8 +214,15 @@ __global__ void k_rollback(uint8_t* grid, uint32_t n);
 __global__ void k_seed_tiles(BatchArgs A);
 __global__ void k_full_tiles(BatchArgs A);
 __global__ void k_sweep_prepare(BatchArgs A);
-__global__ void k_sweep(BatchArgs A);  // dynamic LDS: sweep_lds_bytes(blockDim.x)
+// dynamic LDS: sweep_lds_bytes(blockDim.x); kWalls: the grids may hold other phases' cells
+template <bool kWalls> __global__ void k_sweep(BatchArgs A);
 size_t sweep_lds_bytes(uint32_t block);
 __global__ void k_sweep_end(BatchArgs A);
+
+// Byte relabelling table of k_map_bytes (passed by value).
+struct ByteMap {
+  uint8_t lut[256];
+};
+__global__ void k_map_bytes(uint32_t* words, uint32_t n_words, ByteMap m);
 
 }  // namespace qsgs

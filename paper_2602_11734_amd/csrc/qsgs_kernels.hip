@@ -271,6 +271,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
   typedef __attribute__((address_space(1))) uint8_t gbyte;
   typedef __attribute__((address_space(1))) uint32_t gword;
   uint32_t cr = 0xFFFFFFFFu, n = 0, k0 = 0, k1 = 0, tiles = 0;
+  bool walls = false;
   uint64_t t_seed = 0;
   gbyte* grid = nullptr;
   gword* stamp = nullptr;
@@ -286,6 +287,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
       grid = (gbyte*)uniform64((uint64_t)R.grid);
       stamp = (gword*)uniform64((uint64_t)R.stamp);
       tiles = uniform(R.tl.n);
+      walls = uniform(R.walls) != 0;
       cand_list = (int32_t*)uniform64((uint64_t)R.cand);
       n_cand = &R.ctl.n_cand;
       cr = r;
@@ -294,7 +296,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
     if (v < n) {
       const U4 w = philox10(v, 0u, 0u, kTagSeed, k0, k1);
       cand = (uint64_t)w.x < t_seed;
-      grid[v] = kVoid;
+      if (walls)  // a later phase: cores only on cells no earlier phase holds
+        cand = cand && grid[v] == kVoid;
+      else
+        grid[v] = kVoid;
       if (stamp && v < tiles) stamp[v] = 0;  // fused sweep: no tile listed yet
     }
     const uint32_t pos = wave_append_flag(cand, n_cand);
@@ -1249,9 +1254,12 @@ __device__ __forceinline__ void wave_sync() {
 size_t sweep_lds_bytes(uint32_t block) { return sizeof(TileImage) * (block / kWave); }
 
 // Each wavefront sweeps whole tiles on its own (no workgroup barrier per tile); the
-// workgroup resolves its share of list entries into LDS 64 at a time.
+// workgroup resolves its share of list entries into LDS 64 at a time.  kWalls: the
+// grids may hold other phases' cells (multi-phase generation), so "solid" is tested
+// as such instead of as "not void".
 // At most 96 VGPRs: five waves per SIMD, the occupancy the per-wave LDS images
 // (< 8 KB each) allow at the default 256-thread workgroup.
+template <bool kWalls>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5)))
 void k_sweep(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char sweep_lds[];
@@ -1461,10 +1469,12 @@ void k_sweep(BatchArgs A) {
               if (hy >= 1 && hy <= kTileY && hz >= 1 && hz <= kTileZ) {
                 // (interior rows lie in the domain in y and z: rmask is xin)
                 const uint32_t i = (uint32_t)((hy - 1) + kTileY * (hz - 1));
-                const uint64_t Sm = rmask & ~V;
+                const uint64_t Pm = __ballot(b == pmark) & rmask;
+                // solid: 1 or grown in the previous step (with other phases' cells in
+                // the grid, "not void" is not enough)
+                const uint64_t Sm = kWalls ? (__ballot(b == kSolid) & rmask) | Pm : rmask & ~V;
                 rs_lo = write_lane(rs_lo, (uint32_t)Sm, i);
                 rs_hi = write_lane(rs_hi, (uint32_t)(Sm >> 32), i);
-                const uint64_t Pm = __ballot(b == pmark) & rmask;
                 if (Pm) {  // grown in the previous step: fold to 1
                   if (b == pmark && lane_in) {
                     const uint32_t q = yrow(y0 - 1 + hy) + zrow(z0 - 1 + hz) + vx;
@@ -1669,6 +1679,9 @@ void k_sweep(BatchArgs A) {
   }
 }
 
+template __global__ void k_sweep<false>(BatchArgs A);
+template __global__ void k_sweep<true>(BatchArgs A);
+
 // End of a fused pass (one workgroup of 1024 threads, launched after k_sweep): sums
 // every workgroup's kept count and part fill per realization in LDS, writes the tail
 // segments, ends the step for every active realization (a6: log, count, status,
@@ -1755,6 +1768,20 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
   __syncthreads();
   plan_assign(A, p ^ 1u);
   if (threadIdx.x == 0) A.bctl->plan = p ^ 1u;
+}
+
+// Relabelling of a whole grid (multi-phase generation, Sec. 2.1 steps 4-5): every byte b
+// becomes lut[b].  n_words 32-bit words (the grid's padding included: lut[0] must be 0).
+__global__ __launch_bounds__(256) void k_map_bytes(uint32_t* __restrict__ words,
+                                                   uint32_t n_words, ByteMap m) {
+  __shared__ uint32_t t[256];
+  t[threadIdx.x] = m.lut[threadIdx.x];
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n_words; i += gridDim.x * 256u) {
+    const uint32_t x = words[i];
+    words[i] = t[x & 255u] | t[(x >> 8) & 255u] << 8 | t[(x >> 16) & 255u] << 16 |
+               t[x >> 24] << 24;
+  }
 }
 
 }  // namespace qsgs

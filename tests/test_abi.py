@@ -112,6 +112,32 @@ def test_invalid_dims_and_pointers(q):
                          None) == q.ERR_INVALID
 
 
+def test_phases_arguments_checked(q):
+    """Multi-phase queries and argument checks (nothing is launched)."""
+    dims = (16, 16, 16)
+    p1 = q.make_params(0.3, 0.01, (0.1, 0.05, 0.01), 3, 1)
+    p2 = q.make_params(0.2, 0.01, (0.1, 0.05, 0.01), 30, 2)
+    w1, w2 = q.qsgs_workspace_bytes(dims, p1), q.qsgs_workspace_bytes(dims, p2)
+    assert q.qsgs_phases_workspace_bytes(dims, [p1, p2]) == max(w1, w2)
+    assert q.qsgs_phases_workspace_bytes(dims, [p1]) == w1
+    bad = q.make_params(1.5, 0.01, (0.1, 0.05, 0.01), 3, 1)
+    assert q.qsgs_phases_workspace_bytes(dims, [p1, bad]) == 0
+    lib = q.load()
+    d = ctypes.byref(q.make_dims(dims))
+    arr = (q.qsgs_params * 2)(p1, p2)
+    infos = (q.qsgs_info * 2)()
+    assert lib.qsgs_phases_workspace_bytes(d, 0, arr) == 0
+    assert lib.qsgs_phases_workspace_bytes(d, 253, arr) == 0
+    assert lib.qsgs_generate_phases(d, 0, arr, 256, 256, 1 << 24, infos, None) == q.ERR_INVALID
+    assert lib.qsgs_generate_phases(d, 2, arr, None, 256, 1 << 24, infos, None) == q.ERR_INVALID
+    assert lib.qsgs_generate_phases(d, 2, arr, 258, 256, 1 << 24, infos, None) == q.ERR_INVALID
+    assert "aligned" in q.qsgs_last_error()
+    assert lib.qsgs_generate_phases(d, 2, arr, 256, 256, 16, infos, None) == q.ERR_WORKSPACE
+    arr_bad = (q.qsgs_params * 2)(p1, bad)
+    assert lib.qsgs_generate_phases(d, 2, arr_bad, 256, 256, 1 << 24, infos,
+                                    None) == q.ERR_INVALID
+
+
 def test_finished_state_is_a_noop(q):
     """A grow step on a state whose status is already terminal returns it untouched
     without launching anything (so it runs on a machine without a GPU)."""

@@ -154,3 +154,49 @@ def small_cases() -> list[Case]:
         Case("key_high_bits", (45, 41, 39), 0.7, 0.006, g, 6, 0xFFFF_FFFF_0000_0001),
         Case("two_voxels", (2, 1, 1), 1.0, 0.5, (0.5, 0.5, 0.5), 0, 24),
     ]
+
+
+@dataclass(frozen=True)
+class PhaseSet:
+    """A multi-phase generation (Sec. 2.1 steps 1-5): growing phases in order, phase
+    n = index + 1; each Case gives that phase's target fraction P^n (solid_fraction),
+    core probability (seed_prob), growth probabilities, spacing, key and step cap."""
+    name: str
+    dims: tuple
+    phases: tuple
+
+
+def _ph(sf, sd, g, s, key, max_steps=0) -> Case:
+    return Case(f"phase_k{key}", (0, 0, 0), sf, sd, g, s, key, max_steps)
+
+
+def phase_sets() -> list[PhaseSet]:
+    """Small multi-phase cases for element-by-element parity: three phases over several
+    tiles; a ragged grid; a phase whose target the earlier phases make unreachable
+    (exhausted); a phase without cores; a phase stopped by its step cap."""
+    g1, g2, g3 = (0.02, 0.005, 0.00125), (0.03, 0.01, 0.002), (0.01, 0.0025, 0.000625)
+    return [
+        PhaseSet("mp3_40x36x30", (40, 36, 30),
+                 (_ph(0.30, 0.004, g1, 4, 11), _ph(0.20, 0.003, g2, 3, 12),
+                  _ph(0.15, 0.002, g1, 0, 13))),
+        PhaseSet("mp2_97x70x45", (97, 70, 45),
+                 (_ph(0.50, 0.002, g3, 6, 21), _ph(0.30, 0.001, g1, 4, 22))),
+        PhaseSet("mp2_blocked_48x40x33", (48, 40, 33),
+                 (_ph(0.70, 0.003, g1, 3, 31), _ph(0.50, 0.002, g1, 2, 32))),
+        PhaseSet("mp3_nocores_20", (20, 20, 20),
+                 (_ph(0.40, 0.01, g1, 2, 41), _ph(0.30, 0.0, g1, 2, 42),
+                  _ph(0.20, 0.02, g2, 0, 43))),
+        PhaseSet("mp2_cap_33x29x31", (33, 29, 31),
+                 (_ph(0.35, 0.003, g1, 3, 51, 4), _ph(0.25, 0.004, g2, 2, 52, 3))),
+    ]
+
+
+def phase_bench() -> PhaseSet:
+    """Three-phase 400^3 medium: a grain phase as in the paper's timing runs (P 0.50,
+    S_d 5e-4, s = 20, G_ref 0.01 / 0.0025 / 0.000625), a sparse second mineral (P 0.15,
+    S_d 1e-4, s = 10) and a fine-grained third phase (P 0.05, S_d 2e-3, no spacing,
+    face 0.02); keys 1, 2, 3."""
+    g = (0.01, 0.0025, 0.000625)
+    return PhaseSet("mp3_400", (400, 400, 400),
+                    (_ph(0.50, 5e-4, g, 20, 1), _ph(0.15, 1e-4, g, 10, 2),
+                     _ph(0.05, 2e-3, g_from_face(0.02), 0, 3)))
