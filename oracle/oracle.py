@@ -41,7 +41,8 @@ def build(force: bool = False) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("solid_fraction", ctypes.c_double), ("seed_prob", ctypes.c_double),
                 ("g_ref", ctypes.c_double * 3), ("spacing", ctypes.c_int32),
-                ("max_steps", ctypes.c_int32), ("key", ctypes.c_uint64)]
+                ("max_steps", ctypes.c_int32), ("key", ctypes.c_uint64),
+                ("front_rule", ctypes.c_int32), ("unused", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -198,10 +199,13 @@ class OracleRun:
 
 
 def generate(dims, solid_fraction: float, seed_prob: float, g_ref, spacing: int, key: int,
-             max_steps: int = 0, birth: bool = False, log_cap: int = 0) -> OracleRun:
+             max_steps: int = 0, birth: bool = False, log_cap: int = 0,
+             literal_front: bool = False) -> OracleRun:
+    """``literal_front``: the next sources are this step's new cells with a void
+    neighbour (Algorithm 3 as printed) instead of the whole interface."""
     nx, ny, nz = dims
     p = _Params(float(solid_fraction), float(seed_prob), (ctypes.c_double * 3)(*g_ref),
-                int(spacing), int(max_steps), int(key))
+                int(spacing), int(max_steps), int(key), 1 if literal_front else 0, 0)
     res = _Result()
     grid = np.zeros((nz, ny, nx), dtype=np.uint8)
     b = np.zeros((nz, ny, nx), dtype=np.int32) if birth else None
@@ -242,7 +246,7 @@ def generate_phases(dims, phases) -> tuple[np.ndarray, list[PhaseResult]]:
         sf, sd, g, sp, key = ph[:5]
         ms = ph[5] if len(ph) > 5 else 0
         arr[i] = _Params(float(sf), float(sd), (ctypes.c_double * 3)(*g), int(sp), int(ms),
-                         int(key))
+                         int(key), 0, 0)
     res = (_Result * k)()
     labels = np.zeros((nz, ny, nx), dtype=np.uint8)
     lib().orc_generate_phases(nx, ny, nz, k, arr, _ptr(labels), res)

@@ -410,6 +410,13 @@ static int32_t generate_on(int32_t nx, int32_t ny, int32_t nz, const orc_params*
     int64_t n_new = 0;
     int64_t nA_next = orc_step_liets(nx, ny, nz, grid, A, nA, (uint32_t)t, T, p->key, A_next,
                                      &n_new, mask, added, NULL, NULL);
+    if (p->front_rule == 1) {
+      /* Algorithm 3 as printed: only this step's new cells that still have a void
+       * neighbour are the next step's sources (failed sources are dropped) */
+      nA_next = 0;
+      for (int64_t k = 0; k < n_new; ++k)
+        if (has_void_neighbour(nx, ny, nz, grid, added[k])) A_next[nA_next++] = added[k];
+    }
     if (t < log_cap) {
       if (log_front) log_front[t] = nA;
       if (log_new) log_new[t] = n_new;

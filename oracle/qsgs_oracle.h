@@ -48,6 +48,9 @@ typedef struct {
   int32_t  spacing;        /* s: minimum pairwise L1 seed distance; s <= 1 = none  */
   int32_t  max_steps;      /* <= 0 selects ORC_DEFAULT_MAX_STEPS                    */
   uint64_t key;            /* Philox key: k0 = low 32 bits, k1 = high 32 bits      */
+  int32_t  front_rule;     /* 0: A <- prune(A u A_new) (the interface); 1: the     */
+                           /* literal Algorithm 3 rule A <- prune(A_new)           */
+  int32_t  unused;
 } orc_params;
 
 typedef struct {

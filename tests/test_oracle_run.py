@@ -150,3 +150,69 @@ def test_step_work_log_matches_front_counts(orc, dims, spacing, key):
         assert int(front.sum()) == run.log_front[t]
         assert int(nv[front].sum()) == run.log_draws[t]
         assert int(((nv[front] + 7) // 8).sum()) == run.log_blocks[t]
+
+
+def _replay_literal(orc, dims, run, key, g_ref):
+    """Birth-map replay of the literal Algorithm 3 front (A <- prune(A_new)): the
+    sources of step 0 are the seeds, those of step t >= 1 the cells grown in step t - 1;
+    a cell is born at t + 1 iff some source has a passing draw to it (rank over the
+    source's void neighbours at the step's start)."""
+    nx, ny, nz = dims
+    birth = run.birth.ravel()
+    s_star = run.target_count
+    t_ref = [orc.prob_threshold(g) for g in g_ref]
+    offs = ref_tiny.OFFSETS
+    for t in range(run.steps):
+        solid = (birth >= 0) & (birth <= t)
+        cnt = int(solid.sum())
+        T = [orc.growth_threshold(tr, cnt, s_star) for tr in t_ref]
+        sources = np.flatnonzero(birth == t)
+        grown = set()
+        for a in sources:
+            ax, ay, az = a % nx, (a // nx) % ny, a // (nx * ny)
+            j = 0
+            for d, (dx, dy, dz) in enumerate(offs):
+                qx, qy, qz = ax + dx, ay + dy, az + dz
+                if not (0 <= qx < nx and 0 <= qy < ny and 0 <= qz < nz):
+                    continue
+                q = qx + nx * (qy + ny * qz)
+                if solid[q]:
+                    continue
+                if orc.growth_draw(key, int(a), t, j) < T[ref_tiny.CLASSES[d]]:
+                    grown.add(int(q))
+                j += 1
+        born = set(int(v) for v in np.flatnonzero(birth == t + 1))
+        assert born == grown, t
+
+
+def test_literal_front_replays_exactly(orc):
+    dims = (13, 12, 10)
+    g_ref = (0.06, 0.02, 0.005)
+    run = orc.generate(dims, 0.6, 0.01, g_ref, 2, key=77, birth=True, log_cap=10000,
+                       literal_front=True)
+    assert run.steps >= 3
+    _replay_literal(orc, dims, run, 77, g_ref)
+
+
+def test_literal_front_dies_out_at_paper_like_parameters(orc):
+    """At moderate growth probabilities the literal rule drops failed sources and the
+    front empties before the target (the reason for the interface reading)."""
+    dims = (48, 48, 48)
+    g = (0.01, 0.0025, 0.000625)
+    lit = orc.generate(dims, 0.8, 0.001, g, 4, key=3, literal_front=True)
+    ref = orc.generate(dims, 0.8, 0.001, g, 4, key=3)
+    assert ref.status == orc.DONE
+    assert lit.status == orc.EXHAUSTED and lit.solid_count < lit.target_count
+    assert lit.n_seeds == ref.n_seeds
+
+
+def test_literal_front_equals_interface_rule_when_every_draw_passes(orc):
+    """With every probability 1 each source grows into all its void neighbours, so an
+    old source has none left: prune(A u A_new) = prune(A_new) and the runs coincide."""
+    dims = (21, 17, 15)
+    for key, sp in ((5, 0), (6, 3)):
+        a = orc.generate(dims, 0.9, 0.003, (1.0, 1.0, 1.0), sp, key, log_cap=1000)
+        b = orc.generate(dims, 0.9, 0.003, (1.0, 1.0, 1.0), sp, key, log_cap=1000,
+                         literal_front=True)
+        assert np.array_equal(a.grid, b.grid) and a.steps == b.steps
+        assert np.array_equal(a.log_front, b.log_front)
