@@ -214,6 +214,25 @@ def voxel_list_step_api(q, torch, case):
             "identical_outputs": bool(torch.equal(steps_grid, b.grid[:n]))}
 
 
+def front_rules(q, torch, case):
+    """The two front rules on one 400^3 realization: the interface, prune(F_t u New_t),
+    against Algorithm 3 as printed, prune(New_t) (failed sources dropped)."""
+    out = {"workload": case.name}
+    for rule, lit in (("interface", False), ("literal_alg3", True)):
+        p = q.params_of(case, literal_front=lit)
+        b = q.alloc(case.dims, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = q.qsgs_generate(case.dims, p, b.grid, b.ws, b.ws_bytes)
+        torch.cuda.synchronize()
+        out[rule] = {"generation_ms": (time.perf_counter() - t0) * 1e3,
+                     "status": q.STATUS_NAMES[st], "steps": info.step,
+                     "solid_fraction": info.solid_count / case.n,
+                     "target_fraction": case.solid_fraction}
+        del b
+    return out
+
+
 def multiphase(q, torch):
     """Three independent growing phases in sequence on one 400^3 label grid (Sec. 2.1
     steps 1-5): wall time of qsgs_generate_phases and voxels grown per second over all
@@ -404,6 +423,7 @@ def main():
         out["detail"]["list_vs_full_field"] = [
             list_vs_full_field(q, torch, cases[1]),
             list_vs_full_field(q, torch, workloads.config4_singletons()[3])]
+        out["detail"]["front_rules"] = front_rules(q, torch, cases[1])
     if not args.no_batch:
         out["detail"]["batched"] = batched_vs_plain(q, torch)
     if not args.no_phases:

@@ -75,7 +75,11 @@ typedef struct {
                           /* 1 = full-field sweep (Alg. 2: every tile, every step).  Results  */
                           /* are identical; the full-field form is the baseline for the      */
                           /* list-indexed one.  Ignored by qsgs_seed / qsgs_grow_step.         */
-  int32_t  reserved;      /* must be 0                                                      */
+  int32_t  front_rule;    /* whole-generation calls only: 0 = the next front is the        */
+                          /* interface, prune(F_t u New_t) (Sec. 2.3 steps 2 and 4: failed   */
+                          /* sources stay); 1 = Algorithm 3 as printed, prune(New_t): only   */
+                          /* this step's new voxels are the next sources.  qsgs_grow_step    */
+                          /* rejects 1 (QSGS_ERR_INVALID).                                   */
 } qsgs_params;
 
 typedef struct {

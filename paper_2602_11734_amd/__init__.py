@@ -36,7 +36,7 @@ class qsgs_params(ctypes.Structure):
     _fields_ = [("solid_fraction", ctypes.c_double), ("seed_prob", ctypes.c_double),
                 ("g_ref", ctypes.c_double * 3), ("spacing", ctypes.c_int32),
                 ("max_steps", ctypes.c_int32), ("key", ctypes.c_uint64),
-                ("full_field", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("full_field", ctypes.c_int32), ("front_rule", ctypes.c_int32)]
 
 
 class qsgs_info(ctypes.Structure):
@@ -123,15 +123,18 @@ def make_dims(dims) -> qsgs_dims:
 
 
 def make_params(solid_fraction: float, seed_prob: float, g_ref, spacing: int, key: int,
-                max_steps: int = 0, full_field: bool = False) -> qsgs_params:
+                max_steps: int = 0, full_field: bool = False,
+                literal_front: bool = False) -> qsgs_params:
+    """``literal_front``: Algorithm 3's front rule prune(New_t) instead of the interface."""
     g = (ctypes.c_double * 3)(*[float(v) for v in g_ref])
     return qsgs_params(float(solid_fraction), float(seed_prob), g, int(spacing), int(max_steps),
-                       int(key) & 0xFFFFFFFFFFFFFFFF, 1 if full_field else 0, 0)
+                       int(key) & 0xFFFFFFFFFFFFFFFF, 1 if full_field else 0,
+                       1 if literal_front else 0)
 
 
-def params_of(case, full_field: bool = False) -> qsgs_params:
+def params_of(case, full_field: bool = False, literal_front: bool = False) -> qsgs_params:
     return make_params(case.solid_fraction, case.seed_prob, case.g_ref, case.spacing, case.key,
-                       case.max_steps, full_field)
+                       case.max_steps, full_field, literal_front)
 
 
 def _ptr(x) -> int | None:

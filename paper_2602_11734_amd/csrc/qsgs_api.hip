@@ -169,6 +169,8 @@ qsgs_status qsgs_grow_step(const qsgs_dims* dims, const qsgs_params* params, uin
   Geometry g{};
   QSGS_TRY(check_dims(dims, &g));
   QSGS_TRY(check_params(params));
+  if (params->front_rule != 0)
+    return fail(QSGS_ERR_INVALID, "front_rule 1 is for the whole-generation calls");
   QSGS_TRY(check_grid(d_grid));
   if (!d_front_in || !d_front_out || d_front_in == d_front_out || front_cap < 0)
     return fail(QSGS_ERR_INVALID, "bad front buffers / front_cap");

@@ -121,7 +121,8 @@ inline qsgs_status check_params(const qsgs_params* p) {
   if (p->spacing < 0) return fail(QSGS_ERR_INVALID, "spacing must be >= 0");
   if (p->full_field != 0 && p->full_field != 1)
     return fail(QSGS_ERR_INVALID, "full_field must be 0 or 1");
-  if (p->reserved != 0) return fail(QSGS_ERR_INVALID, "reserved must be 0");
+  if (p->front_rule != 0 && p->front_rule != 1)
+    return fail(QSGS_ERR_INVALID, "front_rule must be 0 or 1");
   return QSGS_OK;
 }
 
@@ -319,7 +320,8 @@ inline uint32_t resident_sweep_grid(uint32_t block) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<false>, (int)block,
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<false, false>,
+                                                   (int)block,
                                                    sweep_lds_bytes(block)) != hipSuccess ||
       cus <= 0 || per_cu <= 0) {
     (void)hipGetLastError();
@@ -479,6 +481,7 @@ struct Engine {
                 2 * make_tiles(sp.g).n);
     reals[r].stamp = at<uint32_t>(sweep, 2 * lb);
     reals[r].full = (uint32_t)p->full_field;
+    reals[r].literal = (uint32_t)p->front_rule;
   }
 
   qsgs_status upload_header() {
@@ -691,10 +694,14 @@ struct Engine {
       e1 = prof_event();
       QSGS_HIP(hipEventRecord(e0, s));
     }
-    bool walls = false;
-    for (const Real& R : reals) walls = walls || R.walls != 0;
-    hipLaunchKernelGGL(walls ? k_sweep<true> : k_sweep<false>, dim3(sweep_grid),
-                       dim3(tune.grow_block),
+    bool walls = false, literal = false;
+    for (const Real& R : reals) {
+      walls = walls || R.walls != 0;
+      literal = literal || R.literal != 0;
+    }
+    auto kernel = walls ? (literal ? k_sweep<true, true> : k_sweep<true, false>)
+                        : (literal ? k_sweep<false, true> : k_sweep<false, false>);
+    hipLaunchKernelGGL(kernel, dim3(sweep_grid), dim3(tune.grow_block),
                        sweep_lds_bytes(tune.grow_block), s, args);
     QSGS_LAUNCHED("k_sweep");
     if (ev) {

@@ -126,6 +126,7 @@ struct Real {
   uint32_t phase;
   uint32_t walls;       // the grid holds other phases' cells (bytes >= 4): never cores,
                         // sources or targets; seeding keeps the grid instead of clearing it
+  uint32_t literal;     // front rule: the next sources are only this step's new voxels
   Ctl ctl;
 };
 
@@ -214,8 +215,9 @@ __global__ void k_rollback(uint8_t* grid, uint32_t n);
 __global__ void k_seed_tiles(BatchArgs A);
 __global__ void k_full_tiles(BatchArgs A);
 __global__ void k_sweep_prepare(BatchArgs A);
-// dynamic LDS: sweep_lds_bytes(blockDim.x); kWalls: the grids may hold other phases' cells
-template <bool kWalls> __global__ void k_sweep(BatchArgs A);
+// dynamic LDS: sweep_lds_bytes(blockDim.x); kWalls: the grids may hold other phases' cells;
+// kLiteral: some realizations take only the previous step's new voxels as sources
+template <bool kWalls, bool kLiteral> __global__ void k_sweep(BatchArgs A);
 size_t sweep_lds_bytes(uint32_t block);
 __global__ void k_sweep_end(BatchArgs A);
 

@@ -1256,10 +1256,12 @@ size_t sweep_lds_bytes(uint32_t block) { return sizeof(TileImage) * (block / kWa
 // Each wavefront sweeps whole tiles on its own (no workgroup barrier per tile); the
 // workgroup resolves its share of list entries into LDS 64 at a time.  kWalls: the
 // grids may hold other phases' cells (multi-phase generation), so "solid" is tested
-// as such instead of as "not void".
+// as such instead of as "not void".  kLiteral: a realization with the literal front
+// rule takes as sources, from its second step on, only the voxels grown in the
+// previous step (they still carry that step's mark when the tile is staged).
 // At most 96 VGPRs: five waves per SIMD, the occupancy the per-wave LDS images
 // (< 8 KB each) allow at the default 256-thread workgroup.
-template <bool kWalls>
+template <bool kWalls, bool kLiteral>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5)))
 void k_sweep(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char sweep_lds[];
@@ -1319,6 +1321,8 @@ void k_sweep(BatchArgs A) {
     const uint32_t t = uniform((uint32_t)c.step);
     const bool run = uniform(c.mode) == kModeRun;
     const uint32_t mark = kGrown + (t & 1u), pmark = mark ^ 1u;
+    // all ones where the solid rows are the previous step's new voxels only
+    const uint64_t lit = kLiteral && uniform(R.literal) != 0 && t > 0 ? ~0ull : 0ull;
     const DrawThresholds th =
         draw_thresholds(uniform64(c.T[0]), uniform64(c.T[1]), uniform64(c.T[2]));
     if (threadIdx.x < 26u) {  // read after the first barrier
@@ -1472,7 +1476,8 @@ void k_sweep(BatchArgs A) {
                 const uint64_t Pm = __ballot(b == pmark) & rmask;
                 // solid: 1 or grown in the previous step (with other phases' cells in
                 // the grid, "not void" is not enough)
-                const uint64_t Sm = kWalls ? (__ballot(b == kSolid) & rmask) | Pm : rmask & ~V;
+                uint64_t Sm = kWalls ? (__ballot(b == kSolid) & rmask) | Pm : rmask & ~V;
+                if (kLiteral) Sm = (Pm & lit) | (Sm & ~lit);
                 rs_lo = write_lane(rs_lo, (uint32_t)Sm, i);
                 rs_hi = write_lane(rs_hi, (uint32_t)(Sm >> 32), i);
                 if (Pm) {  // grown in the previous step: fold to 1
@@ -1679,8 +1684,10 @@ void k_sweep(BatchArgs A) {
   }
 }
 
-template __global__ void k_sweep<false>(BatchArgs A);
-template __global__ void k_sweep<true>(BatchArgs A);
+template __global__ void k_sweep<false, false>(BatchArgs A);
+template __global__ void k_sweep<true, false>(BatchArgs A);
+template __global__ void k_sweep<false, true>(BatchArgs A);
+template __global__ void k_sweep<true, true>(BatchArgs A);
 
 // End of a fused pass (one workgroup of 1024 threads, launched after k_sweep): sums
 // every workgroup's kept count and part fill per realization in LDS, writes the tail

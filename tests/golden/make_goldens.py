@@ -4,9 +4,10 @@ Calls only the CPU oracle (``oracle/``) on the inputs stated in ``workloads.py``
 GPU tests compare the library's outputs with these stored values.  Each entry holds
 the SHA-256 of the final grid (N bytes, C order), the counts, the terminal status and
 the per-step series |F_t|, |New_t|, the solid count at the start of each step and the
-step's work (draws, high-half Philox blocks).
+step's work (draws, high-half Philox blocks).  The group ``lit`` runs cases with the
+literal Algorithm 3 front rule (entries named ``<case>_literal``, ``literal_front`` true).
 
-    python tests/golden/make_goldens.py [--jobs 8] [--only c2,c3]
+    python tests/golden/make_goldens.py [--jobs 8] [--only c2,c3,lit]
 """
 from __future__ import annotations
 
@@ -27,13 +28,15 @@ from oracle import oracle  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_runs.json")
 
 
-def run_case(case_dict: dict) -> dict:
+def run_case(job: tuple) -> dict:
+    case_dict, literal = job
     c = workloads.Case(**{**case_dict, "dims": tuple(case_dict["dims"]),
                           "g_ref": tuple(case_dict["g_ref"])})
     t0 = time.time()
     r = oracle.generate(c.dims, c.solid_fraction, c.seed_prob, c.g_ref, c.spacing, c.key,
-                        max_steps=c.max_steps, log_cap=100000)
+                        max_steps=c.max_steps, log_cap=100000, literal_front=literal)
     return {
+        "name": c.name + ("_literal" if literal else ""), "literal_front": literal,
         "case": c.as_dict(),
         "grid_sha256": hashlib.sha256(r.grid.tobytes()).hexdigest(),
         "n_candidates": r.n_candidates, "n_seeds": r.n_seeds, "solid_count": r.solid_count,
@@ -53,20 +56,22 @@ def main():
     args = ap.parse_args()
     oracle.build()
     groups = {"c1": workloads.config1, "c2": workloads.config2, "c3": workloads.config3,
-              "c4": workloads.config4, "c4s": workloads.config4_singletons}
+              "c4": workloads.config4, "c4s": workloads.config4_singletons,
+              "lit": lambda: workloads.config1() + workloads.config2()[:1] +
+              workloads.config3()[1:2]}
     cases = []
     for g in args.only.split(","):
-        cases += groups[g]()
+        cases += [(c, g == "lit") for c in groups[g]()]
     existing = {}
     if os.path.exists(OUT):
         with open(OUT) as f:
             existing = json.load(f)
     # largest first so the pool stays busy
-    cases.sort(key=lambda c: -c.n)
+    cases.sort(key=lambda cl: -cl[0].n)
     with ProcessPoolExecutor(max_workers=args.jobs) as ex:
-        for res in ex.map(run_case, [c.as_dict() for c in cases]):
-            existing[res["case"]["name"]] = res
-            print(res["case"]["name"], res["steps"], res["solid_count"], res["oracle_seconds"],
+        for res in ex.map(run_case, [(c.as_dict(), lit) for c, lit in cases]):
+            existing[res["name"]] = res
+            print(res["name"], res["steps"], res["solid_count"], res["oracle_seconds"],
                   flush=True)
             with open(OUT, "w") as f:
                 json.dump(existing, f, indent=1, sort_keys=True)

@@ -76,12 +76,17 @@ def test_sweep_form_flag_checked(q):
     p.full_field = 2
     assert q.qsgs_workspace_bytes((8, 8, 8), p) == 0
     p.full_field = 0
-    p.reserved = 7
+    p.front_rule = 7
     assert q.qsgs_workspace_bytes((8, 8, 8), p) == 0
     info = q.qsgs_info()
     st = q.load().qsgs_generate(ctypes.byref(q.make_dims((8, 8, 8))), ctypes.byref(p), 256,
                                 256, 1 << 20, ctypes.byref(info), None)
-    assert st == q.ERR_INVALID and "reserved" in q.qsgs_last_error()
+    assert st == q.ERR_INVALID and "front_rule" in q.qsgs_last_error()
+    p.front_rule = 1  # the literal rule: whole-generation calls only
+    assert q.qsgs_workspace_bytes((8, 8, 8), p) > 0
+    st = q.load().qsgs_grow_step(ctypes.byref(q.make_dims((8, 8, 8))), ctypes.byref(p), 256,
+                                 512, 1024, 100, 256, 1 << 20, ctypes.byref(info), None)
+    assert st == q.ERR_INVALID and "front_rule" in q.qsgs_last_error()
 
 
 def test_invalid_dims_and_pointers(q):

@@ -36,10 +36,11 @@ def say(*a):
     print(*a, flush=True)
 
 
-def run_gpu(q, case):
+def run_gpu(q, case, literal_front=False):
     import torch
-    say("GPU generate", case.name, case.dims, "key", case.key)
-    params = q.params_of(case)
+    say("GPU generate", case.name, case.dims, "key", case.key,
+        "literal front" if literal_front else "")
+    params = q.params_of(case, literal_front=literal_front)
     grid, info, buf = q.generate(case.dims, params)
     torch.cuda.synchronize()
     logs = q.qsgs_read_step_log(buf.ws, buf.ws_bytes) + q.qsgs_read_step_work(buf.ws,
@@ -225,7 +226,7 @@ def _golden_check(q, entry):
     import torch
     c = entry["case"]
     case = workloads.Case(**{**c, "dims": tuple(c["dims"]), "g_ref": tuple(c["g_ref"])})
-    got, info, (lf, ln, lc, ld, lb) = run_gpu(q, case)
+    got, info, (lf, ln, lc, ld, lb) = run_gpu(q, case, entry.get("literal_front", False))
     assert info["status"] == entry["status"]
     assert info["n_candidates"] == entry["n_candidates"]
     assert info["n_seeds"] == entry["n_seeds"]
@@ -478,3 +479,51 @@ def test_phases_at_400_cube_properties(q):
         assert i3[k]["status"] in (q.DONE, q.EXHAUSTED)
         if k < 2:
             assert i3[k] == i2[k]
+
+
+# ----- the literal Algorithm 3 front rule, prune(New_t) -----
+
+LIT = workloads.small_cases()[::2] + workloads.config1()
+
+
+@pytest.mark.parametrize("full", [False, True], ids=["list", "full_field"])
+@pytest.mark.parametrize("case", LIT, ids=[c.name for c in LIT])
+def test_literal_front_matches_oracle(q, orc, case, full):
+    import torch
+    if full and case.name != LIT[0].name:
+        pytest.skip("full-field form with the literal rule checked on one case")
+    say("GPU generate (literal front)", case.name, case.dims, "full" if full else "list")
+    params = q.params_of(case, full_field=full, literal_front=True)
+    grid, info, buf = q.generate(case.dims, params)
+    torch.cuda.synchronize()
+    lf, ln, lc = q.qsgs_read_step_log(buf.ws, buf.ws_bytes)
+    ld, lb = q.qsgs_read_step_work(buf.ws, buf.ws_bytes)
+    ref = run_oracle(orc, case, literal_front=True)
+    assert info["status"] == ref.status and info["step"] == ref.steps
+    assert info["solid_count"] == ref.solid_count and info["front_size"] == ref.front_size
+    assert np.array_equal(lf, ref.log_front) and np.array_equal(ln, ref.log_new)
+    assert np.array_equal(lc, ref.log_count)
+    assert np.array_equal(ld, ref.log_draws) and np.array_equal(lb, ref.log_blocks)
+    assert np.array_equal(grid.cpu().numpy(), ref.grid)
+
+
+def test_batch_mixes_front_rules(q, orc):
+    """Realizations with either front rule in one batch: each equals its oracle run."""
+    import torch
+    cases = workloads.small_cases() + workloads.config1()
+    lit = [k % 2 == 0 for k in range(len(cases))]
+    params = [q.params_of(c, literal_front=f) for c, f in zip(cases, lit)]
+    dims = [c.dims for c in cases]
+    grids = [torch.empty(q.qsgs_grid_bytes(d), dtype=torch.uint8, device="cuda") for d in dims]
+    wsb = q.qsgs_batch_workspace_bytes(dims, params)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    say("GPU generate_batch (mixed front rules) of", len(cases))
+    st, infos = q.qsgs_generate_batch(dims, params, grids, ws, wsb)
+    torch.cuda.synchronize()
+    for c, f, g, info in zip(cases, lit, grids, infos):
+        ref = run_oracle(orc, c, literal_front=f)
+        nx, ny, nz = c.dims
+        got = g[: nx * ny * nz].view(nz, ny, nx).cpu().numpy()
+        assert info.status == ref.status and info.step == ref.steps, c.name
+        assert info.solid_count == ref.solid_count and info.front_size == ref.front_size, c.name
+        assert np.array_equal(got, ref.grid), c.name
