@@ -287,6 +287,13 @@ const char* qsgs_last_error(void);
 /* Library version string, e.g. "qsgs 0.1.0 gfx950". */
 const char* qsgs_version(void);
 
+/* Seed probability for a granular medium of grain diameter d and voxel size delta (same
+ * unit): S_d = 6 phi_s delta^3 / (pi d^3), the expected number of grains per voxel times
+ * one (Sec. 3.3, the rule used for the Fontainebleau samples).  Returns -1 for
+ * arguments outside phi_s in [0, 1], d > 0, delta > 0, and min(result, 1) otherwise. */
+double qsgs_seed_prob_from_grain(double solid_fraction, double grain_diameter,
+                                 double voxel_size);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,8 @@ SIGNATURES = {
     "qsgs_profile_read": (None, [_VP, _I32]),
     "qsgs_last_error": (ctypes.c_char_p, []),
     "qsgs_version": (ctypes.c_char_p, []),
+    "qsgs_seed_prob_from_grain": (ctypes.c_double, [ctypes.c_double, ctypes.c_double,
+                                                    ctypes.c_double]),
 }
 
 _lib = None
@@ -331,6 +333,16 @@ def qsgs_profile_read(reset: bool = False) -> dict:
 
 def qsgs_last_error() -> str:
     return load().qsgs_last_error().decode()
+
+
+def qsgs_seed_prob_from_grain(solid_fraction: float, grain_diameter: float,
+                              voxel_size: float) -> float:
+    """S_d = 6 phi_s delta^3 / (pi d^3) (Sec. 3.3); raises on invalid arguments."""
+    v = float(load().qsgs_seed_prob_from_grain(float(solid_fraction), float(grain_diameter),
+                                               float(voxel_size)))
+    if v < 0:
+        raise QsgsError(ERR_INVALID, "solid_fraction in [0, 1], grain and voxel size > 0")
+    return v
 
 
 def qsgs_version() -> str:

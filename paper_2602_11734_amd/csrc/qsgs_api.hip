@@ -417,4 +417,14 @@ const char* qsgs_last_error(void) { return last_error().c_str(); }
 
 const char* qsgs_version(void) { return "qsgs 0.2.0 gfx950"; }
 
+double qsgs_seed_prob_from_grain(double solid_fraction, double grain_diameter,
+                                 double voxel_size) {
+  if (!(solid_fraction >= 0.0 && solid_fraction <= 1.0) || !(grain_diameter > 0.0) ||
+      !(voxel_size > 0.0) || !std::isfinite(grain_diameter) || !std::isfinite(voxel_size))
+    return -1.0;
+  const double r = voxel_size / grain_diameter;
+  const double pi = 3.14159265358979323846;
+  return std::min(1.0, 6.0 * solid_fraction * r * r * r / pi);
+}
+
 }  // extern "C"

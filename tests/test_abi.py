@@ -164,3 +164,19 @@ def test_package_fails_loudly_without_library(tmp_path):
             q.load(str(tmp_path / "missing.so"))
     finally:
         q._lib = saved
+
+
+def test_seed_prob_from_grain(q):
+    """S_d = 6 phi_s delta^3 / (pi d^3) (Sec. 3.3): a grain of diameter d holds
+    pi d^3 / (6 delta^3) voxels, so phi_s N / that volume cores give the fraction phi_s."""
+    import math
+    v = q.qsgs_seed_prob_from_grain(0.8, 225.0, 4.0)
+    assert abs(v - 6 * 0.8 * 64 / (math.pi * 225.0**3)) < 1e-18
+    assert abs(v - 8.584e-6) < 1e-9
+    # one grain per voxel-sized sphere volume: d = delta (6/pi)^(1/3) gives phi_s
+    d = 4.0 * (6 / math.pi) ** (1 / 3)
+    assert abs(q.qsgs_seed_prob_from_grain(0.3, d, 4.0) - 0.3) < 1e-12
+    assert q.qsgs_seed_prob_from_grain(1.0, 1.0, 10.0) == 1.0  # capped
+    for bad in ((1.2, 200.0, 4.0), (0.5, 0.0, 4.0), (0.5, 200.0, -1.0)):
+        with pytest.raises(q.QsgsError):
+            q.qsgs_seed_prob_from_grain(*bad)
