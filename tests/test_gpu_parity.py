@@ -527,3 +527,22 @@ def test_batch_mixes_front_rules(q, orc):
         assert info.status == ref.status and info.step == ref.steps, c.name
         assert info.solid_count == ref.solid_count and info.front_size == ref.front_size, c.name
         assert np.array_equal(got, ref.grid), c.name
+
+
+def test_phases_at_the_label_limit(q, orc):
+    """252 phases (the largest label) on a small grid: labels, counts and statuses equal
+    the oracle's; the late phases find few free cells and exhaust."""
+    import torch
+    dims = (23, 19, 17)
+    g = (0.05, 0.02, 0.005)
+    tuples = [(0.004, 0.002, g, k % 4, 900 + k, 6) for k in range(252)]
+    params = [q.make_params(*t[:5], max_steps=t[5]) for t in tuples]
+    say("GPU generate_phases, 252 phases", dims)
+    labels, infos = q.generate_phases(dims, params)
+    torch.cuda.synchronize()
+    ref, res = orc.generate_phases(dims, tuples)
+    assert np.array_equal(labels.cpu().numpy(), ref)
+    assert int(ref.max()) > 200
+    for info, r in zip(infos, res):
+        assert (info["solid_count"], info["step"], info["status"], info["n_seeds"]) == \
+               (r.count, r.steps, r.status, r.n_seeds)
