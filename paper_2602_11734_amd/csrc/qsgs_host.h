@@ -545,7 +545,7 @@ struct Engine {
     const dim3 sg(tune.seed_grid), sb(tune.seed_block);
     hipLaunchKernelGGL(k_ctl_init, dim3(16), dim3(256), 0, s, args, 1u);
     QSGS_LAUNCHED("k_ctl_init");
-    QSGS_TRY(offsets(kItemsVoxels));
+    QSGS_TRY(offsets(kItemsQuads));
     hipLaunchKernelGGL(k_seed_draw, sg, sb, 0, s, args);
     QSGS_LAUNCHED("k_seed_draw");
     const uint32_t tb = L.total_buckets;

@@ -169,6 +169,7 @@ enum ItemKind : uint32_t {
   kItemsGrow = 3,    // F_t of running realizations
   kItemsPrune = 4,   // F_t + New_t of running realizations
   kItemsList = 5,    // L_t of realizations with a pending fused pass
+  kItemsQuads = 6,   // every aligned group of four voxels (seed draw)
 };
 
 struct BatchArgs {

@@ -28,6 +28,7 @@ __device__ __forceinline__ uint64_t items_of(const Real& R, uint32_t kind) {
   const bool growing = R.phase == kPhaseGrow && c.status == 0;
   switch (kind) {
     case kItemsVoxels: return seeding ? R.g.n : 0;
+    case kItemsQuads: return seeding ? (R.g.n + 3u) / 4u : 0;
     case kItemsCand: return seeding ? c.n_cand : 0;
     case kItemsSeeds: return seeding ? c.n_seeds : 0;
     case kItemsGrow: return growing ? c.front_size : 0;
@@ -277,7 +278,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
   gword* stamp = nullptr;
   int32_t* cand_list = nullptr;
   uint32_t* n_cand = nullptr;
-  for_each_chunk(A, kItemsVoxels, [&](uint32_t r, uint32_t v) {
+  // each lane takes the four voxels 4i .. 4i + 3: four independent blocks in flight and
+  // one word store of the grid (byte stores only for the last, partial group, so that
+  // the grid's padding is never written)
+  for_each_chunk(A, kItemsQuads, [&](uint32_t r, uint32_t i) {
     if (r != cr) {
       Real& R = A.reals[r];
       n = uniform(R.g.n);
@@ -292,18 +296,42 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
       n_cand = &R.ctl.n_cand;
       cr = r;
     }
-    bool cand = false;
-    if (v < n) {
-      const U4 w = philox10(v, 0u, 0u, kTagSeed, k0, k1);
-      cand = (uint64_t)w.x < t_seed;
-      if (walls)  // a later phase: cores only on cells no earlier phase holds
-        cand = cand && grid[v] == kVoid;
-      else
-        grid[v] = kVoid;
-      if (stamp && v < tiles) stamp[v] = 0;  // fused sweep: no tile listed yet
+    const uint32_t v0 = 4u * i;
+    uint32_t cand = 0;  // bit k: voxel v0 + k is a candidate
+    if (v0 < n) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t v = v0 + (uint32_t)k;
+        const U4 w = philox10(v, 0u, 0u, kTagSeed, k0, k1);
+        if (v < n && (uint64_t)w.x < t_seed) cand |= 1u << k;
+      }
+      const bool whole = v0 + 4u <= n;
+      if (walls) {  // a later phase: cores only on cells no earlier phase holds
+        uint32_t occ = 0;  // bit k: voxel v0 + k holds another phase
+        if (whole) {
+          const uint32_t b = *(const gword*)(grid + v0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) occ |= (((b >> (8 * k)) & 0xFFu) != kVoid ? 1u : 0u) << k;
+        } else {
+          for (uint32_t k = 0; v0 + k < n; ++k) occ |= (grid[v0 + k] != kVoid ? 1u : 0u) << k;
+        }
+        cand &= ~occ;
+      } else if (whole) {
+        *(gword*)(grid + v0) = 0u;  // kVoid x 4
+      } else {
+        for (uint32_t k = 0; v0 + k < n; ++k) grid[v0 + k] = kVoid;
+      }
+      if (stamp)  // fused sweep: no tile listed yet
+        for (uint32_t k = 0; k < 4u && v0 + k < tiles; ++k) stamp[v0 + k] = 0;
     }
-    const uint32_t pos = wave_append_flag(cand, n_cand);
-    if (cand) cand_list[pos] = (int32_t)v;  // capacity N: cannot overflow
+    if (__ballot(cand != 0)) {
+      uint32_t pos = wave_append((uint32_t)__builtin_popcount(cand), n_cand);
+      while (cand) {  // capacity N: cannot overflow
+        const int k = __builtin_ctz(cand);
+        cand &= cand - 1u;
+        cand_list[pos++] = (int32_t)(v0 + (uint32_t)k);
+      }
+    }
   });
 }
 
