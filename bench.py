@@ -24,9 +24,10 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-# 32-bit integer vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one op per lane
-# per cycle
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# 32-bit integer vector ALU: 256 CUs x 128 lanes x 2.4 GHz.  A SIMD issues one wave64
+# 32-bit instruction every two cycles (32 lanes per cycle, 4 SIMDs per CU): the rate behind
+# the published 157.3 TFLOP/s fp32 vector peak (one FMA = 2 flops per lane)
+ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 # algorithmic integer ops: a Philox4x32-10 block is 10 rounds of two 32x32->64
 # products (2 ops each), four XORs and two key additions; a draw extracts a 16-bit
 # half and compares it; a front voxel tests its 26 neighbours
