@@ -284,7 +284,7 @@ void qsgs_profile_read(double out[5], int32_t reset);
  * valid until the next library call on this thread. */
 const char* qsgs_last_error(void);
 
-/* Library version string, e.g. "qsgs 0.1.0 gfx950". */
+/* Library version string, e.g. "qsgs 0.3.0 gfx950". */
 const char* qsgs_version(void);
 
 /* Seed probability for a granular medium of grain diameter d and voxel size delta (same

@@ -415,7 +415,7 @@ void qsgs_profile_read(double out[5], int32_t reset) {
 
 const char* qsgs_last_error(void) { return last_error().c_str(); }
 
-const char* qsgs_version(void) { return "qsgs 0.2.0 gfx950"; }
+const char* qsgs_version(void) { return "qsgs 0.3.0 gfx950"; }
 
 double qsgs_seed_prob_from_grain(double solid_fraction, double grain_diameter,
                                  double voxel_size) {
