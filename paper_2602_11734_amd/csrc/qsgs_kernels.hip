@@ -1493,13 +1493,16 @@ void k_sweep(BatchArgs A) {
             for (int hy = 0; hy < kTileY + 2; ++hy) {
               const int hz = hz0 + dz;
               const uint32_t h = (uint32_t)(hy + (kTileY + 2) * hz);
-              const uint64_t rmask = ((rows_in >> h) & 1ull) ? xin : 0ull;
               const uint32_t b = bv[dz][hy];
-              const uint64_t V = (__ballot(b == kVoid) | __ballot(b == mark)) & rmask;
+              // (the domain mask of a halo row is applied by its lane when the windows
+              // are written)
+              const uint64_t V = __ballot(b == kVoid) | __ballot(b == mark);
               rv_lo = write_lane(rv_lo, (uint32_t)V, h);
               rv_hi = write_lane(rv_hi, (uint32_t)(V >> 32), h);
               if (hy >= 1 && hy <= kTileY && hz >= 1 && hz <= kTileZ) {
-                // (interior rows lie in the domain in y and z: rmask is xin)
+                // an interior row lies in the domain unless it is past the grid's end in
+                // y or z (a ragged last tile)
+                const uint64_t rmask = ((rows_in >> h) & 1ull) ? xin : 0ull;
                 const uint32_t i = (uint32_t)((hy - 1) + kTileY * (hz - 1));
                 const uint64_t Pm = __ballot(b == pmark) & rmask;
                 // solid: 1 or grown in the previous step (with other phases' cells in
@@ -1524,9 +1527,12 @@ void k_sweep(BatchArgs A) {
         const uint64_t lm = __ballot(inl && (bl == kVoid || bl == mark));
         const uint64_t rm = __ballot(inr && (br == kVoid || br == mark));
         if (lane < (uint32_t)kHaloRows) {
-          T.win[lane][0] = rv_lo << 1 | (uint32_t)((lm >> lane) & 1ull);
-          T.win[lane][1] = __builtin_amdgcn_alignbit(rv_hi, rv_lo, 31u);
-          T.win[lane][2] = rv_hi >> 31 | (uint32_t)((rm >> lane) & 1ull) << 1;
+          const bool rin = ((rows_in >> lane) & 1ull) != 0;
+          const uint32_t vlo = rin ? rv_lo & (uint32_t)xin : 0u;
+          const uint32_t vhi = rin ? rv_hi & (uint32_t)(xin >> 32) : 0u;
+          T.win[lane][0] = vlo << 1 | (uint32_t)((lm >> lane) & 1ull);
+          T.win[lane][1] = __builtin_amdgcn_alignbit(vhi, vlo, 31u);
+          T.win[lane][2] = vhi >> 31 | (uint32_t)((rm >> lane) & 1ull) << 1;
         }
         if (lane < (uint32_t)kTileRows) T.S[lane] = (uint64_t)rs_hi << 32 | rs_lo;
         wave_sync();
