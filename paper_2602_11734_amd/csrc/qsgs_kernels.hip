@@ -1553,30 +1553,20 @@ void k_sweep(BatchArgs A) {
             }
           F = T.S[lane] & D;
         }
-        const uint32_t cnt = (uint32_t)__popcll(F);
-        uint32_t incl = cnt;
-#pragma unroll
-        for (int o = 1; o < kTileRows; o <<= 1) {
-          const uint32_t v = __shfl_up(incl, o, kWave);
-          if (lane >= (uint32_t)o) incl += v;
-        }
-        const uint32_t nq = uniform(__shfl(incl, kTileRows - 1, kWave));
+        // 3. compact the front voxels into the queue: lane L takes the 16 bits
+        // 16 (L % 4) .. 16 (L % 4) + 15 of interior row L / 4 (in row-major order the
+        // lanes' pieces follow each other), so one wave prefix places every piece
+        const uint32_t frl = (uint32_t)__shfl((int)(uint32_t)F, (int)(lane >> 2), kWave);
+        const uint32_t frh = (uint32_t)__shfl((int)(uint32_t)(F >> 32), (int)(lane >> 2), kWave);
+        const uint32_t piece = (((lane & 2u) ? frh : frl) >> ((lane & 1u) * 16u)) & 0xFFFFu;
+        uint32_t nq_l;
+        uint32_t pos = wave_prefix((uint32_t)__builtin_popcount(piece), &nq_l);
+        const uint32_t nq = uniform(nq_l);
         kept_w += nq;
         if (!run || nq == 0) continue;
         const bool full = R.full != 0;
-        // 3. compact the front voxels into the queue (row i's prefix and mask are
-        // broadcast from lane i)
-        const uint32_t excl = incl - cnt;
-#pragma unroll 4
-        for (int i = 0; i < kTileRows; ++i) {
-          const uint32_t flo = (uint32_t)__builtin_amdgcn_readlane((uint32_t)F, i);
-          const uint32_t fhi = (uint32_t)__builtin_amdgcn_readlane((uint32_t)(F >> 32), i);
-          const uint32_t pi = (uint32_t)__builtin_amdgcn_readlane(excl, i);
-          // lanes below this one that hold a front voxel of row i
-          const uint32_t rank = __builtin_amdgcn_mbcnt_hi(fhi, __builtin_amdgcn_mbcnt_lo(flo, 0u));
-          if ((((uint64_t)fhi << 32 | flo) >> lane) & 1ull)
-            T.qo[pi + rank] = (uint16_t)((uint32_t)i << 6 | lane);
-        }
+        for (uint32_t c = piece; c; c &= c - 1u)
+          T.qo[pos++] = (uint16_t)((lane >> 2) << 6 | (lane & 3u) * 16u | (uint32_t)__builtin_ctz(c));
         wave_sync();
         // 4. void masks of the queue, then a counting sort of the queue by void count
         // so that the lanes of one round draw similar numbers of blocks and slots
