@@ -1500,25 +1500,23 @@ void k_sweep(BatchArgs A) {
               rv_lo = write_lane(rv_lo, (uint32_t)V, h);
               rv_hi = write_lane(rv_hi, (uint32_t)(V >> 32), h);
               if (hy >= 1 && hy <= kTileY && hz >= 1 && hz <= kTileZ) {
-                // an interior row lies in the domain unless it is past the grid's end in
-                // y or z (a ragged last tile)
-                const uint64_t rmask = ((rows_in >> h) & 1ull) ? xin : 0ull;
+                // (an interior row's solid mask is also masked by its lane at the end: the
+                // row lies in the domain unless it is past the grid's end in y or z)
                 const uint32_t i = (uint32_t)((hy - 1) + kTileY * (hz - 1));
-                const uint64_t Pm = __ballot(b == pmark) & rmask;
+                const uint64_t Pb = __ballot(b == pmark);
                 // solid: 1 or grown in the previous step (with other phases' cells in
                 // the grid, "not void" is not enough)
-                uint64_t Sm = kWalls ? (__ballot(b == kSolid) & rmask) | Pm : rmask & ~V;
-                if (kLiteral) Sm = (Pm & lit) | (Sm & ~lit);
+                uint64_t Sm = kWalls ? __ballot(b == kSolid) | Pb : ~V;
+                if (kLiteral) Sm = (Pb & lit) | (Sm & ~lit);
                 rs_lo = write_lane(rs_lo, (uint32_t)Sm, i);
                 rs_hi = write_lane(rs_hi, (uint32_t)(Sm >> 32), i);
-                if (Pm) {  // grown in the previous step: fold to 1
-                  if (b == pmark && lane_in) {
-                    const uint32_t q = yrow(y0 - 1 + hy) + zrow(z0 - 1 + hz) + vx;
-                    __hip_atomic_fetch_xor(
-                        (__attribute__((address_space(1))) uint32_t*)(grid + (q & ~3u)),
-                        (pmark ^ kSolid) << ((q & 3u) * 8u), __ATOMIC_RELAXED,
-                        __HIP_MEMORY_SCOPE_AGENT);
-                  }
+                // grown in the previous step: fold to 1
+                if (((rows_in >> h) & 1ull) && lane_in && b == pmark) {
+                  const uint32_t q = yrow(y0 - 1 + hy) + zrow(z0 - 1 + hz) + vx;
+                  __hip_atomic_fetch_xor(
+                      (__attribute__((address_space(1))) uint32_t*)(grid + (q & ~3u)),
+                      (pmark ^ kSolid) << ((q & 3u) * 8u), __ATOMIC_RELAXED,
+                      __HIP_MEMORY_SCOPE_AGENT);
                 }
               }
             }
@@ -1534,7 +1532,10 @@ void k_sweep(BatchArgs A) {
           T.win[lane][1] = __builtin_amdgcn_alignbit(vhi, vlo, 31u);
           T.win[lane][2] = vhi >> 31 | (uint32_t)((rm >> lane) & 1ull) << 1;
         }
-        if (lane < (uint32_t)kTileRows) T.S[lane] = (uint64_t)rs_hi << 32 | rs_lo;
+        if (lane < (uint32_t)kTileRows) {
+          const uint32_t hi = (lane % kTileY + 1u) + (kTileY + 2u) * (lane / kTileY + 1u);
+          T.S[lane] = ((rows_in >> hi) & 1ull) ? ((uint64_t)rs_hi << 32 | rs_lo) & xin : 0ull;
+        }
         wave_sync();
         // 2. front rows (solid with a void neighbour) and their prefix
         uint64_t F = 0;
