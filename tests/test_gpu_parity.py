@@ -370,6 +370,41 @@ def test_server_results_equal_solo_runs(q, orc):
         assert np.array_equal(grid, ref.grid), c.name
 
 
+def test_server_mixes_front_rules(q, orc):
+    """Requests with either front rule share the server's launches: each result equals
+    the oracle's run of that request alone with its rule."""
+    import torch
+    cases = workloads.small_cases()[:8] + workloads.config1()
+    lit = [k % 2 == 1 for k in range(len(cases))]
+    reserved = q.qsgs_server_reserved_bytes(len(cases))
+    arena_bytes = reserved + 64 * 64**3
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    srv = q.qsgs_server_create(arena, arena_bytes, len(cases), steps_per_tick=3)
+    results = {}
+    try:
+        for rid, (c, f) in enumerate(zip(cases, lit)):
+            q.qsgs_server_submit(srv, rid, c.dims, q.params_of(c, literal_front=f))
+        ticks = 0
+        while len(results) < len(cases):
+            say("server tick (mixed front rules)", ticks)
+            q.qsgs_server_tick(srv)
+            for rid, info in q.qsgs_server_ready(srv):
+                nx, ny, nz = cases[rid].dims
+                out = np.empty(nx * ny * nz, dtype=np.uint8)
+                q.qsgs_server_take(srv, rid, out)
+                results[rid] = (out.reshape(nz, ny, nx), info)
+            ticks += 1
+            assert ticks < 2000
+    finally:
+        q.qsgs_server_destroy(srv)
+    for rid, (c, f) in enumerate(zip(cases, lit)):
+        grid, info = results[rid]
+        ref = run_oracle(orc, c, literal_front=f)
+        assert info.status == ref.status and info.step == ref.steps, c.name
+        assert info.solid_count == ref.solid_count, c.name
+        assert np.array_equal(grid, ref.grid), c.name
+
+
 def test_server_rejects_oversized_request(q):
     import torch
     reserved = q.qsgs_server_reserved_bytes(2)
