@@ -236,17 +236,18 @@ class PhaseResult:
 
 def generate_phases(dims, phases) -> tuple[np.ndarray, list[PhaseResult]]:
     """Independent growing phases in sequence (Sec. 2.1 steps 1-5).  ``phases`` is a
-    sequence of (solid_fraction, seed_prob, g_ref, spacing, key[, max_steps]) tuples,
-    phase n = index + 1; returns the label grid (0 = matrix, n = phase n) and one
-    result per phase."""
+    sequence of (solid_fraction, seed_prob, g_ref, spacing, key[, max_steps[,
+    literal_front]]) tuples, phase n = index + 1; returns the label grid (0 = matrix,
+    n = phase n) and one result per phase."""
     nx, ny, nz = dims
     k = len(phases)
     arr = (_Params * k)()
     for i, ph in enumerate(phases):
         sf, sd, g, sp, key = ph[:5]
         ms = ph[5] if len(ph) > 5 else 0
+        lit = 1 if (len(ph) > 6 and ph[6]) else 0
         arr[i] = _Params(float(sf), float(sd), (ctypes.c_double * 3)(*g), int(sp), int(ms),
-                         int(key), 0, 0)
+                         int(key), lit, 0)
     res = (_Result * k)()
     labels = np.zeros((nz, ny, nx), dtype=np.uint8)
     lib().orc_generate_phases(nx, ny, nz, k, arr, _ptr(labels), res)

@@ -469,6 +469,23 @@ def test_phases_match_oracle(q, orc, ps, full):
     assert np.array_equal(labels.cpu().numpy(), ref)
 
 
+def test_phases_with_literal_front_match_oracle(q, orc):
+    """A later phase under Algorithm 3's literal front rule on a walled grid (the sweep
+    instance for both): labels and per-phase results equal the oracle's."""
+    import torch
+    ps = PHASES[0]
+    tuples = [t + (k == 1,) for k, t in enumerate(_phase_tuples(ps))]
+    params = [q.params_of(c, literal_front=(k == 1)) for k, c in enumerate(ps.phases)]
+    say("GPU generate_phases (phase 2 literal front)", ps.name)
+    labels, infos = q.generate_phases(ps.dims, params)
+    torch.cuda.synchronize()
+    ref, res = orc.generate_phases(ps.dims, tuples)
+    for info, r in zip(infos, res):
+        assert (info["solid_count"], info["step"], info["status"], info["front_size"]) == \
+               (r.count, r.steps, r.status, r.front_size)
+    assert np.array_equal(labels.cpu().numpy(), ref)
+
+
 def test_one_phase_equals_generate(q):
     import torch
     case = workloads.small_cases()[0]
