@@ -259,10 +259,31 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* data, uint32_
   if (i < n) data[i] += sums[blockIdx.x];
 }
 
+// Wave-wide exclusive prefix of cnt; *total receives the wave's sum.
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t cnt, uint32_t* total) {
+  const uint32_t lane = lane_id();
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t v = __shfl_up(incl, off, kWave);
+    if (lane >= (uint32_t)off) incl += v;
+  }
+  *total = __shfl(incl, kWave - 1, kWave);
+  return incl - cnt;
+}
+
+// Orders LDS accesses of the lanes of one wavefront (a wave executes in lockstep; this
+// keeps the compiler from moving LDS accesses across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // a1: seed candidates (items: voxels).  Voxel v draws the block at (v, 0, 0, 1);
 // word 0 below T_seed makes it a candidate (Sec. 2.1 step 2).  The grid is zeroed
-// in the same pass; candidates are appended with one atomic per wavefront.
+// in the same pass; candidates are buffered per wavefront in LDS and appended in bulk.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
   // the record's fields, read once per realization (the byte stores below could alias
@@ -278,11 +299,29 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
   gword* stamp = nullptr;
   int32_t* cand_list = nullptr;
   uint32_t* n_cand = nullptr;
+  // Candidates collect in a per-wavefront LDS buffer and go to the realization's list
+  // with one atomic per flush: one global counter per realization would otherwise take
+  // an atomic from every chunk that holds a candidate, all on one address.
+  constexpr uint32_t kSeedBuf = 512;
+  __shared__ int32_t s_cbuf[kMaxBlock / kWave][kSeedBuf];
+  int32_t* cbuf = s_cbuf[threadIdx.x / kWave];
+  uint32_t nbuf = 0;  // (wave-uniform)
+  auto flush = [&]() {
+    if (nbuf == 0) return;
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(n_cand, nbuf);
+    base = uniform((uint32_t)__builtin_amdgcn_readfirstlane(base));
+    wave_sync();  // the buffer's entries are written
+    for (uint32_t k = lane_id(); k < nbuf; k += kWave) cand_list[base + k] = cbuf[k];
+    wave_sync();  // and read before the buffer is reused
+    nbuf = 0;
+  };
   // each lane takes the four voxels 4i .. 4i + 3: four independent blocks in flight and
   // one word store of the grid (byte stores only for the last, partial group, so that
   // the grid's padding is never written)
   for_each_chunk(A, kItemsQuads, [&](uint32_t r, uint32_t i) {
     if (r != cr) {
+      flush();  // (the previous realization's candidates)
       Real& R = A.reals[r];
       n = uniform(R.g.n);
       k0 = uniform(R.k0);
@@ -325,14 +364,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
         for (uint32_t k = 0; k < 4u && v0 + k < tiles; ++k) stamp[v0 + k] = 0;
     }
     if (__ballot(cand != 0)) {
-      uint32_t pos = wave_append((uint32_t)__builtin_popcount(cand), n_cand);
-      while (cand) {  // capacity N: cannot overflow
+      uint32_t tot;
+      uint32_t pos = nbuf + wave_prefix((uint32_t)__builtin_popcount(cand), &tot);
+      while (cand) {
         const int k = __builtin_ctz(cand);
         cand &= cand - 1u;
-        cand_list[pos++] = (int32_t)(v0 + (uint32_t)k);
+        cbuf[pos++] = (int32_t)(v0 + (uint32_t)k);
       }
+      nbuf += uniform(tot);
+      if (nbuf > kSeedBuf - 4u * kWave) flush();  // room for one more chunk's four per lane
     }
   });
+  flush();  // (capacity N: the list cannot overflow)
 }
 
 // ---------------------------------------------------------------------------
@@ -1096,18 +1139,6 @@ __device__ void sweep_end(const BatchArgs& A, uint32_t r, uint32_t kept, uint32_
   }
 }
 
-// Wave-wide exclusive prefix of cnt; *total receives the wave's sum.
-__device__ __forceinline__ uint32_t wave_prefix(uint32_t cnt, uint32_t* total) {
-  const uint32_t lane = lane_id();
-  uint32_t incl = cnt;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const uint32_t v = __shfl_up(incl, off, kWave);
-    if (lane >= (uint32_t)off) incl += v;
-  }
-  *total = __shfl(incl, kWave - 1, kWave);
-  return incl - cnt;
-}
 
 // Directions (26-bit masks) whose step leaves the voxel's tile on each side.
 constexpr uint32_t dir_mask_where(int field, int val) {
@@ -1270,13 +1301,6 @@ __device__ __forceinline__ uint32_t write_lane(uint32_t v, uint32_t s, uint32_t 
 }
 
 
-// Orders LDS accesses of the lanes of one wavefront (a wave executes in lockstep; this
-// keeps the compiler from moving LDS accesses across the point).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Dynamic LDS of k_sweep: one TileImage per wavefront.
 size_t sweep_lds_bytes(uint32_t block) { return sizeof(TileImage) * (block / kWave); }
