@@ -780,8 +780,39 @@ __device__ __forceinline__ uint32_t grow_draws(uint8_t* __restrict__ grid, uint3
 // and the first claimer appends it after F_t in the same list.  Sources are F_t
 // only (Jacobi step).
 // ---------------------------------------------------------------------------
+// A wavefront's appends to one realization's list go through an LDS buffer and reach the
+// list's counter with one atomic per flush (per-chunk atomics on one counter serialize).
+constexpr uint32_t kListBuf = 512;
+
 __global__ __launch_bounds__(kMaxBlock) void k_grow(BatchArgs A) {
+  __shared__ int32_t s_lbuf[kMaxBlock / kWave][kListBuf];
+  int32_t* lbuf = s_lbuf[threadIdx.x / kWave];
+  uint32_t nbuf = 0, cr = 0xFFFFFFFFu;  // (wave-uniform)
+  auto flush = [&]() {
+    if (nbuf == 0) return;
+    Real& R = A.reals[cr];
+    Ctl& c = R.ctl;
+    int32_t* __restrict__ fin = c.cur ? R.f1 : R.f0;
+    const uint32_t nf = c.front_size;
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(&c.new_count, nbuf);
+    base = uniform((uint32_t)__builtin_amdgcn_readfirstlane(base));
+    wave_sync();  // the buffer's entries are written
+    for (uint32_t k = lane_id(); k < nbuf; k += kWave) {
+      const uint32_t slot = nf + base + k;
+      if (slot < R.cap)
+        fin[slot] = lbuf[k];
+      else
+        c.overflow = 1u;
+    }
+    wave_sync();  // and read before the buffer is reused
+    nbuf = 0;
+  };
   for_each_chunk(A, kItemsGrow, [&](uint32_t r, uint32_t i) {
+    if (r != cr) {
+      flush();
+      cr = r;
+    }
     Real& R = A.reals[r];
     Ctl& c = R.ctl;
     const uint32_t t = (uint32_t)c.step;
@@ -803,33 +834,75 @@ __global__ __launch_bounds__(kMaxBlock) void k_grow(BatchArgs A) {
                             nb.voidm, nb.grown, th, kGrown);
       }
     }
-    uint32_t pos = wave_append((uint32_t)__builtin_popcount(claims), &c.new_count);
+    if (__ballot(claims != 0) == 0) return;
+    uint32_t tot;
+    uint32_t pos = wave_prefix((uint32_t)__builtin_popcount(claims), &tot);
+    tot = uniform(tot);
+    if (nbuf + tot > kListBuf) flush();
+    if (tot > kListBuf) {  // (a chunk with more claims than the buffer holds: direct)
+      uint32_t base = 0;
+      if (lane_id() == 0) base = atomicAdd(&c.new_count, tot);
+      pos += uniform((uint32_t)__builtin_amdgcn_readfirstlane(base));
+      while (claims) {
+        const int d = __builtin_ctz(claims);
+        claims &= claims - 1u;
+        const uint32_t slot = nf + pos;
+        if (slot < R.cap)
+          fin[slot] = (int32_t)((int32_t)a + dir_offset(g, d));
+        else
+          c.overflow = 1u;
+        ++pos;
+      }
+      return;
+    }
+    pos += nbuf;
     while (claims) {
       const int d = __builtin_ctz(claims);
       claims &= claims - 1u;
-      const uint32_t slot = nf + pos;
-      if (slot < R.cap)
-        fin[slot] = (int32_t)((int32_t)a + dir_offset(g, d));
-      else
-        c.overflow = 1u;
-      ++pos;
+      lbuf[pos++] = (int32_t)((int32_t)a + dir_offset(g, d));
     }
+    nbuf += tot;
   });
+  flush();
 }
 
 // ---------------------------------------------------------------------------
 // a5: prune and compaction (Sec. 2.3 step 4), items: F_t + New_t.  F_{t+1} = the
-// entries that still have an in-domain void neighbour, appended with one atomic per
-// wavefront.  New voxels are folded from 2 to 1 here.
+// entries that still have an in-domain void neighbour, appended through the
+// wavefront's LDS buffer.  New voxels are folded from 2 to 1 here.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kMaxBlock) void k_prune(BatchArgs A) {
+  __shared__ int32_t s_lbuf[kMaxBlock / kWave][kListBuf];
+  int32_t* lbuf = s_lbuf[threadIdx.x / kWave];
+  uint32_t nbuf = 0, cr = 0xFFFFFFFFu;  // (wave-uniform)
+  auto flush = [&]() {
+    if (nbuf == 0) return;
+    Real& R = A.reals[cr];
+    Ctl& c = R.ctl;
+    int32_t* __restrict__ fout = c.cur ? R.f0 : R.f1;
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(&c.out_count, nbuf);
+    base = uniform((uint32_t)__builtin_amdgcn_readfirstlane(base));
+    wave_sync();  // the buffer's entries are written
+    for (uint32_t k = lane_id(); k < nbuf; k += kWave) {
+      if (base + k < R.cap)
+        fout[base + k] = lbuf[k];
+      else
+        c.overflow = 1u;
+    }
+    wave_sync();  // and read before the buffer is reused
+    nbuf = 0;
+  };
   for_each_chunk(A, kItemsPrune, [&](uint32_t r, uint32_t i) {
+    if (r != cr) {
+      flush();
+      cr = r;
+    }
     Real& R = A.reals[r];
     Ctl& c = R.ctl;
     const uint32_t nf = c.front_size;
     const uint32_t n_in = nf + c.new_count;
     const int32_t* __restrict__ fin = c.cur ? R.f1 : R.f0;
-    int32_t* __restrict__ fout = c.cur ? R.f0 : R.f1;
     const Geometry g = R.g;
     bool keep = false;
     uint32_t v = 0;
@@ -842,14 +915,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_prune(BatchArgs A) {
         if (i >= nf) R.grid[v] = kSolid;
       }
     }
-    const uint32_t pos = wave_append_flag(keep, &c.out_count);
-    if (keep) {
-      if (pos < R.cap)
-        fout[pos] = (int32_t)v;
-      else
-        c.overflow = 1u;
-    }
+    const uint64_t km = __ballot(keep);
+    if (km == 0) return;
+    if (nbuf + kWave > kListBuf) flush();
+    if (keep)
+      lbuf[nbuf + __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u))] =
+          (int32_t)v;
+    nbuf += (uint32_t)__popcll(km);
   });
+  flush();
 }
 
 // ---------------------------------------------------------------------------
