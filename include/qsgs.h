@@ -152,6 +152,25 @@ qsgs_status qsgs_grow_step(const qsgs_dims* dims, const qsgs_params* params, uin
 qsgs_status qsgs_generate(const qsgs_dims* dims, const qsgs_params* params, uint8_t* d_grid,
                           void* d_ws, size_t ws_bytes, qsgs_info* info, void* stream);
 
+/* Allocation-free whole generation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same result as qsgs_generate; the workspace is a scratch array of 128 MiB that the
+ * library holds in device memory, one per device it runs on, for the life of the process.
+ * The call allocates nothing: no device memory, no pinned host memory, no events (its
+ * small control transfers go through pageable host memory).
+ *   d_grid  device, qsgs_grid_bytes(dims) bytes, 4-byte aligned; receives the final grid.
+ *   info    host; receives the final counts, steps and status.
+ * Every call on one device uses that device's scratch and leaves its contents behind
+ * (each call re-initialises what it reads).  Calls on one device from several host
+ * threads are serialised by the library; work of this entry point enqueued on one device
+ * from several processes does not share a scratch.  The per-step log is not readable
+ * (qsgs_read_step_log needs the caller's workspace).
+ * Errors: QSGS_ERR_INVALID, QSGS_ERR_WORKSPACE when the generation needs more scratch
+ * than 128 MiB (qsgs_workspace_bytes(dims, params) > 134217728: roughly N above 6 million
+ * voxels with spacing; nothing is launched), QSGS_ERR_DEVICE.  Synchronises `stream`. */
+qsgs_status qsgs_generate_noalloc(const qsgs_dims* dims, const qsgs_params* params,
+                                  uint8_t* d_grid, qsgs_info* info, void* stream);
+
 /* Batched generation (many independent realizations, e.g. for uncertainty
  * quantification, Sec. 1): `count` realizations of possibly different sizes and
  * parameters share one persistent launch per kernel per growth step, addressed

@@ -72,6 +72,8 @@ SIGNATURES = {
                                       _SZ, _P(qsgs_info), _VP]),
     "qsgs_generate": (ctypes.c_int, [_P(qsgs_dims), _P(qsgs_params), _VP, _VP, _SZ,
                                      _P(qsgs_info), _VP]),
+    "qsgs_generate_noalloc": (ctypes.c_int, [_P(qsgs_dims), _P(qsgs_params), _VP,
+                                             _P(qsgs_info), _VP]),
     "qsgs_batch_workspace_bytes": (_SZ, [_I32, _VP, _VP]),
     "qsgs_generate_batch": (ctypes.c_int, [_I32, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
     "qsgs_phases_workspace_bytes": (_SZ, [_P(qsgs_dims), _I32, _VP]),
@@ -198,6 +200,15 @@ def qsgs_generate(dims, params, grid, ws, ws_bytes: int, info: qsgs_info | None 
     info = info if info is not None else qsgs_info()
     st = load().qsgs_generate(ctypes.byref(make_dims(dims)), ctypes.byref(params), _ptr(grid),
                               _ptr(ws), int(ws_bytes), ctypes.byref(info), _stream(stream))
+    return _check(st), info
+
+
+def qsgs_generate_noalloc(dims, params, grid, info: qsgs_info | None = None,
+                          stream=None) -> tuple[int, qsgs_info]:
+    """Whole generation in the library's own scratch (no workspace argument)."""
+    info = info if info is not None else qsgs_info()
+    st = load().qsgs_generate_noalloc(ctypes.byref(make_dims(dims)), ctypes.byref(params),
+                                      _ptr(grid), ctypes.byref(info), _stream(stream))
     return _check(st), info
 
 

@@ -50,9 +50,12 @@ qsgs_status make_specs(int32_t count, const qsgs_dims* dims, const qsgs_params* 
   return QSGS_OK;
 }
 
+// no_alloc: the call may not allocate (the allocation-free entry point): transfers go
+// through pageable host memory instead of the pinned staging buffer, and no timing
+// events are recorded.
 qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_params* params,
                           uint8_t* const* grids, void* ws, size_t ws_bytes, qsgs_info* infos,
-                          hipStream_t s, bool walls = false) {
+                          hipStream_t s, bool walls = false, bool no_alloc = false) {
   std::vector<Spec> specs;
   QSGS_TRY(make_specs(count, dims, params, grids, &specs));
   if (!ws || !infos) return fail(QSGS_ERR_INVALID, "d_ws and info must not be NULL");
@@ -61,7 +64,8 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
     return fail(QSGS_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", G.total, ws_bytes);
   Engine E;
   E.bind(ws, G.P, (size_t)count, s);
-  E.stage = thread_pinned_stage(Engine::stage_bytes((size_t)count));
+  E.no_events = no_alloc;
+  E.stage = no_alloc ? nullptr : thread_pinned_stage(Engine::stage_bytes((size_t)count));
   std::vector<size_t> group;
   for (int32_t r = 0; r < count; ++r) {
     E.init_sweep_record((size_t)r, specs[r], &params[r], grids[r], at<void>(ws, G.sweep[r]));
@@ -69,7 +73,7 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
     group.push_back((size_t)r);
   }
   E.attach_scratch(group, at<void>(ws, G.seed), G.S);
-  const bool profiling = prof_on();
+  const bool profiling = prof_on() && !no_alloc;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (profiling) {
     prof_release_all();
@@ -103,9 +107,58 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
   return (qsgs_status)worst;
 }
 
+// Scratch of the allocation-free entry point: the generation workspace of one call,
+// held in device memory by the code object (each device that runs the library holds its
+// own copy until the process ends).  Host code never passes `scratch` itself to a kernel
+// or a copy (in host code the name is a stand-in, not a device address): it uses the
+// device address hipGetSymbolAddress returns, taken once per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+
+struct NoAllocDevice {
+  std::mutex mu;   // serialises the calls that share this device's scratch
+  void* ptr = nullptr;
+};
+
+NoAllocDevice* no_alloc_devices() {
+  static NoAllocDevice d[kMaxDevices];
+  return d;
+}
+
 }  // namespace
 
 extern "C" {
+
+qsgs_status qsgs_generate_noalloc(const qsgs_dims* dims, const qsgs_params* params,
+                                  uint8_t* d_grid, qsgs_info* info, void* stream) {
+  last_error().clear();
+  std::vector<Spec> specs;
+  QSGS_TRY(make_specs(1, dims, params, &d_grid, &specs));
+  if (!info) return fail(QSGS_ERR_INVALID, "info must not be NULL");
+  const size_t need = gen_layout(specs, true).total;
+  if (need > kNoAllocScratchBytes)
+    return fail(QSGS_ERR_WORKSPACE,
+                "qsgs_generate_noalloc: this grid needs %zu bytes of scratch, more than the "
+                "%zu it holds; use qsgs_generate with a workspace of "
+                "qsgs_workspace_bytes() bytes",
+                need, kNoAllocScratchBytes);
+  int dev = 0;
+  QSGS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(QSGS_ERR_DEVICE, "device %d outside [0, %d)", dev, kMaxDevices);
+  NoAllocDevice& D = no_alloc_devices()[dev];
+  std::lock_guard<std::mutex> lk(D.mu);
+  if (!D.ptr) {  // first call on this device (it is current): the array's device address
+    void* p = nullptr;
+    QSGS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(QSGS_ERR_DEVICE, "hipGetSymbolAddress returned NULL for the scratch");
+    D.ptr = p;
+  }
+  return generate_impl(1, dims, params, &d_grid, D.ptr, kNoAllocScratchBytes, info,
+                       (hipStream_t)stream, false, true);
+}
 
 size_t qsgs_grid_bytes(const qsgs_dims* dims) {
   Geometry g{};

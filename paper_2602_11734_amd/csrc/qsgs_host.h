@@ -385,6 +385,7 @@ struct Engine {
   Tuning tune;
   WsHeader hdr{};
   uint32_t sweep_grid = 2048;
+  bool no_events = false;  // the call may not allocate: no timing events
   // pinned staging (see thread_pinned_stage): uploads, then readbacks, each in its own
   // region; nullptr for pageable copies
   char* stage = nullptr;
@@ -437,8 +438,13 @@ struct Engine {
     const void* src = &b;
     if (stage) src = std::memcpy(st_up_ctl(), &b, sizeof b);
     QSGS_HIP(hipMemcpyAsync(args.bctl, src, sizeof b, hipMemcpyHostToDevice, s));
-    QSGS_HIP(hipMemsetAsync(args.tailfill, 0, sizeof(uint32_t) * reals.size(), s));
-    QSGS_HIP(hipMemsetAsync(args.plan[0].rseg, 0, sizeof(uint32_t) * (reals.size() + 1), s));
+    // (fill kernels rather than memsets, so that the stream's work stays kernels and copies)
+    const uint32_t n = (uint32_t)reals.size();
+    hipLaunchKernelGGL(k_fill_u32, dim3((n + 256) / 256), dim3(256), 0, s, args.tailfill, 0u, n);
+    QSGS_LAUNCHED("k_fill_u32");
+    hipLaunchKernelGGL(k_fill_u32, dim3((n + 256) / 256), dim3(256), 0, s, args.plan[0].rseg, 0u,
+                       n + 1);
+    QSGS_LAUNCHED("k_fill_u32");
     return QSGS_OK;
   }
 
@@ -720,7 +726,7 @@ struct Engine {
   // (passes after the stop find nothing to do and cost two empty launches, less than a
   // round trip to the host).
   qsgs_status run_sweep_loop() {
-    const bool profiling = prof_on();
+    const bool profiling = prof_on() && !no_events;
     std::vector<hipEvent_t> ev;
     BatchCtl b{};
     Ctl c{};

@@ -180,3 +180,15 @@ def test_seed_prob_from_grain(q):
     for bad in ((1.2, 200.0, 4.0), (0.5, 0.0, 4.0), (0.5, 200.0, -1.0)):
         with pytest.raises(q.QsgsError):
             q.qsgs_seed_prob_from_grain(*bad)
+
+
+def test_noalloc_refuses_oversized_grids_before_touching_a_device(q):
+    """The allocation-free entry point checks the generation's scratch need against its
+    fixed scratch first: a 400^3 generation is refused without any HIP call."""
+    p = q.make_params(0.8, 5e-4, (0.01, 0.0025, 0.000625), 20, 1)
+    info = q.qsgs_info()
+    st = q.load().qsgs_generate_noalloc(ctypes.byref(q.make_dims((400, 400, 400))),
+                                        ctypes.byref(p), 256, ctypes.byref(info), None)
+    assert st == q.ERR_WORKSPACE
+    assert "scratch" in q.qsgs_last_error()
+    assert q.qsgs_workspace_bytes((400, 400, 400), p) > 128 << 20
