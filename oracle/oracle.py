@@ -88,6 +88,12 @@ def lib():
         _lib.orc_generate.restype = i32
         _lib.orc_generate_phases.argtypes = [i32, i32, i32, i32, P(_Params), vp, P(_Result)]
         _lib.orc_generate_phases.restype = i32
+        _lib.orc_step_interacting.argtypes = [i32, i32, i32, vp, vp, vp, vp, i64, u32, u64, vp,
+                                              P(i64), vp, vp, vp, vp]
+        _lib.orc_step_interacting.restype = i64
+        _lib.orc_generate_phases_interacting.argtypes = [i32, i32, i32, i32, P(_Params), vp, vp,
+                                                         P(_Result)]
+        _lib.orc_generate_phases_interacting.restype = i32
     return _lib
 
 
@@ -234,12 +240,7 @@ class PhaseResult:
     status: int
 
 
-def generate_phases(dims, phases) -> tuple[np.ndarray, list[PhaseResult]]:
-    """Independent growing phases in sequence (Sec. 2.1 steps 1-5).  ``phases`` is a
-    sequence of (solid_fraction, seed_prob, g_ref, spacing, key[, max_steps[,
-    literal_front]]) tuples, phase n = index + 1; returns the label grid (0 = matrix,
-    n = phase n) and one result per phase."""
-    nx, ny, nz = dims
+def _phase_params(phases):
     k = len(phases)
     arr = (_Params * k)()
     for i, ph in enumerate(phases):
@@ -248,9 +249,53 @@ def generate_phases(dims, phases) -> tuple[np.ndarray, list[PhaseResult]]:
         lit = 1 if (len(ph) > 6 and ph[6]) else 0
         arr[i] = _Params(float(sf), float(sd), (ctypes.c_double * 3)(*g), int(sp), int(ms),
                          int(key), lit, 0)
+    return arr
+
+
+def generate_phases(dims, phases, interact=None) -> tuple[np.ndarray, list[PhaseResult]]:
+    """Growing phases in sequence (Sec. 2.1 steps 1-5).  ``phases`` is a sequence of
+    (solid_fraction, seed_prob, g_ref, spacing, key[, max_steps[, literal_front]]) tuples,
+    phase n = index + 1; returns the label grid (0 = matrix, n = phase n) and one result
+    per phase.  ``interact`` (optional): array [n_phases, n_phases, 3] of the
+    phase-interaction probabilities I_c^{n,m} (index [n - 1, m - 1, c], read for m < n);
+    None means independent phases."""
+    nx, ny, nz = dims
+    k = len(phases)
+    arr = _phase_params(phases)
     res = (_Result * k)()
     labels = np.zeros((nz, ny, nx), dtype=np.uint8)
-    lib().orc_generate_phases(nx, ny, nz, k, arr, _ptr(labels), res)
+    if interact is None:
+        lib().orc_generate_phases(nx, ny, nz, k, arr, _ptr(labels), res)
+    else:
+        I = np.ascontiguousarray(interact, dtype=np.float64)
+        assert I.shape == (k, k, 3)
+        lib().orc_generate_phases_interacting(nx, ny, nz, k, arr, _ptr(I), _ptr(labels), res)
     out = [PhaseResult(r.n_candidates, r.n_seeds, r.solid_count, r.target_count, r.front_size,
                        r.steps, r.status) for r in res]
     return labels, out
+
+
+def step_interacting(labels: np.ndarray, cand, thr, front: np.ndarray, t: int, key: int,
+                     counters: bool = False):
+    """One growth step of the phase held as label 1 on ``labels`` (in place), with the
+    candidate table ``cand`` (256 flags) and thresholds ``thr`` (256 x 3); returns (next
+    front, converted cells[, attempts, successes]) -- counters 52 entries each: index d
+    for unassigned targets, 26 + d for targets of other phases."""
+    assert labels.flags.c_contiguous and labels.dtype == np.uint8
+    nz, ny, nx = labels.shape
+    n = labels.size
+    A = np.ascontiguousarray(front, dtype=np.int32)
+    c = np.ascontiguousarray(cand, dtype=np.uint8)
+    T = np.ascontiguousarray(thr, dtype=np.uint64).reshape(-1)
+    assert c.size == 256 and T.size == 768
+    A_next = np.zeros(max(n, 1), dtype=np.int32)
+    conv = np.zeros(max(n, 1), dtype=np.int32)
+    mask = np.zeros(max(len(A), 1), dtype=np.uint32)
+    att = np.zeros(52, dtype=np.uint64) if counters else None
+    suc = np.zeros(52, dtype=np.uint64) if counters else None
+    nn = ctypes.c_int64()
+    k = lib().orc_step_interacting(nx, ny, nz, _ptr(labels), _ptr(c), _ptr(T), _ptr(A), len(A),
+                                   int(t), int(key), _ptr(A_next), ctypes.byref(nn), _ptr(conv),
+                                   _ptr(mask), _ptr(att), _ptr(suc))
+    out = (A_next[:nn.value].copy(), conv[:k].copy())
+    return out + (att, suc) if counters else out

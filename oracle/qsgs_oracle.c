@@ -476,3 +476,168 @@ int32_t orc_generate_phases(int32_t nx, int32_t ny, int32_t nz, int32_t n_phases
     if (labels[v] >= 4) labels[v] = (uint8_t)(labels[v] - 3);
   return worst;
 }
+/* ------------------------------------------------------------------------ */
+/* Interacting phases (Sec. 2.1 step 4): the n-th growing phase also grows   */
+/* into a neighbour held by an earlier phase m, with the phase-interaction   */
+/* probability I_i^{n,m} of the direction's class.                           */
+/* Readings: while phase n grows, the label grid holds 0 (unassigned), 1     */
+/* (phase n) and 3 + m (earlier phase m).  A neighbour is a candidate target */
+/* of a phase-n cell when it is unassigned, or when it belongs to a phase m  */
+/* that phase n interacts with (I^{n,m} > 0 for some class).  The j-th       */
+/* candidate neighbour of a source (ascending d) takes the draw of rank j    */
+/* (the single-phase draw rule).  An unassigned target passes with the       */
+/* Eq. (1) threshold of the step, a target of phase m with P32(I_c^{n,m}),   */
+/* not scaled by Eq. (1) (the interaction probability is given as such).     */
+/* A passing draw converts the target to phase n; it counts towards phase   */
+/* n's fraction.  Candidates, labels and thresholds are those of the step's  */
+/* start (Jacobi, as for one phase); the front is the set of phase-n cells   */
+/* with a candidate neighbour.  With every I = 0 nothing but unassigned      */
+/* cells is a candidate, and the phases are the independent ones.            */
+/* ------------------------------------------------------------------------ */
+
+/* Candidate targets of phase-n cell a: one bit per direction. */
+static uint32_t candidate_mask(int32_t nx, int32_t ny, int32_t nz, const uint8_t* labels,
+                               const uint8_t cand[256], int64_t a) {
+  int32_t x, y, z;
+  coords(nx, ny, a, &x, &y, &z);
+  uint32_t m = 0;
+  for (int32_t d = 0; d < 26; ++d) {
+    int64_t q = neighbour(nx, ny, nz, x, y, z, d);
+    if (q >= 0 && cand[labels[q]]) m |= 1u << d;
+  }
+  return m;
+}
+
+int64_t orc_step_interacting(int32_t nx, int32_t ny, int32_t nz, uint8_t* labels,
+                             const uint8_t cand[256], const uint64_t thr[768],
+                             const int32_t* A, int64_t nA, uint32_t t, uint64_t key,
+                             int32_t* A_next, int64_t* n_next, int32_t* converted,
+                             uint32_t* mask_scratch, uint64_t* attempts,
+                             uint64_t* successes) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  /* the step's start: every source's candidates, and every cell's label */
+  for (int64_t i = 0; i < nA; ++i)
+    mask_scratch[i] = candidate_mask(nx, ny, nz, labels, cand, A[i]);
+  uint8_t* claimed = (uint8_t*)calloc((size_t)n, 1);
+  int64_t added = 0;
+  for (int32_t d = 0; d < 26; ++d) {
+    int32_t dx, dy, dz, cls;
+    orc_direction(d, &dx, &dy, &dz, &cls);
+    for (int64_t i = 0; i < nA; ++i) {
+      uint32_t m = mask_scratch[i];
+      if (!((m >> d) & 1u)) continue;
+      int32_t j = popcount32(m & ((1u << d) - 1u));
+      int64_t q = (int64_t)A[i] + dx + (int64_t)nx * (dy + (int64_t)ny * dz);
+      uint64_t T = thr[3 * labels[q] + cls]; /* labels are untouched during the step */
+      if (attempts) attempts[d + 26 * (labels[q] != 0)] += 1;
+      if ((uint64_t)orc_growth_draw(key, A[i], t, j) < T) {
+        if (successes) successes[d + 26 * (labels[q] != 0)] += 1;
+        if (!claimed[q]) {
+          claimed[q] = 1;
+          converted[added++] = (int32_t)q;
+        }
+      }
+    }
+  }
+  for (int64_t k = 0; k < added; ++k) labels[converted[k]] = 1;
+  free(claimed);
+  /* the next front: cells of A and converted cells with a candidate neighbour left */
+  int64_t kept = 0;
+  for (int64_t i = 0; i < nA; ++i)
+    if (candidate_mask(nx, ny, nz, labels, cand, A[i])) A_next[kept++] = A[i];
+  for (int64_t k = 0; k < added; ++k)
+    if (candidate_mask(nx, ny, nz, labels, cand, converted[k])) A_next[kept++] = converted[k];
+  *n_next = kept;
+  return added;
+}
+
+/* Phase-n generation on a label grid with the candidate table `cand` and the
+ * interaction thresholds of the labels 3 + m in `thr` (entries 3..767); entries 0..2
+ * (unassigned cells) take the Eq. (1) thresholds of each step.  Seeding as for an
+ * independent phase: cores only on unassigned cells. */
+static int32_t grow_phase_interacting(int32_t nx, int32_t ny, int32_t nz, const orc_params* p,
+                                      uint8_t* labels, const uint8_t cand[256], uint64_t thr[768],
+                                      orc_result* res) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  const int64_t s_star = orc_target_count(p->solid_fraction, n);
+  const uint64_t t_seed = orc_prob_threshold(p->seed_prob);
+  uint64_t t_ref[3];
+  for (int c = 0; c < 3; ++c) t_ref[c] = orc_prob_threshold(p->g_ref[c]);
+  const int32_t max_steps = p->max_steps > 0 ? p->max_steps : ORC_DEFAULT_MAX_STEPS;
+
+  int32_t* A = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* A_next = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* conv = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  uint32_t* mask = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
+  uint64_t* prio = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+
+  int64_t n_drawn = orc_seed_candidates(nx, ny, nz, p->key, t_seed, A, prio, n);
+  int64_t n_cand = 0;
+  for (int64_t i = 0; i < n_drawn; ++i)
+    if (labels[A[i]] == 0) {
+      A[n_cand] = A[i];
+      prio[n_cand] = prio[i];
+      ++n_cand;
+    }
+  int64_t n_seeds = orc_seed_select(nx, ny, nz, p->spacing, n_cand, A, prio, labels);
+
+  int64_t cnt = n_seeds, nA = 0;
+  for (int64_t v = 0; v < n; ++v)
+    if (labels[v] == 1 && candidate_mask(nx, ny, nz, labels, cand, v)) A[nA++] = (int32_t)v;
+  int32_t t = 0;
+  while (cnt < s_star && nA > 0 && t < max_steps) {
+    for (int c = 0; c < 3; ++c) thr[c] = orc_growth_threshold(t_ref[c], cnt, s_star);
+    int64_t nA_next = 0;
+    int64_t added = orc_step_interacting(nx, ny, nz, labels, cand, thr, A, nA, (uint32_t)t,
+                                         p->key, A_next, &nA_next, conv, mask, NULL, NULL);
+    if (p->front_rule == 1) { /* Algorithm 3 as printed: only the new cells */
+      nA_next = 0;
+      for (int64_t k = 0; k < added; ++k)
+        if (candidate_mask(nx, ny, nz, labels, cand, conv[k])) A_next[nA_next++] = conv[k];
+    }
+    cnt += added;
+    int32_t* tmp = A; A = A_next; A_next = tmp;
+    nA = nA_next;
+    ++t;
+  }
+  res->n_candidates = n_cand;
+  res->n_seeds = n_seeds;
+  res->solid_count = cnt;
+  res->target_count = s_star;
+  res->front_size = nA;
+  res->steps = t;
+  res->status = cnt >= s_star ? ORC_DONE : (nA == 0 ? ORC_EXHAUSTED : ORC_MAXSTEPS);
+  free(A); free(A_next); free(conv); free(mask); free(prio);
+  return res->status;
+}
+
+int32_t orc_generate_phases_interacting(int32_t nx, int32_t ny, int32_t nz, int32_t n_phases,
+                                        const orc_params* phases, const double* interact,
+                                        uint8_t* labels, orc_result* results) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  memset(labels, 0, (size_t)n);
+  int32_t worst = ORC_DONE;
+  for (int32_t k = 0; k < n_phases; ++k) {
+    /* phase k + 1 grows; earlier phase m + 1 is held as label 4 + m */
+    uint8_t cand[256];
+    uint64_t thr[768];
+    memset(cand, 0, sizeof cand);
+    memset(thr, 0, sizeof thr);
+    cand[0] = 1;
+    for (int32_t m = 0; m < k; ++m) {
+      const double* I = interact + ((size_t)k * (size_t)n_phases + (size_t)m) * 3;
+      if (I[0] > 0.0 || I[1] > 0.0 || I[2] > 0.0) {
+        cand[4 + m] = 1;
+        for (int c = 0; c < 3; ++c) thr[3 * (4 + m) + c] = orc_prob_threshold(I[c]);
+      }
+    }
+    const int32_t st =
+        grow_phase_interacting(nx, ny, nz, &phases[k], labels, cand, thr, &results[k]);
+    if (st > worst) worst = st;
+    for (int64_t v = 0; v < n; ++v)
+      if (labels[v] == 1) labels[v] = (uint8_t)(3 + (k + 1));
+  }
+  for (int64_t v = 0; v < n; ++v)
+    if (labels[v] >= 4) labels[v] = (uint8_t)(labels[v] - 3);
+  return worst;
+}

@@ -115,6 +115,36 @@ int32_t orc_generate(int32_t nx, int32_t ny, int32_t nz, const orc_params* p, ui
 int32_t orc_generate_phases(int32_t nx, int32_t ny, int32_t nz, int32_t n_phases,
                             const orc_params* phases, uint8_t* labels, orc_result* results);
 
+/* One growth step of phase n on a label grid with interacting phases (Sec. 2.1 step 4).
+ * labels: 0 unassigned, 1 the growing phase n, 3 + m a cell of earlier phase m.
+ * cand[l] != 0: a neighbour of label l is a candidate target (label 0 always; 3 + m when
+ * phase n interacts with phase m).  thr[3 l + c]: the threshold of such a target for
+ * direction class c (label 0: the step's Eq. (1) thresholds; 3 + m: P32(I_c^{n,m})).
+ * The j-th candidate neighbour of a source in A (ascending d) takes the draw of rank j
+ * (orc_growth_draw); a passing draw converts the target to label 1.  Candidates, labels
+ * and thresholds are those of the step's start.  Returns the number of converted cells
+ * (listed in `converted`, capacity N); A_next receives the cells of A and the converted
+ * cells that still have a candidate neighbour (*n_next of them).  mask_scratch holds nA
+ * entries.  attempts / successes (52 entries each, may be NULL): per direction d, index
+ * d for unassigned targets and 26 + d for targets of other phases. */
+int64_t orc_step_interacting(int32_t nx, int32_t ny, int32_t nz, uint8_t* labels,
+                             const uint8_t cand[256], const uint64_t thr[768],
+                             const int32_t* A, int64_t nA, uint32_t t, uint64_t key,
+                             int32_t* A_next, int64_t* n_next, int32_t* converted,
+                             uint32_t* mask_scratch, uint64_t* attempts, uint64_t* successes);
+
+/* Multi-phase generation with interacting phases (Sec. 2.1 steps 1-5): as
+ * orc_generate_phases, but phase n also grows into cells of an earlier phase m with the
+ * phase-interaction probability interact[3 ((n - 1) n_phases + (m - 1)) + c] of the
+ * direction's class c (face, edge, corner), not scaled by Eq. (1); entries with m >= n
+ * are not read.  A phase n with I^{n,m} > 0 for some class treats phase m's cells as
+ * candidate targets; a converted cell joins phase n and counts towards its fraction.
+ * results[n - 1].solid_count is phase n's count when it stopped (later phases may convert
+ * some of its cells).  With every I = 0 the result equals orc_generate_phases. */
+int32_t orc_generate_phases_interacting(int32_t nx, int32_t ny, int32_t nz, int32_t n_phases,
+                                        const orc_params* phases, const double* interact,
+                                        uint8_t* labels, orc_result* results);
+
 #ifdef __cplusplus
 }
 #endif
