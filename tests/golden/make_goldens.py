@@ -7,7 +7,7 @@ the per-step series |F_t|, |New_t|, the solid count at the start of each step an
 step's work (draws, high-half Philox blocks).  The group ``lit`` runs cases with the
 literal Algorithm 3 front rule (entries named ``<case>_literal``, ``literal_front`` true).
 
-    python tests/golden/make_goldens.py [--jobs 8] [--only c2,c3,lit]
+    python tests/golden/make_goldens.py [--jobs 8] [--only c2,c3,lit,c4,c4s,c5]
 """
 from __future__ import annotations
 
@@ -57,6 +57,7 @@ def main():
     oracle.build()
     groups = {"c1": workloads.config1, "c2": workloads.config2, "c3": workloads.config3,
               "c4": workloads.config4, "c4s": workloads.config4_singletons,
+              "c5": workloads.config5_parity,
               "lit": lambda: workloads.config1() + workloads.config2()[:1] +
               workloads.config3()[1:2]}
     cases = []

@@ -115,6 +115,19 @@ def config5(n_requests: int = 1000, rate_per_s: float = 100.0, seed: int = 0) ->
             for i in range(n_requests)]
 
 
+def config5_parity(n_first: int = 12, n_large: int = 4) -> list[Case]:
+    """Requests of the config-5 stream checked against the oracle at full size: the first
+    ``n_first`` requests, and the ``n_large`` requests with cube edge >= 300 and spacing
+    >= 25 that have the largest seed probabilities (the heaviest seeding in the mix)."""
+    stream = config5()
+    large = [r for r in stream if r.case.dims[0] >= 300 and r.case.spacing >= 25]
+    large.sort(key=lambda r: -r.case.seed_prob)
+    picked = {r.rid: r for r in stream[:n_first]}
+    for r in large[:n_large]:
+        picked[r.rid] = r
+    return [picked[k].case for k in sorted(picked)]
+
+
 def many_small_cases(n: int = 80, seed: int = 2602) -> list[Case]:
     """More small realizations than one wavefront of the step-end planner handles at
     once (edges U{6..28}, porosity U[0.1, 0.5], S_d U[0.002, 0.05], face U[0.02, 0.2],
