@@ -63,6 +63,15 @@ typedef struct {
   int32_t nx, ny, nz;     /* each >= 1 and nx*ny*nz < 2^31                                */
 } qsgs_dims;
 
+/* Growth forms of the whole-generation calls (qsgs_params.sweep_form).  All three give
+ * the same grids; they differ in the work done per step. */
+#define QSGS_SWEEP_LIST 0      /* list-indexed tile sweep (LIETS, Sec. 2.3, Algorithm 3): */
+                               /* only tiles that may hold the front are visited          */
+#define QSGS_SWEEP_FIELD 1     /* full-field steps (Sec. 2.2, Algorithm 2): every cell of */
+                               /* the grid draws for all its directions every step, then  */
+                               /* a whole-grid pass folds the claims into the solid phase */
+#define QSGS_SWEEP_ALL_TILES 2 /* the tile sweep with every tile listed every step        */
+
 typedef struct {
   double   solid_fraction;/* phi_s in (0, 1]: target solid volume fraction = 1 - porosity */
   double   seed_prob;     /* S_d in [0, 1]: seed (core) probability, Sec. 2.1 step 2       */
@@ -70,16 +79,15 @@ typedef struct {
   int32_t  spacing;       /* s >= 0: minimum pairwise L1 seed distance; s <= 1 = none       */
   int32_t  max_steps;     /* growth step cap; <= 0 selects 2^20                             */
   uint64_t key;           /* Philox key of the realization                                  */
-  int32_t  full_field;    /* whole-generation calls only: 0 = list-indexed sweep (LIETS,    */
-                          /* Alg. 3: only tiles that may hold the front are visited);        */
-                          /* 1 = full-field sweep (Alg. 2: every tile, every step).  Results  */
-                          /* are identical; the full-field form is the baseline for the      */
-                          /* list-indexed one.  Ignored by qsgs_seed / qsgs_grow_step.         */
+  int32_t  sweep_form;    /* whole-generation calls only: QSGS_SWEEP_LIST (0),              */
+                          /* QSGS_SWEEP_FIELD (1) or QSGS_SWEEP_ALL_TILES (2).  Results are   */
+                          /* identical; the full-field form is the baseline the list-indexed */
+                          /* one is measured against.  Ignored by qsgs_seed / qsgs_grow_step. */
   int32_t  front_rule;    /* whole-generation calls only: 0 = the next front is the        */
                           /* interface, prune(F_t u New_t) (Sec. 2.3 steps 2 and 4: failed   */
                           /* sources stay); 1 = Algorithm 3 as printed, prune(New_t): only   */
                           /* this step's new voxels are the next sources.  qsgs_grow_step    */
-                          /* rejects 1 (QSGS_ERR_INVALID).                                   */
+                          /* and the full-field form reject 1 (QSGS_ERR_INVALID).            */
 } qsgs_params;
 
 typedef struct {
@@ -213,6 +221,29 @@ size_t qsgs_phases_workspace_bytes(const qsgs_dims* dims, int32_t n_phases,
 qsgs_status qsgs_generate_phases(const qsgs_dims* dims, int32_t n_phases,
                                  const qsgs_params* phases, uint8_t* d_labels, void* d_ws,
                                  size_t ws_bytes, qsgs_info* infos, void* stream);
+
+/* Multi-phase generation with interacting phases (Sec. 2.1 step 4): as qsgs_generate_phases,
+ * but growing phase n also converts a neighbour that belongs to an earlier phase m, with the
+ * phase-interaction probability of the direction's class.
+ *   interact  host, 3 * n_phases * n_phases doubles: interact[3 ((n-1) n_phases + (m-1)) + c]
+ *             = I_c^{n,m} in [0, 1] for class c (0 face, 1 edge, 2 corner), read for m < n;
+ *             NULL = every I is 0 (qsgs_generate_phases).
+ * Rules (the library's reading of the step): while phase n grows, a neighbour is a
+ * candidate target when it is unassigned, or when it belongs to a phase m with
+ * I_c^{n,m} > 0 for some class c.  The j-th candidate neighbour of a phase-n cell
+ * (ascending direction) takes the draw of rank j (the draw rule above); an unassigned
+ * target passes below the Eq. (1) threshold of the step, a phase-m target below
+ * floor(I_c^{n,m} 2^32) (not scaled by Eq. (1)).  A converted cell belongs to phase n and
+ * counts towards its target fraction; the front is the set of phase-n cells with a
+ * candidate neighbour.  infos[m - 1].solid_count is phase m's count when it stopped (a
+ * later phase may convert some of its cells).  With every I = 0 the result equals
+ * qsgs_generate_phases.  A phase that interacts with an earlier one may not use
+ * QSGS_SWEEP_FIELD (QSGS_ERR_INVALID).  Workspace: qsgs_phases_workspace_bytes.  Other
+ * arguments and errors as qsgs_generate_phases.  Synchronises `stream`. */
+qsgs_status qsgs_generate_phases_interacting(const qsgs_dims* dims, int32_t n_phases,
+                                             const qsgs_params* phases, const double* interact,
+                                             uint8_t* d_labels, void* d_ws, size_t ws_bytes,
+                                             qsgs_info* infos, void* stream);
 
 /* Copies the per-step log of realization `index` of the last qsgs_generate or
  * qsgs_generate_batch that used this workspace into host arrays (any may be NULL):

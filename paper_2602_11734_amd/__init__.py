@@ -16,6 +16,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libqsgs.so")
 
 OK, DONE, EXHAUSTED, MAXSTEPS = 0, 1, 2, 3
+# growth forms of the whole-generation calls (qsgs_params.sweep_form)
+SWEEP_LIST, SWEEP_FIELD, SWEEP_ALL_TILES = 0, 1, 2
 ERR_INVALID, ERR_CAPACITY, ERR_WORKSPACE, ERR_DEVICE = -1, -2, -3, -4
 STATUS_NAMES = {OK: "ok", DONE: "done", EXHAUSTED: "exhausted", MAXSTEPS: "max_steps",
                 ERR_INVALID: "invalid", ERR_CAPACITY: "capacity", ERR_WORKSPACE: "workspace",
@@ -36,7 +38,7 @@ class qsgs_params(ctypes.Structure):
     _fields_ = [("solid_fraction", ctypes.c_double), ("seed_prob", ctypes.c_double),
                 ("g_ref", ctypes.c_double * 3), ("spacing", ctypes.c_int32),
                 ("max_steps", ctypes.c_int32), ("key", ctypes.c_uint64),
-                ("full_field", ctypes.c_int32), ("front_rule", ctypes.c_int32)]
+                ("sweep_form", ctypes.c_int32), ("front_rule", ctypes.c_int32)]
 
 
 class qsgs_info(ctypes.Structure):
@@ -79,6 +81,8 @@ SIGNATURES = {
     "qsgs_phases_workspace_bytes": (_SZ, [_P(qsgs_dims), _I32, _VP]),
     "qsgs_generate_phases": (ctypes.c_int, [_P(qsgs_dims), _I32, _VP, _VP, _VP, _SZ, _VP,
                                             _VP]),
+    "qsgs_generate_phases_interacting": (ctypes.c_int, [_P(qsgs_dims), _I32, _VP, _VP, _VP,
+                                                        _VP, _SZ, _VP, _VP]),
     "qsgs_read_step_log": (_I64, [_VP, _SZ, _I32, _VP, _VP, _VP, _I64, _VP]),
     "qsgs_read_step_work": (_I64, [_VP, _SZ, _I32, _VP, _VP, _I64, _VP]),
     "qsgs_server_reserved_bytes": (_SZ, [_I32]),
@@ -127,18 +131,20 @@ def make_dims(dims) -> qsgs_dims:
 
 
 def make_params(solid_fraction: float, seed_prob: float, g_ref, spacing: int, key: int,
-                max_steps: int = 0, full_field: bool = False,
+                max_steps: int = 0, sweep_form: int = SWEEP_LIST,
                 literal_front: bool = False) -> qsgs_params:
-    """``literal_front``: Algorithm 3's front rule prune(New_t) instead of the interface."""
+    """``sweep_form``: SWEEP_LIST (the list-indexed sweep), SWEEP_FIELD (full-field steps,
+    Algorithm 2) or SWEEP_ALL_TILES; ``literal_front``: Algorithm 3's front rule
+    prune(New_t) instead of the interface."""
     g = (ctypes.c_double * 3)(*[float(v) for v in g_ref])
     return qsgs_params(float(solid_fraction), float(seed_prob), g, int(spacing), int(max_steps),
-                       int(key) & 0xFFFFFFFFFFFFFFFF, 1 if full_field else 0,
+                       int(key) & 0xFFFFFFFFFFFFFFFF, int(sweep_form),
                        1 if literal_front else 0)
 
 
-def params_of(case, full_field: bool = False, literal_front: bool = False) -> qsgs_params:
+def params_of(case, sweep_form: int = SWEEP_LIST, literal_front: bool = False) -> qsgs_params:
     return make_params(case.solid_fraction, case.seed_prob, case.g_ref, case.spacing, case.key,
-                       case.max_steps, full_field, literal_front)
+                       case.max_steps, sweep_form, literal_front)
 
 
 def _ptr(x) -> int | None:
@@ -271,6 +277,26 @@ def qsgs_generate_phases(dims, phases, labels, ws, ws_bytes: int, stream=None):
     return _check(st), list(infos)
 
 
+def qsgs_generate_phases_interacting(dims, phases, interact, labels, ws, ws_bytes: int,
+                                     stream=None):
+    """Multi-phase generation with interacting phases; ``interact`` is None or an array
+    [n_phases, n_phases, 3] of I_c^{n,m} (index [n - 1, m - 1, c], read for m < n).
+    Returns (status, list of qsgs_info, one per phase)."""
+    import numpy as np
+    n = len(phases)
+    p = (qsgs_params * n)(*phases)
+    infos = (qsgs_info * n)()
+    I = None
+    if interact is not None:
+        I = np.ascontiguousarray(interact, dtype=np.float64)
+        if I.shape != (n, n, 3):
+            raise QsgsError(ERR_INVALID, f"interact must have shape ({n}, {n}, 3)")
+    st = load().qsgs_generate_phases_interacting(
+        ctypes.byref(make_dims(dims)), n, p, None if I is None else I.ctypes.data, _ptr(labels),
+        _ptr(ws), int(ws_bytes), infos, _stream(stream))
+    return _check(st), list(infos)
+
+
 def qsgs_server_reserved_bytes(max_slots: int) -> int:
     return int(load().qsgs_server_reserved_bytes(int(max_slots)))
 
@@ -399,9 +425,10 @@ def generate(dims, params: qsgs_params, buffers: Buffers | None = None, stream=N
     return buffers.view(), d, buffers
 
 
-def generate_phases(dims, phases, stream=None, device: str = "cuda"):
-    """Run qsgs_generate_phases; returns (label grid view [nz, ny, nx] uint8 on the
-    device: n for phase n, 0 for the matrix; list of per-phase info dicts)."""
+def generate_phases(dims, phases, stream=None, device: str = "cuda", interact=None):
+    """Run qsgs_generate_phases (or, with ``interact``, qsgs_generate_phases_interacting);
+    returns (label grid view [nz, ny, nx] uint8 on the device: n for phase n, 0 for the
+    matrix; list of per-phase info dicts)."""
     import torch
     dims = tuple(int(v) for v in dims)
     gb = qsgs_grid_bytes(dims)
@@ -410,7 +437,11 @@ def generate_phases(dims, phases, stream=None, device: str = "cuda"):
         raise QsgsError(ERR_INVALID, qsgs_last_error() or "invalid dims or phases")
     labels = torch.empty(gb, dtype=torch.uint8, device=device)
     ws = torch.empty(wb, dtype=torch.uint8, device=device)
-    _, infos = qsgs_generate_phases(dims, phases, labels, ws, wb, stream=stream)
+    if interact is None:
+        _, infos = qsgs_generate_phases(dims, phases, labels, ws, wb, stream=stream)
+    else:
+        _, infos = qsgs_generate_phases_interacting(dims, phases, interact, labels, ws, wb,
+                                                    stream=stream)
     out = []
     for info in infos:
         d = info.as_dict()

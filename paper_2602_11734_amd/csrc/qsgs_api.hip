@@ -1,5 +1,7 @@
 // qsgs_api.hip -- host side of libqsgs: seeding, single steps, whole generations and
 // batches (C ABI in include/qsgs.h), all driven through the shared Engine.
+#include <array>
+
 #include "qsgs_host.h"
 
 using namespace qsgs;
@@ -15,19 +17,24 @@ constexpr size_t kStepWorkspace = 1024 * 1024;
 struct GenLayout {
   PersistLayout P;
   std::vector<size_t> sweep;
+  size_t itab = 0;  // multi-phase grids: the interaction table of the growing phase
   size_t seed = 0, total = 0;
   SeedLayout S;
 };
 
-GenLayout gen_layout(const std::vector<Spec>& specs, bool with_sweep) {
+GenLayout gen_layout(const std::vector<Spec>& specs, bool with_sweep, bool walls = false) {
   GenLayout G;
   G.P = persist_layout(specs.size(), specs.size() == 1 ? kLogCapSingle : kLogCapBatch);
   size_t off = G.P.total;
   if (with_sweep) {
     for (const Spec& s : specs) {
       G.sweep.push_back(off);
-      off = align_up(off + sweep_state_bytes(s.g));
+      off = align_up(off + sweep_state_bytes(s.g, walls));
     }
+  }
+  if (walls) {
+    G.itab = off;
+    off = align_up(off + sizeof(InteractTable));
   }
   G.seed = off;
   G.S = seed_layout(specs, true);
@@ -53,13 +60,17 @@ qsgs_status make_specs(int32_t count, const qsgs_dims* dims, const qsgs_params* 
 // no_alloc: the call may not allocate (the allocation-free entry point): transfers go
 // through pageable host memory instead of the pinned staging buffer, and no timing
 // events are recorded.
+// itab (walls only, may be null): the interaction table of the phase being grown, with
+// ihi_max[c] the largest high half of its thresholds per class.
 qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_params* params,
                           uint8_t* const* grids, void* ws, size_t ws_bytes, qsgs_info* infos,
-                          hipStream_t s, bool walls = false, bool no_alloc = false) {
+                          hipStream_t s, bool walls = false, bool no_alloc = false,
+                          const InteractTable* itab = nullptr,
+                          const uint32_t* ihi_max = nullptr) {
   std::vector<Spec> specs;
   QSGS_TRY(make_specs(count, dims, params, grids, &specs));
   if (!ws || !infos) return fail(QSGS_ERR_INVALID, "d_ws and info must not be NULL");
-  const GenLayout G = gen_layout(specs, true);
+  const GenLayout G = gen_layout(specs, true, walls);
   if (ws_bytes < G.total)
     return fail(QSGS_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", G.total, ws_bytes);
   Engine E;
@@ -68,9 +79,17 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
   E.stage = no_alloc ? nullptr : thread_pinned_stage(Engine::stage_bytes((size_t)count));
   std::vector<size_t> group;
   for (int32_t r = 0; r < count; ++r) {
-    E.init_sweep_record((size_t)r, specs[r], &params[r], grids[r], at<void>(ws, G.sweep[r]));
-    E.reals[r].walls = walls ? 1u : 0u;
+    E.init_sweep_record((size_t)r, specs[r], &params[r], grids[r], at<void>(ws, G.sweep[r]),
+                        walls);
     group.push_back((size_t)r);
+  }
+  if (walls && itab) {
+    InteractTable* d_itab = at<InteractTable>(ws, G.itab);
+    QSGS_HIP(hipMemcpyAsync(d_itab, itab, sizeof(InteractTable), hipMemcpyHostToDevice, s));
+    for (int32_t r = 0; r < count; ++r) {
+      E.reals[r].itab = d_itab;
+      for (int c = 0; c < 3; ++c) E.reals[r].ihi_max[c] = ihi_max[c];
+    }
   }
   E.attach_scratch(group, at<void>(ws, G.seed), G.S);
   const bool profiling = prof_on() && !no_alloc;
@@ -85,9 +104,10 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
   QSGS_TRY(E.upload_control());
   QSGS_TRY(E.upload(0, E.reals.size()));
   QSGS_TRY(E.seed_core(at<void>(ws, G.seed), G.S));
-  QSGS_TRY(E.sweep_start());
+  QSGS_TRY(E.sweep_start(group));
   if (profiling) QSGS_HIP(hipEventRecord(e1, s));
   QSGS_TRY(E.run_sweep_loop());
+  QSGS_TRY(E.export_grids());
   std::vector<Real> fin;
   QSGS_TRY(E.read_all(&fin));
   if (profiling) {
@@ -291,11 +311,12 @@ constexpr uint32_t kWallBase = 3;
 size_t qsgs_phases_workspace_bytes(const qsgs_dims* dims, int32_t n_phases,
                                    const qsgs_params* phases) {
   if (!dims || !phases || n_phases < 1 || n_phases > kMaxPhases) return 0;
+  Geometry g{};
+  if (check_dims(dims, &g) != QSGS_OK) return 0;
   size_t m = 0;
-  for (int32_t k = 0; k < n_phases; ++k) {
-    const size_t b = qsgs_workspace_bytes(dims, &phases[k]);
-    if (b == 0) return 0;
-    m = std::max(m, b);
+  for (int32_t k = 0; k < n_phases; ++k) {  // one phase at a time, with the walls plane
+    if (check_params(&phases[k]) != QSGS_OK) return 0;
+    m = std::max(m, gen_layout({Spec{g, make_buckets(g, phases[k].spacing)}}, true, true).total);
   }
   return m;
 }
@@ -304,6 +325,15 @@ qsgs_status qsgs_generate_phases(const qsgs_dims* dims, int32_t n_phases,
                                  const qsgs_params* phases, uint8_t* d_labels, void* d_ws,
                                  size_t ws_bytes, qsgs_info* infos, void* stream) {
   last_error().clear();
+  return qsgs_generate_phases_interacting(dims, n_phases, phases, nullptr, d_labels, d_ws,
+                                          ws_bytes, infos, stream);
+}
+
+qsgs_status qsgs_generate_phases_interacting(const qsgs_dims* dims, int32_t n_phases,
+                                             const qsgs_params* phases, const double* interact,
+                                             uint8_t* d_labels, void* d_ws, size_t ws_bytes,
+                                             qsgs_info* infos, void* stream) {
+  last_error().clear();
   if (!dims || !phases || !d_labels || !d_ws || !infos)
     return fail(QSGS_ERR_INVALID, "dims, phases, d_labels, d_ws and infos must not be NULL");
   if (n_phases < 1 || n_phases > kMaxPhases)
@@ -311,6 +341,41 @@ qsgs_status qsgs_generate_phases(const qsgs_dims* dims, int32_t n_phases,
   Geometry g{};
   QSGS_TRY(check_dims(dims, &g));
   for (int32_t k = 0; k < n_phases; ++k) QSGS_TRY(check_params(&phases[k]));
+  // the interaction tables: phase k + 1 may convert earlier phase m + 1 (grid byte 4 + m)
+  std::vector<InteractTable> tabs;
+  std::vector<std::array<uint32_t, 3>> hmax;
+  std::vector<bool> interacts((size_t)n_phases, false);
+  if (interact) {
+    tabs.resize((size_t)n_phases);
+    hmax.assign((size_t)n_phases, {0u, 0u, 0u});
+    for (int32_t k = 0; k < n_phases; ++k) {
+      InteractTable& T = tabs[(size_t)k];
+      std::memset(&T, 0, sizeof T);
+      for (int32_t m = 0; m < k; ++m) {
+        const double* I = interact + 3 * ((size_t)k * (size_t)n_phases + (size_t)m);
+        bool any = false;
+        for (int c = 0; c < 3; ++c) {
+          if (!is_prob(I[c]))
+            return fail(QSGS_ERR_INVALID, "interaction of phase %d with phase %d, class %d, "
+                        "must be in [0, 1]", k + 1, m + 1, c);
+          any = any || I[c] > 0.0;
+        }
+        if (!any) continue;
+        const uint32_t b = kWallBase + 1u + (uint32_t)m;
+        T.bits[b >> 5] |= 1u << (b & 31u);
+        for (int c = 0; c < 3; ++c) {
+          const uint64_t thr = prob_threshold(I[c]);
+          T.thr[6 * b + c] = (uint32_t)(thr >> 16);
+          T.thr[6 * b + 3 + c] = (uint32_t)(thr & 0xFFFFu);
+          hmax[(size_t)k][c] = std::max(hmax[(size_t)k][c], (uint32_t)(thr >> 16));
+        }
+        interacts[(size_t)k] = true;
+      }
+      if (interacts[(size_t)k] && phases[k].sweep_form == QSGS_SWEEP_FIELD)
+        return fail(QSGS_ERR_INVALID, "phase %d interacts with an earlier phase: the "
+                    "full-field form does not convert other phases", k + 1);
+    }
+  }
   if (reinterpret_cast<uintptr_t>(d_labels) % 4 != 0)
     return fail(QSGS_ERR_INVALID, "d_labels must be 4-byte aligned");
   const size_t need = qsgs_phases_workspace_bytes(dims, n_phases, phases);
@@ -323,8 +388,10 @@ qsgs_status qsgs_generate_phases(const qsgs_dims* dims, int32_t n_phases,
   QSGS_HIP(hipMemsetAsync(d_labels, 0, gb, s));
   int32_t worst = QSGS_OK;
   for (int32_t k = 0; k < n_phases; ++k) {
+    const bool it = interacts[(size_t)k];
     const qsgs_status st =
-        generate_impl(1, dims, &phases[k], &d_labels, d_ws, ws_bytes, &infos[k], s, true);
+        generate_impl(1, dims, &phases[k], &d_labels, d_ws, ws_bytes, &infos[k], s, true, false,
+                      it ? &tabs[(size_t)k] : nullptr, it ? hmax[(size_t)k].data() : nullptr);
     if (st < 0) return st;
     worst = std::max(worst, (int32_t)st);
     ByteMap m{};  // the phase's cells become walls for the phases after it

@@ -119,10 +119,12 @@ inline qsgs_status check_params(const qsgs_params* p) {
   for (int c = 0; c < 3; ++c)
     if (!is_prob(p->g_ref[c])) return fail(QSGS_ERR_INVALID, "g_ref[%d] must be in [0, 1]", c);
   if (p->spacing < 0) return fail(QSGS_ERR_INVALID, "spacing must be >= 0");
-  if (p->full_field != 0 && p->full_field != 1)
-    return fail(QSGS_ERR_INVALID, "full_field must be 0 or 1");
+  if (p->sweep_form < QSGS_SWEEP_LIST || p->sweep_form > QSGS_SWEEP_ALL_TILES)
+    return fail(QSGS_ERR_INVALID, "sweep_form must be 0 (list), 1 (full field) or 2 (all tiles)");
   if (p->front_rule != 0 && p->front_rule != 1)
     return fail(QSGS_ERR_INVALID, "front_rule must be 0 or 1");
+  if (p->front_rule == 1 && p->sweep_form == QSGS_SWEEP_FIELD)
+    return fail(QSGS_ERR_INVALID, "the full-field form has no front: front_rule must be 0");
   return QSGS_OK;
 }
 
@@ -148,11 +150,19 @@ inline Tiles make_tiles(const Geometry& g) {
 }
 
 // Device memory of the fused sweep per realization: two tile lists of 2 x tiles
-// entries (parts, then spills) and the tile stamps.
+// entries (parts, then spills), the tile stamps and the occupancy planes (S, M0, M1,
+// and W on a multi-phase grid) of ntx * ny * nz 64-bit words each.
 inline size_t list_bytes(const Geometry& g) { return 2 * sizeof(int32_t) * (size_t)make_tiles(g).n; }
 inline size_t stamp_bytes(const Geometry& g) { return sizeof(uint32_t) * (size_t)make_tiles(g).n; }
-inline size_t sweep_state_bytes(const Geometry& g) {
-  return 2 * align_up(list_bytes(g)) + align_up(stamp_bytes(g));
+inline uint32_t plane_words(const Geometry& g) {
+  return make_tiles(g).ntx * (uint32_t)g.ny * (uint32_t)g.nz;
+}
+// S, M0, M1; on a multi-phase grid also W and X
+inline size_t plane_bytes(const Geometry& g, bool walls) {
+  return sizeof(uint64_t) * (size_t)plane_words(g) * (walls ? 5 : 3);
+}
+inline size_t sweep_state_bytes(const Geometry& g, bool walls) {
+  return 2 * align_up(list_bytes(g)) + align_up(stamp_bytes(g)) + align_up(plane_bytes(g, walls));
 }
 
 inline Buckets make_buckets(const Geometry& g, int32_t spacing) {
@@ -481,12 +491,15 @@ struct Engine {
   }
 
   void init_sweep_record(size_t r, const Spec& sp, const qsgs_params* p, uint8_t* grid,
-                         void* sweep) {
+                         void* sweep, bool walls) {
     const size_t lb = align_up(list_bytes(sp.g));
     init_record(r, sp, p, grid, at<int32_t>(sweep, 0), at<int32_t>(sweep, lb),
                 2 * make_tiles(sp.g).n);
     reals[r].stamp = at<uint32_t>(sweep, 2 * lb);
-    reals[r].full = (uint32_t)p->full_field;
+    reals[r].planes = at<uint64_t>(sweep, 2 * lb + align_up(stamp_bytes(sp.g)));
+    reals[r].pwords = plane_words(sp.g);
+    reals[r].walls = walls ? 1u : 0u;
+    reals[r].form = (uint32_t)p->sweep_form;
     reals[r].literal = (uint32_t)p->front_rule;
   }
 
@@ -673,50 +686,95 @@ struct Engine {
     return QSGS_OK;
   }
 
-  // Loop state of the fused sweep for freshly seeded records: their first tile lists
-  // (the tiles of their seeds) and the plan of the first pass.
-  qsgs_status sweep_start() {
+  // Loop state of the fused sweep for the freshly seeded records `group`: their first
+  // tile lists (the tiles of their seeds; every tile for the all-tiles form), their
+  // occupancy planes and the plan of the first pass.
+  qsgs_status sweep_start(const std::vector<size_t>& group) {
     QSGS_TRY(offsets(kItemsSeeds));
     hipLaunchKernelGGL(k_seed_tiles, dim3(tune.seed_grid), dim3(tune.seed_block), 0, s, args);
     QSGS_LAUNCHED("k_seed_tiles");
-    bool any_full = false;
-    for (const Real& R : reals) any_full = any_full || (R.phase == kPhaseSeed && R.full);
-    if (any_full) {
+    bool any_all_tiles = false;
+    for (size_t r : group) any_all_tiles = any_all_tiles || reals[r].form == kFormAllTiles;
+    if (any_all_tiles) {
       QSGS_TRY(offsets(kItemsVoxels));
       hipLaunchKernelGGL(k_full_tiles, dim3(tune.seed_grid), dim3(tune.seed_block), 0, s, args);
       QSGS_LAUNCHED("k_full_tiles");
     }
+    QSGS_TRY(offsets(kItemsPack));
+    hipLaunchKernelGGL(k_pack_planes, dim3(tune.seed_grid), dim3(tune.seed_block), 0, s, args);
+    QSGS_LAUNCHED("k_pack_planes");
     hipLaunchKernelGGL(k_sweep_prepare, dim3(1), dim3(1024), 0, s, args);
     QSGS_LAUNCHED("k_sweep_prepare");
     return QSGS_OK;
   }
 
-  // One fused pass (front of step t and its growth) over every record with a pending
-  // pass; k_sweep_end ends the step.
-  qsgs_status sweep_pass(std::vector<hipEvent_t>* ev) {
+  // Writes the byte grid of every realization whose loop has stopped since the last
+  // call, from its solid plane.
+  qsgs_status export_grids() {
+    QSGS_TRY(offsets(kItemsExport));
+    hipLaunchKernelGGL(k_export_planes, dim3(tune.seed_grid), dim3(tune.seed_block), 0, s, args);
+    QSGS_LAUNCHED("k_export_planes");
+    hipLaunchKernelGGL(k_export_done, rgrid(), dim3(256), 0, s, args);
+    QSGS_LAUNCHED("k_export_done");
+    return QSGS_OK;
+  }
+
+  // Which passes the records need: `tiles` when a record in a tile-sweep form may still
+  // be growing, `field` when one in the full-field form may.  A caller that keeps some
+  // slots empty passes their records' flags as false through `live`.
+  void forms_in_use(bool* tiles, bool* field, const std::vector<bool>* live = nullptr) const {
+    *tiles = *field = false;
+    for (size_t r = 0; r < reals.size(); ++r) {
+      if (live && !(*live)[r]) continue;
+      if (reals[r].form == kFormField)
+        *field = true;
+      else
+        *tiles = true;
+    }
+  }
+
+  // One pass over every record with a pending pass: the fused tile sweep (front of step t
+  // and its growth; k_sweep_end ends the step) and/or the full-field step (every cell;
+  // k_field_fold, then k_field_end ends the step).
+  qsgs_status sweep_pass(std::vector<hipEvent_t>* ev, bool tiles = true, bool field = false) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ev) {
       e0 = prof_event();
       e1 = prof_event();
       QSGS_HIP(hipEventRecord(e0, s));
     }
-    bool walls = false, literal = false;
-    for (const Real& R : reals) {
-      walls = walls || R.walls != 0;
-      literal = literal || R.literal != 0;
+    if (tiles) {
+      bool walls = false, literal = false;
+      for (const Real& R : reals) {
+        walls = walls || R.walls != 0;
+        literal = literal || R.literal != 0;
+      }
+      auto kernel = walls ? (literal ? k_sweep<true, true> : k_sweep<true, false>)
+                          : (literal ? k_sweep<false, true> : k_sweep<false, false>);
+      hipLaunchKernelGGL(kernel, dim3(sweep_grid), dim3(tune.grow_block),
+                         sweep_lds_bytes(tune.grow_block), s, args);
+      QSGS_LAUNCHED("k_sweep");
     }
-    auto kernel = walls ? (literal ? k_sweep<true, true> : k_sweep<true, false>)
-                        : (literal ? k_sweep<false, true> : k_sweep<false, false>);
-    hipLaunchKernelGGL(kernel, dim3(sweep_grid), dim3(tune.grow_block),
-                       sweep_lds_bytes(tune.grow_block), s, args);
-    QSGS_LAUNCHED("k_sweep");
+    if (field) {
+      QSGS_TRY(offsets(kItemsField));
+      hipLaunchKernelGGL(k_field_step, dim3(tune.seed_grid), dim3(tune.seed_block), 0, s, args);
+      QSGS_LAUNCHED("k_field_step");
+    }
     if (ev) {
       QSGS_HIP(hipEventRecord(e1, s));
       ev->push_back(e0);
       ev->push_back(e1);
     }
-    hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(1024), 0, s, args);
-    QSGS_LAUNCHED("k_sweep_end");
+    if (tiles) {
+      hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(1024), 0, s, args);
+      QSGS_LAUNCHED("k_sweep_end");
+    }
+    if (field) {
+      hipLaunchKernelGGL(k_field_fold, dim3(tune.seed_grid), dim3(tune.seed_block), 0, s, args);
+      QSGS_LAUNCHED("k_field_fold");
+      hipLaunchKernelGGL(k_field_end, dim3(1), dim3(1024), 0, s, args, tiles ? 0u : 1u);
+      QSGS_LAUNCHED("k_field_end");
+    }
     return QSGS_OK;
   }
 
@@ -726,6 +784,8 @@ struct Engine {
   // (passes after the stop find nothing to do and cost two empty launches, less than a
   // round trip to the host).
   qsgs_status run_sweep_loop() {
+    bool tiles = false, field = false;
+    forms_in_use(&tiles, &field);
     const bool profiling = prof_on() && !no_events;
     std::vector<hipEvent_t> ev;
     BatchCtl b{};
@@ -745,7 +805,8 @@ struct Engine {
         else if (c.step > 0)
           chunk = 4;
       }
-      for (uint32_t k = 0; k < chunk; ++k) QSGS_TRY(sweep_pass(profiling ? &ev : nullptr));
+      for (uint32_t k = 0; k < chunk; ++k)
+        QSGS_TRY(sweep_pass(profiling ? &ev : nullptr, tiles, field));
       QSGS_TRY(read_state());
     }
     if (profiling && !ev.empty()) {

@@ -54,6 +54,30 @@ struct Tiles {
   FastDiv div_ntx, div_nty;
 };
 
+// Occupancy bit planes of the fused sweep.  A plane holds one bit per voxel in rows of
+// ntx 64-bit words: word ix + ntx (y + ny z), bit b is voxel x = 64 ix + b (bits past
+// nx stay 0), so a 64 x 4 x 4 tile's interior is 16 whole words.
+//   S        solid at the start of the current step (the seeds, then every folded mark);
+//   M0, M1   claims of the steps with t even / odd; the pass of step t claims into
+//            M[t & 1] and folds the tile's bits of M[(t - 1) & 1] into S.  Solid at the
+//            start of step t is S | M[(t - 1) & 1] whether or not the fold has happened.
+//            A mark plane keeps bits of earlier steps (never cleared); such cells are
+//            also in S, so they are never void and never claimed again;
+//   W        (multi-phase generation) cells of other phases: neither void nor sources.
+//   X        (interacting phases) cells of the other phases that the growing phase may
+//            convert (Sec. 2.1 step 4): candidates like unassigned cells, with their own
+//            thresholds.
+constexpr uint32_t kPlaneS = 0, kPlaneM0 = 1, kPlaneM1 = 2, kPlaneW = 3, kPlaneX = 4;
+
+// Interaction table of a growing phase (device memory, Sec. 2.1 step 4): for grid byte
+// b = 3 + m (a cell of earlier phase m), thr[6 b + c] and thr[6 b + 3 + c] are the high
+// and low 16-bit halves of P32(I_c^{n,m}) (c = face, edge, corner; a threshold of 2^32 is
+// high half 65536), and bit b of bits marks the phases it may convert.
+struct InteractTable {
+  uint32_t thr[256 * 6];
+  uint32_t bits[8];
+};
+
 // Per-step log of a realization: |F_t|, voxels grown in step t, the solid count at the
 // start of step t, the step's draws and its high-half Philox blocks.
 constexpr uint32_t kLogWords = 5;
@@ -95,7 +119,17 @@ struct Ctl {
   uint32_t mode;        // kModeIdle / kModeRun / kModeFinal
   uint32_t kept;
   uint32_t pad0;
+  uint32_t export_state;  // fused sweep: 0 running, 1 stopped (grid to be written), 2 written
+  // full-field form: the current step's front, growth and draws, summed by its step kernel
+  uint32_t ff_front;
+  uint32_t ff_grown;
+  uint32_t pad1;
+  uint64_t ff_draws;
 };
+
+// Growth forms of the whole-generation path: the list-indexed tile sweep (LIETS), the
+// full-field step of every cell (Algorithm 2), and the tile sweep over every tile.
+constexpr uint32_t kFormList = 0, kFormField = 1, kFormAllTiles = 2;
 
 // Pass modes of the fused sweep: a running pass finds F_t in its tiles and grows from
 // it; a final pass only counts F_T and folds the last step's marks (clean 0/1 grid).
@@ -114,7 +148,7 @@ struct Real {
   int32_t* f1;
   uint32_t* stamp;      // fused sweep: per tile, 1 + the last pass whose list holds it
   Tiles tl;
-  uint32_t full;        // fused sweep over every tile every step (full-field form)
+  uint32_t form;        // kFormList, kFormField (full-field steps) or kFormAllTiles
   int32_t* cand;        // candidates, then the seed list (N entries)
   uint64_t* log;        // per-step log (3 words per step) or null
   uint32_t log_cap;
@@ -127,6 +161,15 @@ struct Real {
   uint32_t walls;       // the grid holds other phases' cells (bytes >= 4): never cores,
                         // sources or targets; seeding keeps the grid instead of clearing it
   uint32_t literal;     // front rule: the next sources are only this step's new voxels
+  // fused sweep: occupancy bit planes of pwords 64-bit words each (see kPlane*)
+  uint64_t* planes;
+  uint32_t pwords;
+  uint32_t pad2;
+  // interacting phases: the table of the growing phase (null: independent), and per
+  // class the largest high half of its interaction thresholds
+  const InteractTable* itab;
+  uint32_t ihi_max[3];
+  uint32_t pad3;
   Ctl ctl;
 };
 
@@ -170,6 +213,9 @@ enum ItemKind : uint32_t {
   kItemsPrune = 4,   // F_t + New_t of running realizations
   kItemsList = 5,    // L_t of realizations with a pending fused pass
   kItemsQuads = 6,   // every aligned group of four voxels (seed draw)
+  kItemsPack = 7,    // plane words of freshly seeded realizations (byte grid -> planes)
+  kItemsExport = 8,  // plane words of stopped realizations whose grid is not yet written
+  kItemsField = 9,   // plane words of full-field realizations with a pending step
 };
 
 struct BatchArgs {
@@ -216,6 +262,12 @@ __global__ void k_rollback(uint8_t* grid, uint32_t n);
 __global__ void k_seed_tiles(BatchArgs A);
 __global__ void k_full_tiles(BatchArgs A);
 __global__ void k_sweep_prepare(BatchArgs A);
+__global__ void k_pack_planes(BatchArgs A);
+__global__ void k_export_planes(BatchArgs A);
+__global__ void k_export_done(BatchArgs A);
+__global__ void k_field_step(BatchArgs A);
+__global__ void k_field_fold(BatchArgs A);
+__global__ void k_field_end(BatchArgs A, uint32_t reset_running);
 // dynamic LDS: sweep_lds_bytes(blockDim.x); kWalls: the grids may hold other phases' cells;
 // kLiteral: some realizations take only the previous step's new voxels as sources
 template <bool kWalls, bool kLiteral> __global__ void k_sweep(BatchArgs A);

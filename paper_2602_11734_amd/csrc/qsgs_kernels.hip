@@ -34,6 +34,10 @@ __device__ __forceinline__ uint64_t items_of(const Real& R, uint32_t kind) {
     case kItemsGrow: return growing ? c.front_size : 0;
     case kItemsPrune:
       return (growing && !c.overflow) ? (uint64_t)c.front_size + c.new_count : 0;
+    case kItemsPack: return (seeding && R.planes) ? R.pwords : 0;
+    case kItemsExport: return (R.phase == kPhaseGrow && c.export_state == 1u) ? R.pwords : 0;
+    case kItemsField:
+      return (growing && R.form == kFormField && c.mode != kModeIdle) ? R.pwords : 0;
     default: return (growing && c.mode != kModeIdle) ? c.n_list : 0;
   }
 }
@@ -562,7 +566,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_collect_seeds(BatchArgs A) {
 __global__ __launch_bounds__(kMaxBlock) void k_full_tiles(BatchArgs A) {
   for_each_chunk(A, kItemsVoxels, [&](uint32_t r, uint32_t i) {
     Real& R = A.reals[r];
-    if (!R.full || i >= R.tl.n) return;
+    if (R.form != kFormAllTiles || i >= R.tl.n) return;
     R.f0[i] = (int32_t)i;
     R.f1[i] = (int32_t)i;
     if (i == 0) R.ctl.n_list = R.tl.n;
@@ -574,7 +578,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_full_tiles(BatchArgs A) {
 __global__ __launch_bounds__(kMaxBlock) void k_seed_tiles(BatchArgs A) {
   for_each_chunk(A, kItemsSeeds, [&](uint32_t r, uint32_t i) {
     Real& R = A.reals[r];
-    if (R.full) return;  // (uniform per wavefront)
+    if (R.form != kFormList) return;  // (uniform per wavefront)
     bool fresh = false;
     uint32_t u = 0;
     if (i < R.ctl.n_seeds) {
@@ -1053,8 +1057,14 @@ __device__ uint32_t block_scan_u32(uint32_t n, Val val, Out out) {
   return total;
 }
 
+// A realization with a pending tile-sweep pass, or (field_active) a pending full-field step.
 __device__ __forceinline__ bool sweep_active(const Real& R) {
-  return R.phase == kPhaseGrow && R.ctl.status == 0 && R.ctl.mode != kModeIdle;
+  return R.phase == kPhaseGrow && R.ctl.status == 0 && R.ctl.mode != kModeIdle &&
+         R.form != kFormField;
+}
+__device__ __forceinline__ bool field_active(const Real& R) {
+  return R.phase == kPhaseGrow && R.ctl.status == 0 && R.ctl.mode != kModeIdle &&
+         R.form == kFormField;
 }
 
 // Entry prefix and workgroup assignment of plan q, whose segment table and
@@ -1105,6 +1115,94 @@ __device__ void plan_assign(const BatchArgs& A, uint32_t q) {
       [&](uint32_t r, uint32_t x) { P.wgoff[r] = x; });
   if (threadIdx.x == 0) P.wgoff[A.count] = nwg;
   __syncthreads();
+}
+
+// Byte grid <-> occupancy planes of the fused sweep.  Items are plane words; a chunk of
+// 64 words is handled word by word, lane b taking voxel x = 64 ix + b of the word's row,
+// so every grid access of the wavefront is one coalesced 64-byte row piece.
+
+// After seeding: S = the seeds (byte 1), M0 = M1 = 0, W = cells of other phases (bytes
+// above 1, multi-phase generation only).
+__global__ __launch_bounds__(kMaxBlock) void k_pack_planes(BatchArgs A) {
+  const uint32_t lane = lane_id();
+  for_each_chunk(A, kItemsPack, [&](uint32_t r, uint32_t i) {
+    const Real& R = A.reals[r];
+    const uint32_t pw = uniform(R.pwords);
+    const uint32_t w0 = i - lane;
+    if (w0 >= pw) return;  // (uniform) padding of the item range
+    const uint32_t nw = min((uint32_t)kWave, pw - w0);
+    const uint32_t nx = (uint32_t)uniform((uint32_t)R.g.nx), ntx = uniform(R.tl.ntx);
+    const FastDiv dntx = R.tl.div_ntx;
+    const __attribute__((address_space(1))) uint8_t* grid =
+        (const __attribute__((address_space(1))) uint8_t*)uniform64((uint64_t)R.grid);
+    // the phases an interacting phase may convert (bit b: grid byte b)
+    const InteractTable* it = (const InteractTable*)uniform64((uint64_t)R.itab);
+    uint64_t s_mine = 0, w_mine = 0, x_mine = 0;
+    for (uint32_t j = 0; j < nw; ++j) {
+      const uint32_t w = w0 + j;
+      const uint32_t row = dntx.div(w);
+      const uint32_t x = (w - row * ntx) * (uint32_t)kTileX + lane;
+      const uint32_t b = x < nx ? (uint32_t)grid[row * nx + x] : 0u;
+      const uint64_t sm = __ballot(b == kSolid);
+      const uint64_t wm = __ballot(b > kSolid);
+      const uint64_t xm = it ? __ballot(b > kSolid && ((it->bits[b >> 5] >> (b & 31u)) & 1u))
+                             : 0ull;
+      if (lane == j) {
+        s_mine = sm;
+        w_mine = wm;
+        x_mine = xm;
+      }
+    }
+    if (lane < nw) {
+      uint64_t* P = (uint64_t*)uniform64((uint64_t)R.planes);
+      P[(size_t)kPlaneS * pw + w0 + lane] = s_mine;
+      P[(size_t)kPlaneM0 * pw + w0 + lane] = 0ull;
+      P[(size_t)kPlaneM1 * pw + w0 + lane] = 0ull;
+      if (R.walls) P[(size_t)kPlaneW * pw + w0 + lane] = w_mine;
+      if (it) P[(size_t)kPlaneX * pw + w0 + lane] = x_mine;
+    }
+  });
+}
+
+// After the last pass of a realization (every mark folded into S): byte = S bit, or, on
+// a multi-phase grid, 1 where S is set and the byte unchanged elsewhere.
+__global__ __launch_bounds__(kMaxBlock) void k_export_planes(BatchArgs A) {
+  const uint32_t lane = lane_id();
+  for_each_chunk(A, kItemsExport, [&](uint32_t r, uint32_t i) {
+    const Real& R = A.reals[r];
+    const uint32_t pw = uniform(R.pwords);
+    const uint32_t w0 = i - lane;
+    if (w0 >= pw) return;  // (uniform)
+    const uint32_t nw = min((uint32_t)kWave, pw - w0);
+    const uint32_t nx = (uint32_t)uniform((uint32_t)R.g.nx), ntx = uniform(R.tl.ntx);
+    const FastDiv dntx = R.tl.div_ntx;
+    const bool walls = uniform(R.walls) != 0;
+    __attribute__((address_space(1))) uint8_t* grid =
+        (__attribute__((address_space(1))) uint8_t*)uniform64((uint64_t)R.grid);
+    const uint64_t* S = (const uint64_t*)uniform64((uint64_t)R.planes);
+    const uint64_t mine = lane < nw ? S[w0 + lane] : 0ull;
+    const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
+    for (uint32_t j = 0; j < nw; ++j) {
+      const uint32_t w = w0 + j;
+      const uint32_t row = dntx.div(w);
+      const uint32_t x = (w - row * ntx) * (uint32_t)kTileX + lane;
+      const uint32_t half = lane < 32u ? (uint32_t)__builtin_amdgcn_readlane(mlo, j)
+                                       : (uint32_t)__builtin_amdgcn_readlane(mhi, j);
+      const uint32_t bit = (half >> (lane & 31u)) & 1u;
+      if (x < nx) {
+        if (!walls)
+          grid[row * nx + x] = (uint8_t)bit;
+        else if (bit)
+          grid[row * nx + x] = kSolid;
+      }
+    }
+  });
+}
+
+// The grids of the realizations exported by the last k_export_planes are written.
+__global__ void k_export_done(BatchArgs A) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < A.count && A.reals[r].ctl.export_state == 1u) A.reals[r].ctl.export_state = 2u;
 }
 
 // Loop state of step 0 for every freshly seeded realization (its list: the tiles of
@@ -1158,6 +1256,11 @@ __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
   __syncthreads();
   for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) {
     Real& R = A.reals[r];
+    if (field_active(R)) {  // full-field form: no tile list
+      R.ctl.pad0 = 0;
+      atomicAdd(&A.bctl->running, 1u);
+      continue;
+    }
     if (!sweep_active(R)) continue;
     atomicAdd(&A.bctl->running, 1u);
     uint32_t o = O.rseg[r];
@@ -1208,9 +1311,11 @@ __device__ void sweep_end(const BatchArgs& A, uint32_t r, uint32_t kept, uint32_
     }
     atomicAdd(&A.bctl->running, 1u);
   } else {
-    // a final pass, or a running pass that found F_t empty: the loop has stopped
+    // a final pass, or a running pass that found F_t empty: the loop has stopped, and
+    // the grid is written from the solid plane
     c.status = c.cnt >= c.s_star ? kStatusDone : (kept == 0 ? kStatusExhausted : kStatusMaxSteps);
     c.mode = kModeIdle;
+    c.export_state = 1u;
   }
 }
 
@@ -1229,34 +1334,59 @@ constexpr uint32_t kDzNeg = dir_mask_where(2, 0), kDzPos = dir_mask_where(2, 2);
 // The draw rule of grow_draws for the tile sweep, for one block `blk` of a voxel whose
 // void mask has had the ranks of its earlier blocks removed (m: ranks 8 blk onward):
 // a rank goes further only when its high half is at or below its threshold's; a
-// passing rank's claim atomic is issued at once and its old word checked after the
-// block (ranks that did not claim keep an all-ones word, which never counts); the
-// directions of passing ranks are returned in *passed (for the tiles they reach).
-// Returns the number of voxels this thread claimed first.
+// passing rank claims its target with a 32-bit atomicOr of the target's bit in the
+// step's mark plane `mark32` (issued at once; the old words are checked after the block,
+// and a rank that did not claim keeps an all-ones word, which never counts).  The
+// source is voxel a, x coordinate xa, whose row starts at 32-bit word `rb` of a plane;
+// drow[d] is the row offset of direction d in 32-bit words.  The directions of passing
+// ranks are returned in *passed (for the tiles they reach).  Returns the number of
+// voxels this thread claimed first.
 // `lds_key` holds the key again for the rare tie path: read through a volatile LDS load,
 // the low-half block cannot be hoisted out of that path and computed for every block.
-__device__ __forceinline__ uint32_t sweep_block(uint8_t* __restrict__ grid, uint32_t k0,
+// Interacting phases (kInteract, itab != null): dhi[d] is the largest high half any
+// target of direction d can have (unassigned, or a cell of a phase the growing one may
+// convert); a rank at or below it reads its target's grid byte b -- 0 for an unassigned
+// cell, 3 + m for a cell of phase m, as at the phase's start -- and is decided against
+// that target's own threshold (Eq. (1) for b = 0, the interaction table otherwise).
+template <bool kInteract>
+__device__ __forceinline__ uint32_t sweep_block(uint32_t* __restrict__ mark32, uint32_t k0,
                                                 uint32_t k1, const uint32_t* lds_key,
-                                                const int32_t* doff, const uint32_t* dhi,
-                                                uint32_t a, uint32_t t, uint32_t blk,
-                                                uint32_t m, DrawThresholds th, uint32_t mark,
-                                                uint32_t* passed) {
+                                                const int32_t* drow, const uint32_t* dhi,
+                                                uint32_t a, uint32_t rb, uint32_t xa, uint32_t t,
+                                                uint32_t blk, uint32_t m, DrawThresholds th,
+                                                uint32_t* passed, const Geometry& g,
+                                                const uint8_t* __restrict__ labels,
+                                                const InteractTable* __restrict__ itab) {
   const uint32_t lf = th.lo_face, le = th.lo_edge, lc = th.lo_corner;
   uint32_t grown = 0, dirs = 0;
   const U4 H = philox10(a, t, blk, kTagGrowHi, k0, k1);
-  uint32_t old[8], bytes = 0;  // bytes: 2 bits per rank, the claimed byte in its word
+  uint32_t old[8], bits[8];  // a rank's old word and its target's bit in it
   bool have_lo = false;
   U4 L{0, 0, 0, 0};
 #pragma unroll
   for (int sl = 0; sl < 8; ++sl) {
     old[sl] = 0xFFFFFFFFu;
+    bits[sl] = 0xFFFFFFFFu;  // (old & bits) == 0 only for a claim that set its bit first
     if (m) {
       const int d = __builtin_ctz(m);
       m &= m - 1u;
       const uint32_t w = sl < 2 ? H.x : (sl < 4 ? H.y : (sl < 6 ? H.z : H.w));
       const uint32_t h = (sl & 1) ? (w >> 16) : (w & 0xFFFFu);
-      const uint32_t hi = dhi[d];
+      uint32_t hi = dhi[d];
       if (h <= hi) {
+        const uint32_t cls = ((kCornerDirs >> d) & 1u) ? 2u : (((kEdgeDirs >> d) & 1u) ? 1u : 0u);
+        uint32_t lo = cls == 2u ? lc : (cls == 1u ? le : lf);
+        if (kInteract && itab) {  // the target's own threshold
+          const int32_t off = (dir_field(kDirDX, d) - 1) + (dir_field(kDirDY, d) - 1) * g.nx +
+                              (dir_field(kDirDZ, d) - 1) * (int32_t)g.nxy;
+          const uint32_t b = labels[(uint32_t)((int32_t)a + off)];
+          if (b != kVoid) {
+            hi = itab->thr[6u * b + cls];
+            lo = itab->thr[6u * b + 3u + cls];
+          } else {
+            hi = cls == 2u ? th.hi_corner : (cls == 1u ? th.hi_edge : th.hi_face);
+          }
+        }
         bool pass = h < hi;
         if (h == hi) {  // high halves tie (rare): decide on the low half
           if (!have_lo) {
@@ -1267,20 +1397,19 @@ __device__ __forceinline__ uint32_t sweep_block(uint8_t* __restrict__ grid, uint
           }
           const uint32_t wl = sl < 2 ? L.x : (sl < 4 ? L.y : (sl < 6 ? L.z : L.w));
           const uint32_t l = (sl & 1) ? (wl >> 16) : (wl & 0xFFFFu);
-          pass = l < (((kCornerDirs >> d) & 1u) ? lc : (((kEdgeDirs >> d) & 1u) ? le : lf));
+          pass = l < lo;
         }
         if (pass) {
-          const uint32_t q = (uint32_t)((int32_t)a + doff[d]);
-          bytes |= (q & 3u) << (2 * sl);
-          old[sl] = atomicOr((uint32_t*)(grid + (q & ~3u)), mark << ((q & 3u) * 8u));
+          const uint32_t xq = xa + (uint32_t)dir_field(kDirDX, d) - 1u;  // in the domain
+          bits[sl] = 1u << (xq & 31u);
+          old[sl] = atomicOr(mark32 + (uint32_t)((int32_t)rb + drow[d]) + (xq >> 5), bits[sl]);
           dirs |= 1u << d;
         }
       }
     }
   }
 #pragma unroll
-  for (int sl = 0; sl < 8; ++sl)
-    grown += ((old[sl] >> (((bytes >> (2 * sl)) & 3u) * 8u)) & 0xFFu) == kVoid;
+  for (int sl = 0; sl < 8; ++sl) grown += (old[sl] & bits[sl]) == 0u;
   *passed = dirs;
   return grown;
 }
@@ -1314,8 +1443,9 @@ constexpr uint32_t kCandCap = 256;
 // covers y = y0 - 1 + hy, z = z0 - 1 + hz; interior row i = jy + 4 jz is halo row
 // (jy + 1) + 6 (jz + 1).  Bit i of a row mask is voxel x0 + i.
 struct TileImage {
-  // Halo row h as a 66-bit window of "in-domain and void at the step's start" (byte 0
-  // or the mark) in three words: bit i of the window (word i / 32, bit i % 32) is voxel
+  // Halo row h as a 66-bit window of "in-domain candidate at the step's start" (in none
+  // of S, the previous step's marks and the walls, except convertible cells of other
+  // phases) in three words: bit i of the window (word i / 32, bit i % 32) is voxel
   // x0 - 1 + i, i < 66.
   uint32_t win[kHaloRows][3];
   union {
@@ -1356,9 +1486,6 @@ __device__ __forceinline__ uint32_t tile_void_mask(const TileImage& T, int xl, i
   return (acc & 0x1FFFu) | ((acc >> 1) & 0x3FFE000u);
 }
 
-// z planes of halo rows whose loads a wavefront has in flight at once while staging.
-constexpr int kStagePlanes = 3;
-
 // Sets the wave's issue priority (0..3; the builtin takes an immediate).
 __device__ __forceinline__ void set_wave_priority(uint32_t p) {
   switch (p) {
@@ -1369,23 +1496,16 @@ __device__ __forceinline__ void set_wave_priority(uint32_t p) {
   }
 }
 
-// Lane `lane` of v takes the wave-uniform value s; the other lanes keep theirs.
-__device__ __forceinline__ uint32_t write_lane(uint32_t v, uint32_t s, uint32_t lane) {
-  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(s), "i"(lane));
-  return v;
-}
-
-
-
 // Dynamic LDS of k_sweep: one TileImage per wavefront.
 size_t sweep_lds_bytes(uint32_t block) { return sizeof(TileImage) * (block / kWave); }
 
 // Each wavefront sweeps whole tiles on its own (no workgroup barrier per tile); the
-// workgroup resolves its share of list entries into LDS 64 at a time.  kWalls: the
-// grids may hold other phases' cells (multi-phase generation), so "solid" is tested
-// as such instead of as "not void".  kLiteral: a realization with the literal front
-// rule takes as sources, from its second step on, only the voxels grown in the
-// previous step (they still carry that step's mark when the tile is staged).
+// workgroup resolves its share of list entries into LDS 64 at a time.  The pass reads
+// and writes the occupancy planes only (kPlane*), never the byte grid.  kWalls: the
+// grids may hold other phases' cells (multi-phase generation, plane W), which are
+// neither void nor sources.  kLiteral: a realization with the literal front rule takes
+// as sources, from its second step on, only the voxels grown in the previous step
+// (its marks that its tile's fold has not yet moved into S).
 // At most 96 VGPRs: five waves per SIMD, the occupancy the per-wave LDS images
 // (< 8 KB each) allow at the default 256-thread workgroup.
 template <bool kWalls, bool kLiteral>
@@ -1393,7 +1513,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5)))
 void k_sweep(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char sweep_lds[];
   __shared__ uint32_t s_tiles[kWave];
-  __shared__ int32_t s_doff[26];
+  __shared__ int32_t s_drow[26];
   __shared__ uint32_t s_dhi[26];
   __shared__ uint32_t s_key[2];
   __shared__ uint32_t s_fill, s_commit, s_kept, s_grown, s_draws, s_blocks, s_next;
@@ -1428,10 +1548,14 @@ void k_sweep(BatchArgs A) {
     Ctl& c = R.ctl;
     const Geometry g = R.g;
     const Tiles tl = R.tl;
-    uint8_t* __restrict__ grid = R.grid;
     uint32_t* __restrict__ stamp = R.stamp;
-    if (threadIdx.x < 26u) s_doff[threadIdx.x] = dir_offset(g, (int)threadIdx.x);  // read after
-                                                                                 // the first barrier
+    const uint32_t ntx = tl.ntx;
+    if (threadIdx.x < 26u) {  // plane row offset of direction d in 32-bit words (read after
+                              // the first barrier)
+      const int d = (int)threadIdx.x;
+      s_drow[d] = ((dir_field(kDirDY, d) - 1) + (dir_field(kDirDZ, d) - 1) * g.ny) *
+                  (int32_t)(2u * ntx);
+    }
     const uint32_t k0 = uniform(R.k0), k1 = uniform(R.k1);
     if (threadIdx.x == 0) {  // read after the first barrier
       s_key[0] = k0;
@@ -1447,13 +1571,30 @@ void k_sweep(BatchArgs A) {
     const uint32_t part_cap = (uint32_t)(half * (k + 1) / Gr) - part_base;
     const uint32_t t = uniform((uint32_t)c.step);
     const bool run = uniform(c.mode) == kModeRun;
-    const uint32_t mark = kGrown + (t & 1u), pmark = mark ^ 1u;
+    // the planes: S, the previous step's marks M[(t - 1) & 1] (folded into S by the
+    // owner of their tile during this pass), this step's marks M[t & 1] and the walls
+    const uint32_t pw = uniform(R.pwords);
+    uint64_t* __restrict__ plS = (uint64_t*)uniform64((uint64_t)R.planes);
+    const uint64_t* __restrict__ plP = plS + (size_t)pw * (kPlaneM0 + ((t + 1u) & 1u));
+    uint32_t* __restrict__ mark32 = (uint32_t*)(plS + (size_t)pw * (kPlaneM0 + (t & 1u)));
+    const uint64_t* __restrict__ plW =
+        kWalls && uniform(R.walls) != 0 ? plS + (size_t)pw * kPlaneW : nullptr;
+    // interacting phases: the cells of other phases this one may convert, and the table
+    const InteractTable* __restrict__ itab =
+        kWalls ? (const InteractTable*)uniform64((uint64_t)R.itab) : nullptr;
+    const uint64_t* __restrict__ plX = itab ? plS + (size_t)pw * kPlaneX : nullptr;
+    const uint8_t* __restrict__ labels = R.grid;
     // all ones where the solid rows are the previous step's new voxels only
     const uint64_t lit = kLiteral && uniform(R.literal) != 0 && t > 0 ? ~0ull : 0ull;
     const DrawThresholds th =
         draw_thresholds(uniform64(c.T[0]), uniform64(c.T[1]), uniform64(c.T[2]));
     if (threadIdx.x < 26u) {  // read after the first barrier
-      const uint32_t hf = th.hi_face, he = th.hi_edge, hc = th.hi_corner;
+      uint32_t hf = th.hi_face, he = th.hi_edge, hc = th.hi_corner;
+      if (itab) {  // the largest high half a target of each class can have
+        hf = max(hf, R.ihi_max[0]);
+        he = max(he, R.ihi_max[1]);
+        hc = max(hc, R.ihi_max[2]);
+      }
       const uint32_t d = threadIdx.x;
       s_dhi[d] = ((kCornerDirs >> d) & 1u) ? hc : (((kEdgeDirs >> d) & 1u) ? he : hf);
     }
@@ -1542,98 +1683,72 @@ void k_sweep(BatchArgs A) {
         const int32_t y0 = (int32_t)(q1 - iz * tl.nty) * kTileY;
         const int32_t z0 = (int32_t)iz * kTileZ;
         wave_sync();  // the previous tile's image is no longer read
-        // 1. stage the rows of the tile and its halo, kStagePlanes z planes of row loads in
-        // flight at a time (off-domain rows read row 0, off-domain lanes are masked);
-        // fold the previous step's marks.  The halo columns x0 - 1 and x0 + 64 of all 36 rows are
-        // read by 36 lanes at once.
+        // 1. stage the tile and its one-voxel halo from the planes: lane h < 36 takes halo
+        // row h (y = y0 - 1 + h % 6, z = z0 - 1 + h / 6) and loads the row's words ix - 1,
+        // ix and ix + 1 of S, of the previous step's marks and of the walls; bit 63 of
+        // word ix - 1 is voxel x0 - 1 and bit 0 of word ix + 1 voxel x0 + 64.  A row outside
+        // the domain loads a clamped row and is masked.
+        const uint32_t ix = (uint32_t)x0 / (uint32_t)kTileX;
+        const bool has_l = ix > 0, has_r = ix + 1u < ntx;  // (uniform)
+        // voxels of word ix inside the domain in x (uniform)
+        const uint64_t xin = (uint32_t)g.nx - (uint32_t)x0 >= (uint32_t)kTileX
+                                 ? ~0ull
+                                 : (1ull << ((uint32_t)g.nx - (uint32_t)x0)) - 1ull;
+        const int32_t hy_ = (int32_t)(lane % (kTileY + 2)), hz_ = (int32_t)(lane / (kTileY + 2));
+        const int32_t yh = y0 - 1 + hy_, zh = z0 - 1 + hz_;
+        const bool rin = lane < (uint32_t)kHaloRows && yh >= 0 && yh < g.ny && zh >= 0 &&
+                         zh < g.nz;
+        const uint32_t wb = ((uint32_t)min(max(yh, 0), g.ny - 1) +
+                             (uint32_t)g.ny * (uint32_t)min(max(zh, 0), g.nz - 1)) * ntx + ix;
+        const uint32_t wl = has_l ? wb - 1u : wb, wr = has_r ? wb + 1u : wb;
         // (global loads: a flat load would also hold up every wait on LDS)
-        const __attribute__((address_space(1))) uint8_t* ggrid =
-            (const __attribute__((address_space(1))) uint8_t*)grid;
-        // Lane h < 36 finds whether halo row h lies in the domain (bit h of rows_in) and
-        // reads the row's voxels x0 - 1 and x0 + 64 (their ballots come after the rows).
-        // Every address is clamped into the grid; what lies outside it is masked.
-        auto yrow = [&](int32_t y) { return (uint32_t)min(max(y, 0), g.ny - 1) * (uint32_t)g.nx; };
-        auto zrow = [&](int32_t z) { return (uint32_t)min(max(z, 0), g.nz - 1) * g.nxy; };
-        bool inl, inr;
-        uint32_t bl, br;
-        uint64_t rows_in;
+        typedef const __attribute__((address_space(1))) uint64_t gq;
+        const uint64_t sC = ((gq*)plS)[wb], pC = ((gq*)plP)[wb];
+        const uint64_t sL = ((gq*)plS)[wl], pL = ((gq*)plP)[wl];
+        const uint64_t sR = ((gq*)plS)[wr], pR = ((gq*)plP)[wr];
+        uint64_t oC = sC | pC, oL = sL | pL, oR = sR | pR;  // occupied at the step's start
+        if (kWalls && plW) {  // other phases' cells are not candidates, unless convertible
+          uint64_t wC = ((gq*)plW)[wb], wL = ((gq*)plW)[wl], wR = ((gq*)plW)[wr];
+          if (plX) {
+            wC &= ~((gq*)plX)[wb];
+            wL &= ~((gq*)plX)[wl];
+            wR &= ~((gq*)plX)[wr];
+          }
+          oC |= wC;
+          oL |= wL;
+          oR |= wR;
+        }
+        append();  // the previous tile's stamps, while the loads are out
         {
-          const int h = (int)lane;
-          const int32_t y = y0 - 1 + h % (kTileY + 2), z = z0 - 1 + h / (kTileY + 2);
-          const bool rin = h < kHaloRows && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
-          rows_in = __ballot(rin);
-          const uint32_t row = yrow(y) + zrow(z);
-          inl = rin && x0 > 0;
-          inr = rin && x0 + kTileX < g.nx;
-          bl = ggrid[row + (uint32_t)max(x0 - 1, 0)];
-          br = ggrid[row + (uint32_t)min(x0 + kTileX, g.nx - 1)];
+          const uint64_t vm = rin ? ~oC & xin : 0ull;
+          const uint32_t vl = rin && has_l ? (uint32_t)(~oL >> 63) : 0u;
+          const uint32_t vr = rin && has_r ? (uint32_t)(~oR & 1ull) : 0u;
+          if (lane < (uint32_t)kHaloRows) {
+            T.win[lane][0] = (uint32_t)vm << 1 | vl;
+            T.win[lane][1] = (uint32_t)(vm >> 31);
+            T.win[lane][2] = (uint32_t)(vm >> 63) | vr << 1;
+          }
         }
-        // Each row's mask is two compares ballotted into scalar registers, parked in
-        // lane h of rv (an interior row's solid mask in lane i of rs); lanes < 36 write
-        // the image once at the end.
-        const bool lane_in = x0 + (int32_t)lane < g.nx;
-        const uint64_t xin = __ballot(lane_in);  // lanes inside in x
-        const uint32_t vx = (uint32_t)x0 + lane;
-        // lanes past the row's end read its last byte (masked), so every read is in the grid
-        const uint32_t vxc = min(vx, (uint32_t)g.nx - 1u);
-        uint32_t rv_lo = 0, rv_hi = 0, rs_lo = 0, rs_hi = 0;
-#pragma unroll
-        for (int hz0 = 0; hz0 < kTileZ + 2; hz0 += kStagePlanes) {
-          uint32_t bv[kStagePlanes][kTileY + 2];
-#pragma unroll
-          for (int dz = 0; dz < kStagePlanes; ++dz)
-#pragma unroll
-            for (int hy = 0; hy < kTileY + 2; ++hy)
-              bv[dz][hy] = ggrid[yrow(y0 - 1 + hy) + zrow(z0 - 1 + hz0 + dz) + vxc];
-          if (hz0 == 0) append();  // the previous tile's stamps
-#pragma unroll
-          for (int dz = 0; dz < kStagePlanes; ++dz)
-#pragma unroll
-            for (int hy = 0; hy < kTileY + 2; ++hy) {
-              const int hz = hz0 + dz;
-              const uint32_t h = (uint32_t)(hy + (kTileY + 2) * hz);
-              const uint32_t b = bv[dz][hy];
-              // (the domain mask of a halo row is applied by its lane when the windows
-              // are written)
-              const uint64_t V = __ballot(b == kVoid) | __ballot(b == mark);
-              rv_lo = write_lane(rv_lo, (uint32_t)V, h);
-              rv_hi = write_lane(rv_hi, (uint32_t)(V >> 32), h);
-              if (hy >= 1 && hy <= kTileY && hz >= 1 && hz <= kTileZ) {
-                // (an interior row's solid mask is also masked by its lane at the end: the
-                // row lies in the domain unless it is past the grid's end in y or z)
-                const uint32_t i = (uint32_t)((hy - 1) + kTileY * (hz - 1));
-                const uint64_t Pb = __ballot(b == pmark);
-                // solid: 1 or grown in the previous step (with other phases' cells in
-                // the grid, "not void" is not enough)
-                uint64_t Sm = kWalls ? __ballot(b == kSolid) | Pb : ~V;
-                if (kLiteral) Sm = (Pb & lit) | (Sm & ~lit);
-                rs_lo = write_lane(rs_lo, (uint32_t)Sm, i);
-                rs_hi = write_lane(rs_hi, (uint32_t)(Sm >> 32), i);
-                // grown in the previous step: fold to 1
-                if (((rows_in >> h) & 1ull) && lane_in && b == pmark) {
-                  const uint32_t q = yrow(y0 - 1 + hy) + zrow(z0 - 1 + hz) + vx;
-                  __hip_atomic_fetch_xor(
-                      (__attribute__((address_space(1))) uint32_t*)(grid + (q & ~3u)),
-                      (pmark ^ kSolid) << ((q & 3u) * 8u), __ATOMIC_RELAXED,
-                      __HIP_MEMORY_SCOPE_AGENT);
-                }
-              }
-            }
-        }
-        // bit h: voxel x0 - 1 / x0 + 64 of halo row h void (uniform)
-        const uint64_t lm = __ballot(inl && (bl == kVoid || bl == mark));
-        const uint64_t rm = __ballot(inr && (br == kVoid || br == mark));
-        if (lane < (uint32_t)kHaloRows) {
-          const bool rin = ((rows_in >> lane) & 1ull) != 0;
-          const uint32_t vlo = rin ? rv_lo & (uint32_t)xin : 0u;
-          const uint32_t vhi = rin ? rv_hi & (uint32_t)(xin >> 32) : 0u;
-          T.win[lane][0] = vlo << 1 | (uint32_t)((lm >> lane) & 1ull);
-          T.win[lane][1] = __builtin_amdgcn_alignbit(vhi, vlo, 31u);
-          T.win[lane][2] = vhi >> 31 | (uint32_t)((rm >> lane) & 1ull) << 1;
-        }
-        if (lane < (uint32_t)kTileRows) {
+        // interior row i < 16 is halo row (i % 4 + 1) + 6 (i / 4 + 1): its words come from
+        // that lane.  Solid = S | previous marks (literal rule: the previous marks not yet
+        // in S); the tile's owner folds the previous marks of its rows into S (a plain
+        // store: S only gains bits the readers already count as solid through the marks).
+        {
           const uint32_t hi = (lane % kTileY + 1u) + (kTileY + 2u) * (lane / kTileY + 1u);
-          T.S[lane] = ((rows_in >> hi) & 1ull) ? ((uint64_t)rs_hi << 32 | rs_lo) & xin : 0ull;
+          const uint32_t src = lane < (uint32_t)kTileRows ? hi : lane;
+          const uint64_t s_i = (uint64_t)(uint32_t)__shfl((int)(uint32_t)(sC >> 32), (int)src, kWave) << 32 |
+                               (uint32_t)__shfl((int)(uint32_t)sC, (int)src, kWave);
+          const uint64_t p_i = (uint64_t)(uint32_t)__shfl((int)(uint32_t)(pC >> 32), (int)src, kWave) << 32 |
+                               (uint32_t)__shfl((int)(uint32_t)pC, (int)src, kWave);
+          const bool in_i = __shfl((int)rin, (int)src, kWave) != 0;
+          const uint32_t wb_i = (uint32_t)__shfl((int)wb, (int)src, kWave);
+          if (lane < (uint32_t)kTileRows) {
+            const uint64_t fresh = p_i & ~s_i;  // grown in the previous step
+            uint64_t sm = (s_i | p_i) & xin;
+            if (kLiteral) sm = (fresh & lit) | (sm & ~lit);
+            T.S[lane] = in_i ? sm : 0ull;
+            if (in_i && fresh != 0ull) plS[wb_i] = s_i | p_i;
+          }
         }
         wave_sync();
         // 2. front rows (solid with a void neighbour) and their prefix
@@ -1664,7 +1779,7 @@ void k_sweep(BatchArgs A) {
         const uint32_t nq = uniform(nq_l);
         kept_w += nq;
         if (!run || nq == 0) continue;
-        const bool full = R.full != 0;
+        const bool full = R.form == kFormAllTiles;
         for (uint32_t c = piece; c; c &= c - 1u)
           T.qo[pos++] = (uint16_t)((lane >> 2) << 6 | (lane & 3u) * 16u | (uint32_t)__builtin_ctz(c));
         wave_sync();
@@ -1704,7 +1819,8 @@ void k_sweep(BatchArgs A) {
         // pass otherwise); kept blocks go to the LDS list.  B: each listed block is drawn
         // again and its ranks are decided exactly and claimed, 64 blocks per round.
         uint32_t tm = 0, grown = 0, ncand = 0;
-        const uint32_t hmax = max(th.hi_face, max(th.hi_edge, th.hi_corner));
+        uint32_t hmax = max(th.hi_face, max(th.hi_edge, th.hi_corner));
+        if (itab) hmax = max(hmax, max(R.ihi_max[0], max(R.ihi_max[1], R.ihi_max[2])));
         auto drain = [&]() {
           wave_sync();
           for (uint32_t c0 = 0; c0 < ncand; c0 += kWave) {
@@ -1718,8 +1834,11 @@ void k_sweep(BatchArgs A) {
               const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
                                  (uint32_t)(z0 + jz) * g.nxy;
               uint32_t passed = 0;
-              grown += sweep_block(grid, k0, k1, s_key, s_doff, s_dhi, a, t, blk, m, th, mark,
-                                   &passed);
+              const uint32_t rb = ((uint32_t)(y0 + jy) + (uint32_t)g.ny * (uint32_t)(z0 + jz)) *
+                                  (2u * ntx);
+              grown += sweep_block<kWalls>(mark32, k0, k1, s_key, s_drow, s_dhi, a, rb,
+                                           (uint32_t)(x0 + xl), t, blk, m, th, &passed, g,
+                                           labels, itab);
               // passing ranks whose target leaves this tile list the target's tile (this
               // tile is listed anyway); first claim or not, the target was void
               const uint32_t leave = (xl == 0 ? kDxNeg : 0u) | (xl == kTileX - 1 ? kDxPos : 0u) |
@@ -1773,7 +1892,7 @@ void k_sweep(BatchArgs A) {
         }
         if (ncand) drain();
         grown_w += wave_sum(grown);
-        if (full) continue;  // the full-field form lists every tile anyway
+        if (full) continue;  // the all-tiles form lists every tile anyway
         // 6. list the tiles that may hold F_{t+1} for the next pass, each once: this
         // tile (it has front voxels) and every tile that received a claim
         const uint32_t tmask = wave_or(tm) | 1u << 13;
@@ -1799,7 +1918,8 @@ void k_sweep(BatchArgs A) {
     // the full-field form keeps every tile listed: each part of the identity list is full
     const uint32_t tn = A.reals[r].tl.n, Gr = P.wgoff[r + 1] - P.wgoff[r];
     const uint32_t fill =
-        A.reals[r].full ? (uint32_t)((uint64_t)tn * (k + 1) / Gr) - part_base : s_commit;
+        A.reals[r].form == kFormAllTiles ? (uint32_t)((uint64_t)tn * (k + 1) / Gr) - part_base
+                                         : s_commit;
     Q.seg[P.wgoff[r] + r + k] = SegEntry{r, part_base, fill, 0u};
     A.wgkept[beta] = s_kept;
     A.wggrown[beta] = s_grown;
@@ -1899,6 +2019,179 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
   __syncthreads();
   plan_assign(A, p ^ 1u);
   if (threadIdx.x == 0) A.bctl->plan = p ^ 1u;
+}
+
+// ---------------------------------------------------------------------------
+// Full-field growth step (Sec. 2.2, Algorithm 2): the baseline the list-indexed sweep is
+// measured against.  Every step visits every cell of the grid: each cell draws for all
+// its directions (rand over the whole field, Algorithm 2 line 4; here the four high-half
+// Philox blocks of the cell, 32 draws covering its at most 26 ranks), the draws of solid
+// cells that fall below their direction's threshold claim the neighbour (the solid mask
+// and the shift, lines 5-6), and a second pass over the whole field folds the claims into
+// the solid phase (line 8).  The draws are the ones of the draw rule (rank j of the
+// cell's void neighbours), so the grids equal the list-indexed ones step for step; only
+// the work differs.  Items: plane words (kItemsField); a wavefront takes a chunk of 64
+// words one at a time, lane b handling voxel x = 64 ix + b of the word's row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kMaxBlock) void k_field_step(BatchArgs A) {
+  const uint32_t lane = lane_id();
+  uint32_t cr = 0xFFFFFFFFu;  // (wave-uniform) realization of the counts below
+  uint32_t front_l = 0, grown_l = 0, draws_l = 0;
+  auto flush = [&]() {
+    const uint32_t f = wave_sum(front_l), gsum = wave_sum(grown_l), d = wave_sum(draws_l);
+    if (lane == 0 && cr != 0xFFFFFFFFu) {
+      Ctl& c = A.reals[cr].ctl;
+      if (f) atomicAdd(&c.ff_front, f);
+      if (gsum) atomicAdd(&c.ff_grown, gsum);
+      if (d) atomicAdd((unsigned long long*)&c.ff_draws, (unsigned long long)d);
+    }
+    front_l = grown_l = draws_l = 0;
+  };
+  for_each_chunk(A, kItemsField, [&](uint32_t r, uint32_t i) {
+    if (r != cr) {
+      flush();
+      cr = r;
+    }
+    const Real& R = A.reals[r];
+    const uint32_t pw = uniform(R.pwords);
+    const uint32_t w0 = i - lane;
+    if (w0 >= pw) return;  // (uniform)
+    const uint32_t nw = min((uint32_t)kWave, pw - w0);
+    const Geometry g = R.g;
+    const uint32_t ntx = uniform(R.tl.ntx);
+    const FastDiv dntx = R.tl.div_ntx;
+    const uint32_t t = uniform((uint32_t)R.ctl.step);
+    const bool run = uniform(R.ctl.mode) == kModeRun;
+    const uint32_t k0 = uniform(R.k0), k1 = uniform(R.k1);
+    const DrawThresholds th = draw_thresholds(uniform64(R.ctl.T[0]), uniform64(R.ctl.T[1]),
+                                              uniform64(R.ctl.T[2]));
+    const uint64_t* __restrict__ S = (const uint64_t*)uniform64((uint64_t)R.planes);
+    const uint64_t* __restrict__ W =
+        uniform(R.walls) != 0 ? S + (size_t)pw * kPlaneW : nullptr;
+    uint32_t* __restrict__ mark32 = (uint32_t*)(S + (size_t)pw * kPlaneM0);
+    // occupied (solid or another phase's cell) word of the plane(s)
+    auto occ = [&](uint32_t w) -> uint64_t { return W ? (S[w] | W[w]) : S[w]; };
+    for (uint32_t j = 0; j < nw; ++j) {
+      const uint32_t w = w0 + j;
+      const uint32_t row = dntx.div(w);  // y + ny z
+      const uint32_t ix = w - row * ntx;
+      const uint32_t z = g.div_ny.div(row), y = row - z * (uint32_t)g.ny;
+      const uint32_t x = ix * (uint32_t)kTileX + lane;
+      const bool inx = x < (uint32_t)g.nx;
+      // in-domain neighbours in x of this lane's voxel: bit 0 = x - 1, bit 1 = x, bit 2 = x + 1
+      const uint32_t in3 = (x > 0 ? 1u : 0u) | 2u | (x + 1u < (uint32_t)g.nx ? 4u : 0u);
+      uint32_t acc = 0;  // void neighbours, 3 bits per row (dy, dz), row order
+      bool solid = false;
+#pragma unroll
+      for (int kz = 0; kz < 3; ++kz)
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+          const int32_t yy = (int32_t)y + ky - 1, zz = (int32_t)z + kz - 1;
+          if (yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz) continue;  // (uniform)
+          const uint32_t rw = ((uint32_t)yy + (uint32_t)g.ny * (uint32_t)zz) * ntx + ix;
+          const uint64_t wm = occ(rw);
+          const uint64_t wl = ix > 0 ? occ(rw - 1u) : 0ull;
+          const uint64_t wr = ix + 1u < ntx ? occ(rw + 1u) : 0ull;
+          // 66-bit window: bit 0 = voxel 64 ix - 1, bit k + 1 = voxel 64 ix + k
+          const uint64_t lo = wm << 1 | wl >> 63, hi2 = wm >> 63 | (wr & 1ull) << 1;
+          uint32_t b3 = (uint32_t)(lo >> lane) & 7u;
+          if (lane >= 62u) b3 = (b3 | (uint32_t)(hi2 << (64u - lane))) & 7u;
+          acc |= (~b3 & in3 & 7u) << (3 * (ky + 3 * kz));
+          if (ky == 1 && kz == 1) solid = ((S[rw] >> lane) & 1ull) != 0;
+        }
+      const uint32_t vm = inx ? ((acc & 0x1FFFu) | ((acc >> 1) & 0x3FFE000u)) : 0u;
+      solid = solid && inx;
+      if (solid && vm) {
+        ++front_l;
+        draws_l += (uint32_t)__builtin_popcount(vm);
+      }
+      if (!run || !inx) continue;
+      // every cell draws its 32 ranks; the solid mask applies to the result
+      const uint32_t a = x + (uint32_t)g.nx * row;
+      uint32_t m = vm, pass = 0;
+#pragma unroll
+      for (uint32_t blk = 0; blk < 4; ++blk) {
+        const U4 H = philox10(a, t, blk, kTagGrowHi, k0, k1);
+        // (every cell's blocks are drawn, used or not: the full-field work of Algorithm 2)
+        asm volatile("" ::"v"(H.x), "v"(H.y), "v"(H.z), "v"(H.w));
+        bool have_lo = false;
+        U4 L{0, 0, 0, 0};
+#pragma unroll
+        for (int sl = 0; sl < 8; ++sl) {
+          if (!m) break;
+          const int d = __builtin_ctz(m);
+          m &= m - 1u;
+          const uint32_t wv = sl < 2 ? H.x : (sl < 4 ? H.y : (sl < 6 ? H.z : H.w));
+          const uint32_t h = (sl & 1) ? (wv >> 16) : (wv & 0xFFFFu);
+          const bool corner = ((kCornerDirs >> d) & 1u) != 0, edge = ((kEdgeDirs >> d) & 1u) != 0;
+          const uint32_t hi = corner ? th.hi_corner : (edge ? th.hi_edge : th.hi_face);
+          bool ok = h < hi;
+          if (h == hi) {  // high halves tie: the low half decides
+            if (!have_lo) {
+              L = philox10(a, t, blk, kTagGrowLo, k0, k1);
+              have_lo = true;
+            }
+            const uint32_t wl2 = sl < 2 ? L.x : (sl < 4 ? L.y : (sl < 6 ? L.z : L.w));
+            const uint32_t l = (sl & 1) ? (wl2 >> 16) : (wl2 & 0xFFFFu);
+            ok = l < (corner ? th.lo_corner : (edge ? th.lo_edge : th.lo_face));
+          }
+          if (ok) pass |= 1u << d;
+        }
+      }
+      if (!solid) continue;
+      // claims: the target's bit in the mark plane; the first setter owns the voxel
+      while (pass) {
+        const int d = __builtin_ctz(pass);
+        pass &= pass - 1u;
+        const uint32_t xq = x + (uint32_t)dir_field(kDirDX, d) - 1u;
+        const uint32_t yq = y + (uint32_t)dir_field(kDirDY, d) - 1u;
+        const uint32_t zq = z + (uint32_t)dir_field(kDirDZ, d) - 1u;
+        const uint32_t q32 = ((yq + (uint32_t)g.ny * zq) * ntx) * 2u + (xq >> 5);
+        const uint32_t bit = 1u << (xq & 31u);
+        grown_l += (atomicOr(mark32 + q32, bit) & bit) == 0u;
+      }
+    }
+  });
+  flush();
+}
+
+// Full-field step, second pass (Algorithm 2 line 8): S |= claims, the mark plane cleared.
+__global__ __launch_bounds__(kMaxBlock) void k_field_fold(BatchArgs A) {
+  for_each_chunk(A, kItemsField, [&](uint32_t r, uint32_t i) {
+    const Real& R = A.reals[r];
+    const uint32_t pw = R.pwords;
+    if (i >= pw) return;
+    uint64_t* P = R.planes;
+    const uint64_t m = P[(size_t)kPlaneM0 * pw + i];
+    if (m) {
+      P[(size_t)kPlaneS * pw + i] |= m;
+      P[(size_t)kPlaneM0 * pw + i] = 0ull;
+    }
+  });
+}
+
+// End of a full-field step for every realization with a pending one (one workgroup):
+// the step's log, count, loop rule and next thresholds, as at the end of a tile pass.
+// reset_running: this pass runs no tile sweep, whose step end restarts the count of
+// running realizations.
+__global__ __launch_bounds__(1024) void k_field_end(BatchArgs A, uint32_t reset_running) {
+  if (reset_running) {
+    if (threadIdx.x == 0) A.bctl->running = 0;
+    __syncthreads();
+  }
+  for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) {
+    Real& R = A.reals[r];
+    if (!field_active(R)) continue;
+    Ctl& c = R.ctl;
+    const uint32_t front = c.ff_front, grown = c.ff_grown;
+    const uint64_t draws = c.ff_draws;
+    c.ff_front = 0;
+    c.ff_grown = 0;
+    c.ff_draws = 0;
+    // the step's high-half blocks: four for every cell of the field
+    const uint64_t blocks = c.mode == kModeRun ? 4ull * R.g.n : 0ull;
+    sweep_end(A, r, front, 0u, grown, draws, blocks);
+  }
 }
 
 // Relabelling of a whole grid (multi-phase generation, Sec. 2.1 steps 4-5): every byte b

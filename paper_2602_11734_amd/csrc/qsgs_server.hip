@@ -85,7 +85,7 @@ struct qsgs_server {
   std::vector<Real> recs;         // the records as the last tick left them
   char* stage = nullptr;          // the engine's pinned staging (owned by the server)
 
-  static size_t front_bytes(const Geometry& g) { return sweep_state_bytes(g); }
+  static size_t front_bytes(const Geometry& g) { return sweep_state_bytes(g, false); }
   static size_t footprint(const Geometry& g) { return align_up(grid_bytes(g)) + front_bytes(g); }
 };
 
@@ -211,12 +211,12 @@ qsgs_status qsgs_server_tick(qsgs_server* S, int32_t* n_resident, int32_t* n_que
         qsgs_server::Request& q = S->resident.at(S->slot_req[group[k]]);
         E.init_sweep_record(group[k], q.spec, &q.params,
                             reinterpret_cast<uint8_t*>(S->arena + q.grid_off),
-                            S->arena + q.front_off);
+                            S->arena + q.front_off, false);
       }
       E.attach_scratch(group, S->arena + scratch_off, L);
       for (size_t slot : group) QSGS_TRY(E.upload(slot, 1));
       QSGS_TRY(E.seed_core(S->arena + scratch_off, L));
-      QSGS_TRY(E.sweep_start());
+      QSGS_TRY(E.sweep_start(group));
       break;
     }
     const size_t slot = group.back();
@@ -253,7 +253,12 @@ qsgs_status qsgs_server_tick(qsgs_server* S, int32_t* n_resident, int32_t* n_que
       passes = std::min(passes, need);
     }
     passes = std::max<uint64_t>(passes, (uint64_t)S->steps_per_tick);
-    for (uint64_t k = 0; k < passes; ++k) QSGS_TRY(E.sweep_pass(nullptr));
+    std::vector<bool> live(S->slot_req.size());
+    for (size_t slot = 0; slot < live.size(); ++slot) live[slot] = S->slot_req[slot] >= 0;
+    bool tiles = false, field = false;
+    E.forms_in_use(&tiles, &field, &live);
+    for (uint64_t k = 0; k < passes; ++k) QSGS_TRY(E.sweep_pass(nullptr, tiles, field));
+    QSGS_TRY(E.export_grids());  // the requests that stopped: byte grids from their planes
   }
 
   // Retire finished requests: their fronts return to the arena, the grid waits.

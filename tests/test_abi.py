@@ -71,13 +71,50 @@ def test_invalid_params_rejected_before_launch(q, bad):
 
 
 def test_sweep_form_flag_checked(q):
-    p = q.make_params(0.7, 0.01, (0.1, 0.05, 0.01), 3, 1, full_field=True)
-    assert q.qsgs_workspace_bytes((8, 8, 8), p) > 0
-    p.full_field = 2
+    for form in (q.SWEEP_LIST, q.SWEEP_FIELD, q.SWEEP_ALL_TILES):
+        p = q.make_params(0.7, 0.01, (0.1, 0.05, 0.01), 3, 1, sweep_form=form)
+        assert q.qsgs_workspace_bytes((8, 8, 8), p) > 0
+    p.sweep_form = 3
     assert q.qsgs_workspace_bytes((8, 8, 8), p) == 0
-    p.full_field = 0
+    p.sweep_form = -1
+    assert q.qsgs_workspace_bytes((8, 8, 8), p) == 0
+    p.sweep_form = 0
     p.front_rule = 7
     assert q.qsgs_workspace_bytes((8, 8, 8), p) == 0
+    # the full-field form has no front: the literal front rule is refused with it
+    p = q.make_params(0.7, 0.01, (0.1, 0.05, 0.01), 3, 1, sweep_form=q.SWEEP_FIELD,
+                      literal_front=True)
+    assert q.qsgs_workspace_bytes((8, 8, 8), p) == 0
+    p.sweep_form = q.SWEEP_ALL_TILES
+    assert q.qsgs_workspace_bytes((8, 8, 8), p) > 0
+
+
+def test_interaction_arguments_checked_before_launch(q):
+    """Interaction probabilities outside [0, 1] and an interacting phase in the full-field
+    form are refused before anything runs (device pointers here are dummies)."""
+    import numpy as np
+    ph = [q.make_params(0.3, 0.01, (0.1, 0.05, 0.01), 2, 1),
+          q.make_params(0.2, 0.01, (0.1, 0.05, 0.01), 2, 2)]
+    dims = (16, 16, 16)
+    wb = q.qsgs_phases_workspace_bytes(dims, ph)
+    assert wb > q.qsgs_workspace_bytes(dims, ph[0])  # walls and interaction planes, table
+    I = np.zeros((2, 2, 3))
+    I[1, 0] = (0.5, 1.5, 0.0)
+    with pytest.raises(q.QsgsError) as e:
+        q.qsgs_generate_phases_interacting(dims, ph, I, 256, 256, wb, stream=0)
+    assert e.value.status == q.ERR_INVALID and "interaction" in str(e.value)
+    I[1, 0] = (0.5, 0.5, 0.0)
+    ph[1].sweep_form = q.SWEEP_FIELD
+    with pytest.raises(q.QsgsError) as e:
+        q.qsgs_generate_phases_interacting(dims, ph, I, 256, 256, wb, stream=0)
+    assert e.value.status == q.ERR_INVALID and "full-field" in str(e.value)
+    with pytest.raises(q.QsgsError):
+        q.qsgs_generate_phases_interacting(dims, ph, np.zeros((3, 3, 3)), 256, 256, wb, stream=0)
+
+
+def test_front_rule_flag_checked(q):
+    p = q.make_params(0.7, 0.01, (0.1, 0.05, 0.01), 3, 1)
+    p.front_rule = 7
     info = q.qsgs_info()
     st = q.load().qsgs_generate(ctypes.byref(q.make_dims((8, 8, 8))), ctypes.byref(p), 256,
                                 256, 1 << 20, ctypes.byref(info), None)
@@ -123,8 +160,10 @@ def test_phases_arguments_checked(q):
     p1 = q.make_params(0.3, 0.01, (0.1, 0.05, 0.01), 3, 1)
     p2 = q.make_params(0.2, 0.01, (0.1, 0.05, 0.01), 30, 2)
     w1, w2 = q.qsgs_workspace_bytes(dims, p1), q.qsgs_workspace_bytes(dims, p2)
-    assert q.qsgs_phases_workspace_bytes(dims, [p1, p2]) == max(w1, w2)
-    assert q.qsgs_phases_workspace_bytes(dims, [p1]) == w1
+    # one phase at a time, plus the walls and interaction planes and the interaction table
+    assert q.qsgs_phases_workspace_bytes(dims, [p1, p2]) > max(w1, w2)
+    assert q.qsgs_phases_workspace_bytes(dims, [p1, p2]) < max(w1, w2) + 64 * 1024
+    assert w1 < q.qsgs_phases_workspace_bytes(dims, [p1]) < w1 + 64 * 1024
     bad = q.make_params(1.5, 0.01, (0.1, 0.05, 0.01), 3, 1)
     assert q.qsgs_phases_workspace_bytes(dims, [p1, bad]) == 0
     lib = q.load()

@@ -75,14 +75,29 @@ def test_generate_matches_oracle(q, orc, case):
     assert np.array_equal(got, ref.grid)
 
 
-@pytest.mark.parametrize("case", SMALL[::3] + workloads.config1(),
-                         ids=[c.name for c in SMALL[::3] + workloads.config1()])
-def test_full_field_sweep_matches_oracle(q, orc, case):
-    """The full-field form (every tile swept every step, Alg. 2) reaches the same
-    result, logs and work counts as the list-indexed form and the oracle."""
+FORM_CASES = SMALL[::3] + workloads.config1()
+FORM_NAMES = {1: "full_field", 2: "all_tiles"}
+
+
+def expected_blocks(ref, case, form):
+    """High-half Philox blocks per step: the list forms draw one per eight ranks of each
+    front voxel (the oracle's count); the full-field form draws four for every cell of
+    the grid every step (Algorithm 2's work)."""
+    if form == 1:
+        n = case.dims[0] * case.dims[1] * case.dims[2]
+        return np.full(len(ref.log_blocks), 4 * n, dtype=np.int64)
+    return ref.log_blocks
+
+
+@pytest.mark.parametrize("form", [1, 2], ids=["full_field", "all_tiles"])
+@pytest.mark.parametrize("case", FORM_CASES, ids=[c.name for c in FORM_CASES])
+def test_sweep_forms_match_oracle(q, orc, case, form):
+    """The full-field form (every cell draws every step, Algorithm 2) and the all-tiles
+    sweep reach the same grid, logs and draw counts as the list-indexed form and the
+    oracle; the full-field form's Philox work is four blocks per cell per step."""
     import torch
-    say("GPU generate (full field)", case.name, case.dims, "key", case.key)
-    params = q.params_of(case, full_field=True)
+    say("GPU generate", FORM_NAMES[form], case.name, case.dims, "key", case.key)
+    params = q.params_of(case, sweep_form=form)
     grid, info, buf = q.generate(case.dims, params)
     torch.cuda.synchronize()
     lf, ln, lc = q.qsgs_read_step_log(buf.ws, buf.ws_bytes)
@@ -90,8 +105,11 @@ def test_full_field_sweep_matches_oracle(q, orc, case):
     ref = run_oracle(orc, case)
     assert info["status"] == ref.status and info["step"] == ref.steps
     assert info["solid_count"] == ref.solid_count and info["front_size"] == ref.front_size
+    assert info["n_seeds"] == ref.n_seeds
     assert np.array_equal(lf, ref.log_front) and np.array_equal(ln, ref.log_new)
-    assert np.array_equal(ld, ref.log_draws) and np.array_equal(lb, ref.log_blocks)
+    assert np.array_equal(lc, ref.log_count)
+    assert np.array_equal(ld, ref.log_draws)
+    assert np.array_equal(lb, expected_blocks(ref, case, form))
     assert np.array_equal(grid.cpu().numpy(), ref.grid)
 
 
@@ -256,8 +274,10 @@ def test_batch_matches_oracle(q, orc):
     equals the oracle's run of that realization alone."""
     import torch
     cases = workloads.small_cases() + workloads.config1()
-    # every third realization runs the full-field form: both forms share the launches
-    params = [q.params_of(c, full_field=(k % 3 == 1)) for k, c in enumerate(cases)]
+    # the three growth forms in turn: the tile forms share the sweep launches, the
+    # full-field realizations share the full-field launches of the same passes
+    forms = [k % 3 for k in range(len(cases))]
+    params = [q.params_of(c, sweep_form=f) for c, f in zip(cases, forms)]
     dims = [c.dims for c in cases]
     grids = [torch.empty(q.qsgs_grid_bytes(d), dtype=torch.uint8, device="cuda") for d in dims]
     wsb = q.qsgs_batch_workspace_bytes(dims, params)
@@ -279,7 +299,7 @@ def test_batch_matches_oracle(q, orc):
         assert np.array_equal(lc, ref.log_count[: len(lc)])
         ld, lb = q.qsgs_read_step_work(ws, wsb, index=k)
         assert np.array_equal(ld, ref.log_draws[: len(ld)])
-        assert np.array_equal(lb, ref.log_blocks[: len(lb)])
+        assert np.array_equal(lb, expected_blocks(ref, c, forms[k])[: len(lb)])
 
 
 def test_large_batch_matches_oracle(q, orc):
@@ -448,16 +468,19 @@ def _phase_tuples(ps):
 PHASES = workloads.phase_sets()
 
 
-@pytest.mark.parametrize("full", [False, True], ids=["list", "full_field"])
-@pytest.mark.parametrize("ps", PHASES, ids=[p.name for p in PHASES])
-def test_phases_match_oracle(q, orc, ps, full):
+# every set with the list-indexed sweep; two sets with the full-field and all-tiles forms
+PHASE_RUNS = [(ps, 0) for ps in PHASES] + [(ps, f) for f in (1, 2) for ps in PHASES[:2]]
+
+
+@pytest.mark.parametrize("ps,form", PHASE_RUNS,
+                         ids=[f"{p.name}-{['list', 'full_field', 'all_tiles'][f]}"
+                              for p, f in PHASE_RUNS])
+def test_phases_match_oracle(q, orc, ps, form):
     """Independent phases in sequence: labels and per-phase results equal the
-    oracle's, with list-indexed and with full-field sweeps."""
+    oracle's, with each growth form."""
     import torch
-    if full and ps.name not in ("mp3_40x36x30", "mp2_97x70x45"):
-        pytest.skip("full-field form checked on two sets")
-    say("GPU generate_phases", ps.name, ps.dims, "full" if full else "list")
-    params = [q.params_of(c, full_field=full) for c in ps.phases]
+    say("GPU generate_phases", ps.name, ps.dims, "form", form)
+    params = [q.params_of(c, sweep_form=form) for c in ps.phases]
     labels, infos = q.generate_phases(ps.dims, params)
     torch.cuda.synchronize()
     ref, res = orc.generate_phases(ps.dims, _phase_tuples(ps))
@@ -538,14 +561,18 @@ def test_phases_at_400_cube_properties(q):
 LIT = workloads.small_cases()[::2] + workloads.config1()
 
 
-@pytest.mark.parametrize("full", [False, True], ids=["list", "full_field"])
-@pytest.mark.parametrize("case", LIT, ids=[c.name for c in LIT])
-def test_literal_front_matches_oracle(q, orc, case, full):
+# every case with the list-indexed sweep, one with the all-tiles sweep (the full-field
+# form has no front and refuses the literal rule)
+LIT_RUNS = [(c, 0) for c in LIT] + [(LIT[0], 2)]
+
+
+@pytest.mark.parametrize("case,form", LIT_RUNS,
+                         ids=[f"{c.name}-{['list', 'full_field', 'all_tiles'][f]}"
+                              for c, f in LIT_RUNS])
+def test_literal_front_matches_oracle(q, orc, case, form):
     import torch
-    if full and case.name != LIT[0].name:
-        pytest.skip("full-field form with the literal rule checked on one case")
-    say("GPU generate (literal front)", case.name, case.dims, "full" if full else "list")
-    params = q.params_of(case, full_field=full, literal_front=True)
+    say("GPU generate (literal front)", case.name, case.dims, "form", form)
+    params = q.params_of(case, sweep_form=form, literal_front=True)
     grid, info, buf = q.generate(case.dims, params)
     torch.cuda.synchronize()
     lf, ln, lc = q.qsgs_read_step_log(buf.ws, buf.ws_bytes)
@@ -598,3 +625,61 @@ def test_phases_at_the_label_limit(q, orc):
     for info, r in zip(infos, res):
         assert (info["solid_count"], info["step"], info["status"], info["n_seeds"]) == \
                (r.count, r.steps, r.status, r.n_seeds)
+
+
+# ----- interacting phases (Sec. 2.1 step 4) -----
+
+def _interaction(k, pairs):
+    I = np.zeros((k, k, 3))
+    for (n, m), v in pairs.items():
+        I[n - 1, m - 1] = v
+    return I
+
+
+INTERACT_RUNS = [
+    # (name, phase set, interaction {(n, m): (face, edge, corner)}, growth form)
+    ("mp3_zero", PHASES[0], {}, 0),
+    ("mp3_mixed", PHASES[0], {(2, 1): (0.3, 0.1, 0.05), (3, 1): (0.2, 0.0, 0.0),
+                              (3, 2): (0.1, 0.1, 0.1)}, 0),
+    ("mp3_mixed_all_tiles", PHASES[0], {(2, 1): (0.3, 0.1, 0.05), (3, 1): (0.2, 0.0, 0.0),
+                                        (3, 2): (0.1, 0.1, 0.1)}, 2),
+    ("mp2_ragged_strong", PHASES[1], {(2, 1): (0.6, 0.4, 0.2)}, 0),
+    ("mp2_blocked_certain", PHASES[2], {(2, 1): (1.0, 1.0, 1.0)}, 0),
+    ("mp2_cap_face_only", PHASES[4], {(2, 1): (1.0, 0.0, 0.0)}, 0),
+]
+
+
+@pytest.mark.parametrize("name,ps,pairs,form", INTERACT_RUNS, ids=[r[0] for r in INTERACT_RUNS])
+def test_interacting_phases_match_oracle(q, orc, name, ps, pairs, form):
+    """Phases that convert cells of earlier phases: labels and per-phase results equal
+    the oracle's interacting generation."""
+    import torch
+    k = len(ps.phases)
+    I = _interaction(k, pairs)
+    say("GPU generate_phases_interacting", name, ps.dims, "form", form)
+    params = [q.params_of(c, sweep_form=form) for c in ps.phases]
+    labels, infos = q.generate_phases(ps.dims, params, interact=I)
+    torch.cuda.synchronize()
+    ref, res = orc.generate_phases(ps.dims, _phase_tuples(ps), I)
+    for info, r in zip(infos, res):
+        assert (info["n_candidates"], info["n_seeds"], info["solid_count"], info["target_count"],
+                info["front_size"], info["step"], info["status"]) == \
+               (r.n_candidates, r.n_seeds, r.count, r.target_count, r.front_size, r.steps,
+                r.status), name
+    assert np.array_equal(labels.cpu().numpy(), ref), name
+
+
+def test_interacting_phase_with_literal_front_matches_oracle(q, orc):
+    import torch
+    ps = PHASES[0]
+    I = _interaction(3, {(2, 1): (0.4, 0.2, 0.1), (3, 2): (0.3, 0.3, 0.3)})
+    tuples = [t + (k == 2,) for k, t in enumerate(_phase_tuples(ps))]
+    params = [q.params_of(c, literal_front=(k == 2)) for k, c in enumerate(ps.phases)]
+    say("GPU generate_phases_interacting (phase 3 literal front)", ps.name)
+    labels, infos = q.generate_phases(ps.dims, params, interact=I)
+    torch.cuda.synchronize()
+    ref, res = orc.generate_phases(ps.dims, tuples, I)
+    for info, r in zip(infos, res):
+        assert (info["solid_count"], info["step"], info["status"], info["front_size"]) == \
+               (r.count, r.steps, r.status, r.front_size)
+    assert np.array_equal(labels.cpu().numpy(), ref)
