@@ -84,7 +84,7 @@ def lib():
         _lib.orc_step_fullfield.argtypes = [i32, i32, i32, vp, u32, vp, u64]
         _lib.orc_step_fullfield.restype = i64
         _lib.orc_generate.argtypes = [i32, i32, i32, P(_Params), vp, P(_Result), vp, vp, vp, vp,
-                                      vp, vp, i32]
+                                      vp, vp, vp, vp, i32]
         _lib.orc_generate.restype = i32
         _lib.orc_generate_phases.argtypes = [i32, i32, i32, i32, P(_Params), vp, P(_Result)]
         _lib.orc_generate_phases.restype = i32
@@ -202,13 +202,16 @@ class OracleRun:
     log_count: np.ndarray | None = None
     log_draws: np.ndarray | None = None
     log_blocks: np.ndarray | None = None
+    log_band: np.ndarray | None = None
+    log_band_union: np.ndarray | None = None
 
 
 def generate(dims, solid_fraction: float, seed_prob: float, g_ref, spacing: int, key: int,
              max_steps: int = 0, birth: bool = False, log_cap: int = 0,
-             literal_front: bool = False) -> OracleRun:
+             literal_front: bool = False, bands: bool = False) -> OracleRun:
     """``literal_front``: the next sources are this step's new cells with a void
-    neighbour (Algorithm 3 as printed) instead of the whole interface."""
+    neighbour (Algorithm 3 as printed) instead of the whole interface.  ``bands``: also
+    log the sizes of the one-voxel bands around F_t and around F_t u New_t."""
     nx, ny, nz = dims
     p = _Params(float(solid_fraction), float(seed_prob), (ctypes.c_double * 3)(*g_ref),
                 int(spacing), int(max_steps), int(key), 1 if literal_front else 0, 0)
@@ -220,13 +223,16 @@ def generate(dims, solid_fraction: float, seed_prob: float, g_ref, spacing: int,
     lc = np.zeros(max(log_cap, 1), dtype=np.int64) if log_cap else None
     ld = np.zeros(max(log_cap, 1), dtype=np.int64) if log_cap else None
     lb = np.zeros(max(log_cap, 1), dtype=np.int64) if log_cap else None
+    lbf = np.zeros(max(log_cap, 1), dtype=np.int64) if (log_cap and bands) else None
+    lbu = np.zeros(max(log_cap, 1), dtype=np.int64) if (log_cap and bands) else None
     lib().orc_generate(nx, ny, nz, ctypes.byref(p), _ptr(grid), ctypes.byref(res), _ptr(b),
-                       _ptr(lf), _ptr(ln), _ptr(lc), _ptr(ld), _ptr(lb), int(log_cap))
+                       _ptr(lf), _ptr(ln), _ptr(lc), _ptr(ld), _ptr(lb), _ptr(lbf), _ptr(lbu),
+                       int(log_cap))
     m = min(res.steps, log_cap)
     cut = (lambda a: a[:m].copy() if a is not None else None)
     return OracleRun(grid, res.n_candidates, res.n_seeds, res.solid_count, res.target_count,
                      res.front_size, res.steps, res.status, b, cut(lf), cut(ln), cut(lc),
-                     cut(ld), cut(lb))
+                     cut(ld), cut(lb), cut(lbf), cut(lbu))
 
 
 @dataclass

@@ -252,6 +252,30 @@ static uint32_t void_mask(int32_t nx, int32_t ny, int32_t nz, const uint8_t* gri
   return m;
 }
 
+/* Cells of the one-voxel band around a list of cells: the cells within Chebyshev
+ * distance 1 of a listed cell, counted once each (stamp[q] == mark marks a counted cell;
+ * the caller passes a mark not yet in stamp). */
+static int64_t band_count(int32_t nx, int32_t ny, int32_t nz, const int32_t* cells, int64_t k,
+                          uint32_t* stamp, uint32_t mark) {
+  int64_t c = 0;
+  for (int64_t i = 0; i < k; ++i) {
+    int32_t x, y, z;
+    coords(nx, ny, cells[i], &x, &y, &z);
+    for (int32_t dz = -1; dz <= 1; ++dz)
+      for (int32_t dy = -1; dy <= 1; ++dy)
+        for (int32_t dx = -1; dx <= 1; ++dx) {
+          const int32_t X = x + dx, Y = y + dy, Z = z + dz;
+          if (X < 0 || Y < 0 || Z < 0 || X >= nx || Y >= ny || Z >= nz) continue;
+          const int64_t q = X + (int64_t)nx * (Y + (int64_t)ny * Z);
+          if (stamp[q] != mark) {
+            stamp[q] = mark;
+            ++c;
+          }
+        }
+  }
+  return c;
+}
+
 static int popcount32(uint32_t m) {
   int c = 0;
   while (m) { m &= m - 1; ++c; }
@@ -352,7 +376,8 @@ int64_t orc_step_fullfield(int32_t nx, int32_t ny, int32_t nz, uint8_t* grid, ui
 static int32_t generate_on(int32_t nx, int32_t ny, int32_t nz, const orc_params* p,
                            uint8_t* grid, orc_result* res, int32_t* birth, int64_t* log_front,
                            int64_t* log_new, int64_t* log_count, int64_t* log_draws,
-                           int64_t* log_blocks, int32_t log_cap);
+                           int64_t* log_blocks, int64_t* log_band, int64_t* log_band_union,
+                           int32_t log_cap);
 
 /* ------------------------------------------------------------------------ */
 /* Whole generation: seeding, front construction, then list-indexed steps    */
@@ -366,16 +391,17 @@ static int32_t generate_on(int32_t nx, int32_t ny, int32_t nz, const orc_params*
 int32_t orc_generate(int32_t nx, int32_t ny, int32_t nz, const orc_params* p, uint8_t* grid,
                      orc_result* res, int32_t* birth, int64_t* log_front, int64_t* log_new,
                      int64_t* log_count, int64_t* log_draws, int64_t* log_blocks,
-                     int32_t log_cap) {
+                     int64_t* log_band, int64_t* log_band_union, int32_t log_cap) {
   memset(grid, 0, (size_t)nx * ny * nz);
   return generate_on(nx, ny, nz, p, grid, res, birth, log_front, log_new, log_count, log_draws,
-                     log_blocks, log_cap);
+                     log_blocks, log_band, log_band_union, log_cap);
 }
 
 static int32_t generate_on(int32_t nx, int32_t ny, int32_t nz, const orc_params* p,
                            uint8_t* grid, orc_result* res, int32_t* birth, int64_t* log_front,
                            int64_t* log_new, int64_t* log_count, int64_t* log_draws,
-                           int64_t* log_blocks, int32_t log_cap) {
+                           int64_t* log_blocks, int64_t* log_band, int64_t* log_band_union,
+                           int32_t log_cap) {
   const int64_t n = (int64_t)nx * ny * nz;
   const int64_t s_star = orc_target_count(p->solid_fraction, n);
   const uint64_t t_seed = orc_prob_threshold(p->seed_prob);
@@ -388,6 +414,9 @@ static int32_t generate_on(int32_t nx, int32_t ny, int32_t nz, const orc_params*
   int32_t* added = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   uint32_t* mask = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
   uint64_t* prio = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+  /* band sizes of the step log (cells within one voxel of F_t, of F_t u New_t) */
+  uint32_t* stamp =
+      (log_band || log_band_union) ? (uint32_t*)calloc((size_t)n, sizeof(uint32_t)) : NULL;
 
   int64_t n_drawn = orc_seed_candidates(nx, ny, nz, p->key, t_seed, A, prio, n);
   int64_t n_cand = 0; /* cores only on cells still open (Sec. 2.1 step 4) */
@@ -430,6 +459,14 @@ static int32_t generate_on(int32_t nx, int32_t ny, int32_t nz, const orc_params*
       }
       if (log_draws) log_draws[t] = draws;
       if (log_blocks) log_blocks[t] = blocks;
+      if (stamp) { /* A still holds F_t, `added` New_t */
+        const uint32_t m1 = 2u * (uint32_t)t + 1u, m2 = m1 + 1u;
+        const int64_t bf = band_count(nx, ny, nz, A, nA, stamp, m1);
+        const int64_t bu = band_count(nx, ny, nz, A, nA, stamp, m2) +
+                           band_count(nx, ny, nz, added, n_new, stamp, m2);
+        if (log_band) log_band[t] = bf;
+        if (log_band_union) log_band_union[t] = bu;
+      }
     }
     if (birth)
       for (int64_t k = 0; k < n_new; ++k) birth[added[k]] = t + 1;
@@ -446,7 +483,7 @@ static int32_t generate_on(int32_t nx, int32_t ny, int32_t nz, const orc_params*
   res->front_size = nA;
   res->steps = t;
   res->status = cnt >= s_star ? ORC_DONE : (nA == 0 ? ORC_EXHAUSTED : ORC_MAXSTEPS);
-  free(A); free(A_next); free(added); free(mask); free(prio);
+  free(A); free(A_next); free(added); free(mask); free(prio); free(stamp);
   return res->status;
 }
 
@@ -467,7 +504,7 @@ int32_t orc_generate_phases(int32_t nx, int32_t ny, int32_t nz, int32_t n_phases
   int32_t worst = ORC_DONE;
   for (int32_t k = 0; k < n_phases; ++k) {
     const int32_t st = generate_on(nx, ny, nz, &phases[k], labels, &results[k], NULL, NULL,
-                                   NULL, NULL, NULL, NULL, 0);
+                                   NULL, NULL, NULL, NULL, NULL, NULL, 0);
     if (st > worst) worst = st;
     for (int64_t v = 0; v < n; ++v)
       if (labels[v] == 1) labels[v] = (uint8_t)(3 + (k + 1));

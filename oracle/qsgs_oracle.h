@@ -100,12 +100,14 @@ int64_t orc_step_fullfield(int32_t nx, int32_t ny, int32_t nz, uint8_t* grid, ui
 /* Whole generation (seeding, then the list-indexed loop).  Optional outputs may be NULL:
  * birth[v] = step at which v became solid (0 for seeds, -1 for pore), and per-step logs
  * of |F_t|, |New_t|, the solid count at the start of step t, the step's draws (one per
- * front cell and void neighbour) and its high-half Philox blocks (one per eight ranks
- * of a front cell), log_cap entries each. */
+ * front cell and void neighbour), its high-half Philox blocks (one per eight ranks of a
+ * front cell), and the sizes of the one-voxel bands (cells within Chebyshev distance 1)
+ * around F_t and around F_t u New_t -- the occupancy the step reads -- log_cap entries
+ * each. */
 int32_t orc_generate(int32_t nx, int32_t ny, int32_t nz, const orc_params* p, uint8_t* grid,
                      orc_result* res, int32_t* birth, int64_t* log_front, int64_t* log_new,
                      int64_t* log_count, int64_t* log_draws, int64_t* log_blocks,
-                     int32_t log_cap);
+                     int64_t* log_band, int64_t* log_band_union, int32_t log_cap);
 
 /* Multi-phase generation (Sec. 2.1 steps 1-5), independent phases in sequence:
  * labels[v] = n for a cell of growing phase n (1..n_phases), 0 for the matrix phase.

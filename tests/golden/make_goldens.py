@@ -4,8 +4,10 @@ Calls only the CPU oracle (``oracle/``) on the inputs stated in ``workloads.py``
 GPU tests compare the library's outputs with these stored values.  Each entry holds
 the SHA-256 of the final grid (N bytes, C order), the counts, the terminal status and
 the per-step series |F_t|, |New_t|, the solid count at the start of each step and the
-step's work (draws, high-half Philox blocks).  The group ``lit`` runs cases with the
-literal Algorithm 3 front rule (entries named ``<case>_literal``, ``literal_front`` true).
+step's work (draws, high-half Philox blocks) and the sizes of the one-voxel bands
+around F_t and around F_t u New_t (the occupancy a step reads).  The group ``lit`` runs
+cases with the literal Algorithm 3 front rule (entries named ``<case>_literal``,
+``literal_front`` true).
 
     python tests/golden/make_goldens.py [--jobs 8] [--only c2,c3,lit,c4,c4s,c5]
 """
@@ -34,7 +36,8 @@ def run_case(job: tuple) -> dict:
                           "g_ref": tuple(case_dict["g_ref"])})
     t0 = time.time()
     r = oracle.generate(c.dims, c.solid_fraction, c.seed_prob, c.g_ref, c.spacing, c.key,
-                        max_steps=c.max_steps, log_cap=100000, literal_front=literal)
+                        max_steps=c.max_steps, log_cap=100000, literal_front=literal,
+                        bands=True)
     return {
         "name": c.name + ("_literal" if literal else ""), "literal_front": literal,
         "case": c.as_dict(),
@@ -45,6 +48,8 @@ def run_case(job: tuple) -> dict:
         "log_front": [int(x) for x in r.log_front], "log_new": [int(x) for x in r.log_new],
         "log_count": [int(x) for x in r.log_count],
         "log_draws": [int(x) for x in r.log_draws], "log_blocks": [int(x) for x in r.log_blocks],
+        "log_band": [int(x) for x in r.log_band],
+        "log_band_union": [int(x) for x in r.log_band_union],
         "oracle_seconds": round(time.time() - t0, 2),
     }
 

@@ -216,3 +216,23 @@ def test_literal_front_equals_interface_rule_when_every_draw_passes(orc):
                          literal_front=True)
         assert np.array_equal(a.grid, b.grid) and a.steps == b.steps
         assert np.array_equal(a.log_front, b.log_front)
+
+
+def test_band_logs_equal_dilations_of_the_birth_map(orc):
+    """The per-step band sizes the oracle logs (cells within one voxel of F_t, and of
+    F_t u New_t) equal scipy dilations of the front and new sets rebuilt from the birth
+    map: G_t = {birth <= t}, F_t = G_t minus the cells without a void 26-neighbour,
+    New_t = {birth = t + 1}."""
+    from scipy import ndimage
+    dims = (31, 27, 23)
+    r = orc.generate(dims, 0.7, 0.01, (0.05, 0.02, 0.005), 3, 9, birth=True, log_cap=1000,
+                     bands=True)
+    full = ndimage.generate_binary_structure(3, 3)
+    for t in range(r.steps):
+        g = (r.birth >= 0) & (r.birth <= t)
+        front = g & ndimage.binary_dilation(~g, structure=full, border_value=0)
+        new = r.birth == t + 1
+        assert int(front.sum()) == r.log_front[t]
+        assert int(ndimage.binary_dilation(front, structure=full).sum()) == r.log_band[t]
+        assert int(ndimage.binary_dilation(front | new, structure=full).sum()) == \
+            r.log_band_union[t]
