@@ -98,7 +98,8 @@ typedef struct {
   int64_t front_size;     /* |F_t| now                                                      */
   int64_t grown_last_step;/* |New| of the last step taken                                   */
   int32_t step;           /* growth steps taken so far (t)                                  */
-  int32_t status;         /* a qsgs_status value >= 0                                       */
+  int32_t status;         /* a qsgs_status value >= 0 (QSGS_ERR_DEVICE for a failed       */
+                          /* server request)                                                */
 } qsgs_info;
 
 /* Bytes a grid buffer needs: N + 8 rounded up to a multiple of 4.  The voxels occupy the
@@ -282,11 +283,15 @@ int64_t qsgs_read_step_work(const void* d_ws, size_t ws_bytes, int32_t index, in
  *                        id in use, QSGS_ERR_CAPACITY if it cannot fit the arena even
  *                        when alone.
  *   qsgs_server_tick     one scheduling tick; reports resident, queued and finished
- *                        (not yet taken) requests.  Synchronises the stream.
+ *                        (not yet taken) requests.  Synchronises the stream.  If a
+ *                        request fails (an internal list overflow), it is retired with
+ *                        info.status = QSGS_ERR_DEVICE and its arena space released, the
+ *                        tick still retires the others, and then returns QSGS_ERR_DEVICE.
  *   qsgs_server_ready    ids and infos of finished requests, oldest first (at most max).
  *   qsgs_server_take     copies the N-byte grid of a finished request to dst (host
  *                        memory if dst_on_host, else device; dst may be NULL to drop it)
- *                        and releases its arena space.
+ *                        and releases its arena space; for a failed request it copies
+ *                        nothing, forgets the request and returns QSGS_ERR_DEVICE.
  *   qsgs_server_free_bytes  arena bytes not held by requests. */
 typedef struct qsgs_server qsgs_server;
 size_t qsgs_server_reserved_bytes(int32_t max_slots);

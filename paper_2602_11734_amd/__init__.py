@@ -315,8 +315,15 @@ def qsgs_server_submit(server: int, request_id: int, dims, params: qsgs_params) 
 
 
 def qsgs_server_tick(server: int) -> tuple[int, int, int]:
+    """(resident, queued, ready).  A tick that retired a failed request raises
+    QsgsError(ERR_DEVICE) with the counts in ``.counts``; the server stays usable."""
     a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(load().qsgs_server_tick(server, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    try:
+        _check(load().qsgs_server_tick(server, ctypes.byref(a), ctypes.byref(b),
+                                       ctypes.byref(c)))
+    except QsgsError as e:
+        e.counts = (a.value, b.value, c.value)
+        raise
     return a.value, b.value, c.value
 
 
@@ -328,13 +335,16 @@ def qsgs_server_ready(server: int, max_n: int = 4096):
 
 
 def qsgs_server_take(server: int, request_id: int, dst=None, dst_bytes: int = 0,
-                     dst_on_host: bool = False) -> None:
+                     dst_on_host: bool = False, check: bool = True) -> int:
+    """Copies out (or drops, dst=None) a finished request's grid; returns the status
+    (raises on an error unless check=False, e.g. to drop a failed request)."""
     if dst is not None and hasattr(dst, "ctypes"):  # numpy array on the host
         ptr, dst_on_host, dst_bytes = dst.ctypes.data, True, dst.nbytes
     else:
         ptr = _ptr(dst)
-    _check(load().qsgs_server_take(server, int(request_id), ptr, int(dst_bytes),
-                                   1 if dst_on_host else 0))
+    st = load().qsgs_server_take(server, int(request_id), ptr, int(dst_bytes),
+                                 1 if dst_on_host else 0)
+    return _check(st) if check else st
 
 
 def qsgs_server_free_bytes(server: int) -> int:

@@ -68,6 +68,7 @@ struct qsgs_server {
     Spec spec{};
     size_t grid_off = 0, front_off = 0;
     int32_t slot = -1;
+    bool failed = false;  // finished with an error: no grid is kept
     qsgs_info info{};
   };
 
@@ -263,6 +264,7 @@ qsgs_status qsgs_server_tick(qsgs_server* S, int32_t* n_resident, int32_t* n_que
 
   // Retire finished requests: their fronts return to the arena, the grid waits.
   std::vector<Real>& recs = S->recs;
+  int64_t failed_id = -1;
   QSGS_TRY(E.read_all(&recs));
   for (size_t slot = 0; slot < S->slot_req.size(); ++slot) {
     const int64_t id = S->slot_req[slot];
@@ -272,17 +274,25 @@ qsgs_status qsgs_server_tick(qsgs_server* S, int32_t* n_resident, int32_t* n_que
     qsgs_server::Request q = S->resident.at(id);
     S->resident.erase(id);
     S->slot_req[slot] = -1;
-    if (R.ctl.status == kStatusOverflow || R.ctl.bad_entry)
-      return fail(QSGS_ERR_DEVICE, "internal front overflow in request %lld", (long long)id);
     fill_info(R.ctl, &q.info);
     S->heap.release(q.front_off, qsgs_server::front_bytes(q.spec.g));
     q.slot = -1;
+    if (R.ctl.status == kStatusOverflow || R.ctl.bad_entry) {
+      // an internal list overflowed: the request fails, its grid is released at once,
+      // and the other requests of this tick are still retired
+      S->heap.release(q.grid_off, align_up(grid_bytes(q.spec.g)));
+      q.failed = true;
+      q.info.status = QSGS_ERR_DEVICE;
+      if (failed_id < 0) failed_id = id;
+    }
     S->done.emplace(id, q);
     S->ready.push_back(id);
   }
   if (n_resident) *n_resident = (int32_t)S->resident.size();
   if (n_queued) *n_queued = (int32_t)S->queue.size();
   if (n_ready) *n_ready = (int32_t)S->ready.size();
+  if (failed_id >= 0)
+    return fail(QSGS_ERR_DEVICE, "internal front overflow in request %lld", (long long)failed_id);
   return QSGS_OK;
 }
 
@@ -307,6 +317,12 @@ qsgs_status qsgs_server_take(qsgs_server* S, int64_t request_id, void* dst, size
     return fail(QSGS_ERR_INVALID, "request %lld is not finished", (long long)request_id);
   const qsgs_server::Request& q = it->second;
   const size_t n = q.spec.g.n;
+  if (q.failed) {  // its grid was released when it failed
+    S->ready.erase(std::find(S->ready.begin(), S->ready.end(), request_id));
+    S->done.erase(it);
+    return fail(QSGS_ERR_DEVICE, "request %lld failed (internal front overflow)",
+                (long long)request_id);
+  }
   if (dst) {
     if (dst_bytes < n) return fail(QSGS_ERR_INVALID, "dst needs %zu bytes", n);
     QSGS_HIP(hipMemcpyAsync(dst, S->arena + q.grid_off, n,

@@ -12,8 +12,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (params_of, qsgs_generate, qsgs_server_create, qsgs_server_destroy,
-               qsgs_server_ready, qsgs_server_reserved_bytes, qsgs_server_submit,
+from . import (ERR_DEVICE, QsgsError, params_of, qsgs_generate, qsgs_server_create,
+               qsgs_server_destroy, qsgs_server_ready, qsgs_server_reserved_bytes, qsgs_server_submit,
                qsgs_server_take, qsgs_server_tick, qsgs_grid_bytes, qsgs_workspace_bytes)
 
 
@@ -23,6 +23,7 @@ class StreamResult:
     makespan_s: float         # first arrival to last completion
     grown: int                # voxels grown over all requests
     max_resident: int = 0
+    failed: tuple = ()        # ids of requests the server retired as failed
 
     def summary(self) -> dict:
         lat = self.latencies_s
@@ -33,7 +34,8 @@ class StreamResult:
                 "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
                 "mean_latency_ms": float(lat.mean() * 1e3),
                 "makespan_s": float(self.makespan_s),
-                "max_resident": int(self.max_resident)}
+                "max_resident": int(self.max_resident),
+                "failed": len(self.failed)}
 
 
 def serve_stream(requests, arena_bytes: int, max_slots: int = 64, steps_per_tick: int = 2,
@@ -50,6 +52,7 @@ def serve_stream(requests, arena_bytes: int, max_slots: int = 64, steps_per_tick
     finished = 0
     max_res = 0
     nxt = 0
+    failed = []
     try:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -66,11 +69,22 @@ def serve_stream(requests, arena_bytes: int, max_slots: int = 64, steps_per_tick
                 # idle: wait for the next arrival
                 time.sleep(max(0.0, min(requests[nxt].arrival_s - now, 0.005)))
                 continue
-            resident, queued, nready = qsgs_server_tick(srv)
+            try:
+                resident, queued, nready = qsgs_server_tick(srv)
+            except QsgsError as e:  # a failed request was retired; the others go on
+                if e.status != ERR_DEVICE or not hasattr(e, "counts"):
+                    raise
+                resident, queued, nready = e.counts
             max_res = max(max_res, resident)
             if nready:
                 t_done = time.perf_counter() - t0
                 for rid, info in qsgs_server_ready(srv):
+                    if info.status < 0:  # failed: nothing to copy out
+                        qsgs_server_take(srv, rid, None, check=False)
+                        failed.append(rid)
+                        done_at[rid] = t_done
+                        finished += 1
+                        continue
                     if keep is not None:
                         c = requests[rid].case
                         out = np.empty(c.n, dtype=np.uint8)
@@ -85,7 +99,7 @@ def serve_stream(requests, arena_bytes: int, max_slots: int = 64, steps_per_tick
     finally:
         qsgs_server_destroy(srv)
     arrivals = np.array([r.arrival_s for r in requests])
-    return StreamResult(done_at - arrivals, makespan, grown, max_res)
+    return StreamResult(done_at - arrivals, makespan, grown, max_res, tuple(failed))
 
 
 def plain_stream(requests) -> StreamResult:
