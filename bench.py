@@ -43,22 +43,48 @@ def sweep_pass_ops(log_front, log_draws, log_blocks, final_front):
     return out + [OPS_PER_FRONT * final_front]
 
 
-def sweep_pass_bytes(log_front, log_new, n_seeds, final_front):
-    """Algorithmic bytes of every fused-sweep pass of one generation (one pass per step
-    plus the final prune-only pass).  Pass t reads L_t = F_{t-1} + New_{t-1} (4 B per
-    entry) and each entry's own grid byte (1 B; the rest of its 3x3x3 neighbourhood is
-    shared with neighbouring entries), folds New_{t-1} (1 B each), claims New_t (1 B
-    each) and writes L_{t+1} = F_t + New_t (4 B per entry).  L_0 is the seed list."""
-    out = []
-    prev_f, prev_n = None, None
+# occupancy bytes per cell of the growth sweep: one bit per cell and plane
+OCC_BYTES = 1.0 / 8.0
+
+
+def step_bytes(log_front, log_new, band_f, band_u, final_front, g=OCC_BYTES):
+    """Algorithmic bytes of every growth step of one generation (the list-indexed step's
+    own traffic, not the full-field work it avoids): step t reads F_t (4 B per entry) and
+    the occupancy of the one-voxel band around F_t (g B per cell), marks and appends New_t
+    (g + 8 B per voxel: the mark, the append and its read back), reads the occupancy of
+    the band around F_t u New_t to prune (g B per cell) and writes F_{t+1} (4 B per
+    entry):  B_t = 4|F_t| + g|band(F_t)| + (g + 8)|New_t| + g|band(F_t u New_t)|
+    + 4|F_{t+1}|."""
     fronts = list(log_front) + [final_front]
-    news = list(log_new) + [0]
-    for t, (f, g) in enumerate(zip(fronts, news)):
-        l_in = n_seeds if t == 0 else prev_f + prev_n
-        folded = 0 if t == 0 else prev_n
-        out.append(5 * l_in + folded + g + 4 * (f + g))
-        prev_f, prev_n = f, g
-    return out
+    return [4 * fronts[t] + g * band_f[t] + (g + 8) * log_new[t] + g * band_u[t] +
+            4 * fronts[t + 1] for t in range(len(log_front))]
+
+
+def step_api_bands(q, torch, case):
+    """Per-step band sizes (|band(F_t)|, |band(F_t u New_t)|) of `case`, from a run of
+    the step API (the same grid evolution as qsgs_generate) with the grid copied before
+    every step.  Outside every timed region."""
+    n = case.n
+    p = q.params_of(case)
+    grid = torch.empty(q.qsgs_grid_bytes(case.dims), dtype=torch.uint8, device="cuda")
+    before = torch.empty_like(grid)
+    fa = torch.empty(n, dtype=torch.int32, device="cuda")
+    fb = torch.empty(n, dtype=torch.int32, device="cuda")
+    wsb = q.qsgs_workspace_bytes(case.dims, p)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    sws = torch.empty(q.qsgs_step_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    sb = q.qsgs_band_scratch_bytes(case.dims)
+    scratch = torch.empty(sb, dtype=torch.uint8, device="cuda")
+    st, info = q.qsgs_seed(case.dims, p, grid, fa, n, ws, wsb)
+    bf, bu = [], []
+    while st == q.OK:
+        before.copy_(grid)
+        st, info = q.qsgs_grow_step(case.dims, p, grid, fa, fb, n, sws, sws.numel(), info)
+        fa, fb = fb, fa
+        f, u = q.qsgs_band_sizes(case.dims, before, grid, scratch, sb)
+        bf.append(f)
+        bu.append(u)
+    return bf, bu
 
 
 KERNEL_SOURCES = ("qsgs_kernels.hip", "qsgs_device.h", "qsgs_internal.h", "qsgs_host.h")
@@ -90,18 +116,77 @@ def measured_traffic(launches_per_step: float):
     return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
 
 
-def cpu_baseline(case, steps: int):
-    """The oracle (single thread) on the first `steps` growth steps of `case`."""
+def _oracle_job(case):
+    """One end-to-end oracle generation (runs in a worker process)."""
     from oracle import oracle
-    oracle.build()
     t0 = time.perf_counter()
     r = oracle.generate(case.dims, case.solid_fraction, case.seed_prob, case.g_ref,
-                        case.spacing, case.key, max_steps=steps, log_cap=steps)
-    dt = time.perf_counter() - t0
-    grown = r.solid_count - r.n_seeds
-    return {"value": grown / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
-            "sample": f"{case.name}: seeding + first {r.steps} growth steps "
-                      f"({grown} voxels grown) in {dt:.1f} s on one host core"}
+                        case.spacing, case.key)
+    return r.solid_count - r.n_seeds, time.perf_counter() - t0, r.steps
+
+
+def host_cpu() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def cpu_baseline(cases, edge: int = 128, max_workers: int = 16):
+    """The oracle (plain single-threaded C, as committed) timed on this host's cores on
+    a bounded sample of the headline workload: the 400^3 parameter sets (porosity
+    0.10 / 0.20 / 0.30, S_d 5e-4, s = 20, G_ref 0.01 / 0.0025 / 0.000625) on an
+    edge^3 grid, each generation end to end (seeding and every growth step).  One
+    generation in this process gives the one-core rate; then one generation per worker
+    process (porosities in turn, keys 1, 2, ...) over all usable cores (at most
+    max_workers) gives the all-cores rate, the value.  Runs before the GPU is touched, so
+    the workers are plain forks of a process without GPU state."""
+    from concurrent.futures import ProcessPoolExecutor
+    import dataclasses
+    from oracle import oracle
+    oracle.build()
+    sample = [dataclasses.replace(c, name=f"{c.name}_at_{edge}", dims=(edge,) * 3)
+              for c in cases]
+    grown1, dt1, steps1 = _oracle_job(sample[1])
+    workers = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    jobs = [dataclasses.replace(sample[j % len(sample)], key=1 + j // len(sample))
+            for j in range(workers)]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        res = list(ex.map(_oracle_job, jobs))
+    wall = time.perf_counter() - t0
+    grown_all = sum(r[0] for r in res)
+    out = {"value": grown_all / wall, "unit": "voxels/s", "cores": workers, "kind": "oracle",
+           "sample": f"{workers} end-to-end oracle generations in parallel processes, one per "
+                     f"core: the 400^3 workload's parameters (porosity 0.10/0.20/0.30 in turn, "
+                     f"keys 1..) on {edge}^3 grids; {grown_all} voxels grown in {wall:.1f} s",
+           "one_core": {"value": grown1 / dt1, "unit": "voxels/s",
+                        "sample": f"{sample[1].name}: {steps1} steps, {grown1} voxels grown "
+                                  f"in {dt1:.1f} s"},
+           "host": host_cpu()}
+    # the full 400^3 oracle runs stored with the golden values (timed when they were
+    # written, on the build host, one core each), for scale: the full grid no longer
+    # fits the caches, which lowers the rate
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            runs = json.load(f)
+        full = {}
+        for c in cases:
+            e = runs.get(c.name)
+            if e and e.get("oracle_seconds"):
+                full[c.name] = {"voxels_grown": e["solid_count"] - e["n_seeds"],
+                                "seconds": e["oracle_seconds"],
+                                "voxels_per_s": (e["solid_count"] - e["n_seeds"]) /
+                                e["oracle_seconds"]}
+        out["stored_full_400_runs_one_core"] = full
+    return out
 
 
 def batched_vs_plain(q, torch):
@@ -273,20 +358,54 @@ def multiphase(q, torch):
             "counts_match_labels": counts[1:] == [i.solid_count for i in infos]}
 
 
-def served_vs_plain(n_requests: int, rate: float):
-    """Poisson request stream (mixed sizes): continuous batching against the plain
-    one-at-a-time path on the same arrivals; p50/p99 latency and realizations/s."""
+def grid_store(q, torch, reqs):
+    """One device buffer with a grid slot (qsgs_grid_bytes, 256-byte aligned) per request;
+    returns (buffer, {request id: view})."""
+    sizes = [(q.qsgs_grid_bytes(r.case.dims) + 255) // 256 * 256 for r in reqs]
+    buf = torch.empty(sum(sizes), dtype=torch.uint8, device="cuda")
+    views, off = {}, 0
+    for r, sz in zip(reqs, sizes):
+        views[r.rid] = buf[off:off + sz]
+        off += sz
+    return buf, views
+
+
+def served_vs_plain(q, torch, n_requests: int, loads=(0.8, 1.2), light=(0.2, 300)):
+    """The request stream of mixed sizes (cube edge U{64..320}, porosity U[0.05,0.30],
+    s U{4..30}, S_d U[5e-4,5e-3], face U[0.005,0.02], key = request id) through the
+    continuous-batching server and through the plain one-at-a-time path on the same
+    Poisson arrivals.  The server's capacity on the mix (every request present at the
+    start) sets the rates: `loads` x capacity for n_requests, plus a light load
+    (light[0] x capacity, first light[1] requests).  Every served grid is compared byte
+    for byte with the plain path's grid of the same request (both kept on the device)."""
     from paper_2602_11734_amd import serving
-    import paper_2602_11734_amd as q
-    reqs = workloads.config5(n_requests=n_requests, rate_per_s=rate)
     budget = 24 << 30
-    arena = serving.server_arena_bytes(reqs, 64, budget)
-    served = serving.serve_stream(reqs, arena, max_slots=64, steps_per_tick=4).summary()
-    plain = serving.plain_stream(reqs).summary()
-    return {"workload": f"{n_requests} requests at {rate:g}/s, edge U{{64..320}}, porosity "
-                        "U[0.05,0.30], s U{4..30}, S_d U[5e-4,5e-3], face U[0.005,0.02], "
-                        "key = request id", "arena_budget_bytes": budget,
-            "served": served, "plain": plain}
+    slots = 64
+    arena = serving.server_arena_bytes(None, slots, budget)
+    reqs = workloads.config5(n_requests, rate_per_s=1e9)
+    cap = serving.serve_stream(reqs, arena, max_slots=slots, steps_per_tick=4).summary()
+    capacity = cap["realizations_per_s"]
+    out = {"workload": f"{n_requests} requests, edge U{{64..320}}, porosity U[0.05,0.30], "
+                       "s U{4..30}, S_d U[5e-4,5e-3], face U[0.005,0.02] at 4:1:0.25, key = "
+                       "request id, Poisson arrivals", "arena_budget_bytes": budget,
+           "max_slots": slots, "capacity": cap}
+    bufs, views_s = grid_store(q, torch, reqs)
+    bufp, views_p = grid_store(q, torch, reqs)
+    runs = [(f"load_{f:g}", f, n_requests) for f in loads] + [
+        (f"light_load_{light[0]:g}", light[0], light[1])]
+    for name, frac, nreq in runs:
+        rate = frac * capacity
+        rq = workloads.config5(n_requests, rate_per_s=rate)[:nreq]
+        served = serving.serve_stream(rq, arena, max_slots=slots, steps_per_tick=4,
+                                      out=views_s).summary()
+        plain = serving.plain_stream(rq, out=views_p).summary()
+        torch.cuda.synchronize()
+        same = all(bool(torch.equal(views_s[r.rid][:r.case.n], views_p[r.rid][:r.case.n]))
+                   for r in rq)
+        out[name] = {"rate_per_s": rate, "requests": nreq, "served": served, "plain": plain,
+                     "identical_outputs": same}
+    del bufs, bufp
+    return out
 
 
 def main():
@@ -295,7 +414,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-edge", type=int, default=128,
+                    help="grid edge of the oracle's bounded sample (the 400^3 parameters)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the list-indexed vs full-field comparison")
     ap.add_argument("--no-batch", action="store_true",
@@ -304,10 +424,7 @@ def main():
                     help="skip the three-phase 400^3 generation")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served vs plain request-stream measurement")
-    ap.add_argument("--serve-requests", type=int, default=300)
-    ap.add_argument("--serve-rate", type=float, default=150.0,
-                    help="arrivals per second of the moderate-load run (an overload run at "
-                         "20x the rate follows)")
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy kernel over BYTES bytes three times "
                          "(the reference kernel for scaling HBM byte counters)")
@@ -318,6 +435,12 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    # the CPU leg first, before anything touches the GPU (its workers are forks)
+    cpu = None
+    if not args.no_cpu_baseline and not args.copy_calibration:
+        cpu = cpu_baseline(workloads.config3(), edge=args.cpu_edge)
+
     import torch
 
     import paper_2602_11734_amd as q
@@ -373,13 +496,16 @@ def main():
     grown = sum(info["solid_count"] - info["n_seeds"] for _, info, _ in runs)
     value = grown / elapsed
     # algorithmic ops and bytes of the timed sweep launches (every pass of every
-    # generation)
+    # generation: one per step, plus the final prune-only pass)
     ops = [sweep_pass_ops(lg[0], lg[3], lg[4], info["front_size"]) for _, info, lg in runs]
-    passes = [sweep_pass_bytes(lg[0], lg[1], info["n_seeds"], info["front_size"])
-              for _, info, lg in runs]
-    launches = sum(len(x) for x in passes)
-    assert launches == sum(len(x) for x in ops) == int(prof["grow_launches"]), (launches, prof)
-    sbytes = sum(sum(x) for x in passes)
+    launches = sum(len(x) for x in ops)
+    assert launches == int(prof["grow_launches"]), (launches, prof)
+    bands = {c.name: step_api_bands(q, torch, c) for c in cases}
+    sbytes = 0.0
+    for name, info, lg in runs:
+        bf, bu = bands[name]
+        assert len(bf) == len(lg[0]) == info["step"], (name, len(bf), len(lg[0]))
+        sbytes += sum(step_bytes(lg[0], lg[1], bf, bu, info["front_size"]))
     sops = sum(sum(x) for x in ops)
     sweep_avg_ms = prof["grow_ms"] / max(launches, 1)
     sweep_s = sweep_avg_ms * 1e-3
@@ -419,7 +545,10 @@ def main():
                      "ops_per_launch": sops / max(launches, 1),
                      "hbm_algorithmic": {"achieved": sweep_gbs, "peak": HBM_PEAK_GBS,
                                          "unit": "GB/s", "frac": sweep_gbs / HBM_PEAK_GBS,
-                                         "bytes_per_launch": sbytes / max(launches, 1)}},
+                                         "bytes_per_launch": sbytes / max(launches, 1),
+                                         "occupancy_bytes_per_cell": OCC_BYTES,
+                                         "band_cells": {k: [sum(v[0]), sum(v[1])]
+                                                        for k, v in bands.items()}}},
         "detail": {"sweep_ms_total": prof["grow_ms"], "seed_ms_total": prof["seed_ms"],
                    "growth_only_voxels_per_s": grown / (prof["grow_ms"] * 1e-3),
                    "n_over_t_per_realization": cases[0].n * 3 * args.steps / elapsed,
@@ -436,11 +565,9 @@ def main():
     if not args.no_phases:
         out["detail"]["multiphase"] = multiphase(q, torch)
     if not args.no_serve:
-        out["detail"]["serving"] = {
-            "moderate_load": served_vs_plain(args.serve_requests, args.serve_rate),
-            "overload": served_vs_plain(args.serve_requests, 20 * args.serve_rate)}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cases[1], args.cpu_steps)
+        out["detail"]["serving"] = served_vs_plain(q, torch, args.serve_requests)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

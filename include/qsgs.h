@@ -327,6 +327,23 @@ typedef struct {
 qsgs_status qsgs_set_tuning(const qsgs_tuning* tuning);
 void qsgs_get_tuning(qsgs_tuning* tuning);
 
+/* The occupancy one growth step reads, for the algorithmic byte count of a step.  A
+ * step tests the 26 neighbours of every voxel of F_t (Sec. 2.3 step 3), then keeps the
+ * voxels of F_t u New_t that still have a void neighbour (Sec. 2.3 step 4): it reads the
+ * one-voxel band (in-domain cells within Chebyshev distance 1) around F_t and around
+ * F_t u New_t.  From the grid before a step (d_before) and after it (d_after), both N
+ * bytes in the layout of qsgs_grid_bytes (0 = void, any other value solid), computes
+ *   out[0] = |band(F_t)|, F_t = solid cells of d_before with an in-domain void neighbour;
+ *   out[1] = |band(F_t u New_t)|, New_t = cells void in d_before and solid in d_after.
+ *   d_scratch  device, 8-byte aligned, >= qsgs_band_scratch_bytes(dims); overwritten.
+ *   out        host uint64_t[2].
+ * A measurement utility (two passes over the grid), not part of the growth path.
+ * Errors: QSGS_ERR_INVALID, QSGS_ERR_WORKSPACE, QSGS_ERR_DEVICE.  Synchronises `stream`. */
+size_t qsgs_band_scratch_bytes(const qsgs_dims* dims);
+qsgs_status qsgs_band_sizes(const qsgs_dims* dims, const uint8_t* d_before,
+                            const uint8_t* d_after, void* d_scratch, size_t scratch_bytes,
+                            uint64_t* out, void* stream);
+
 /* Kernel timing for measurement.  While enabled (enable != 0), qsgs_generate records HIP
  * events around each growth-sweep and prune launch on its stream and accumulates their
  * durations; qsgs_profile_read returns (and with reset != 0 clears) the totals:

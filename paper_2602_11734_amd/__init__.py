@@ -85,6 +85,8 @@ SIGNATURES = {
                                                         _VP, _SZ, _VP, _VP]),
     "qsgs_read_step_log": (_I64, [_VP, _SZ, _I32, _VP, _VP, _VP, _I64, _VP]),
     "qsgs_read_step_work": (_I64, [_VP, _SZ, _I32, _VP, _VP, _I64, _VP]),
+    "qsgs_band_scratch_bytes": (_SZ, [_P(qsgs_dims)]),
+    "qsgs_band_sizes": (ctypes.c_int, [_P(qsgs_dims), _VP, _VP, _VP, _SZ, _VP, _VP]),
     "qsgs_server_reserved_bytes": (_SZ, [_I32]),
     "qsgs_server_create": (ctypes.c_int, [_VP, _SZ, _I32, _I32, _VP, _P(_VP)]),
     "qsgs_server_submit": (ctypes.c_int, [_VP, _I64, _P(qsgs_dims), _P(qsgs_params)]),
@@ -241,6 +243,18 @@ def qsgs_read_step_work(ws, ws_bytes: int, index: int = 0, max_entries: int = 65
                                    blocks.ctypes.data, int(max_entries), _stream(stream))
     n = _check(int(n))
     return draws[:n].copy(), blocks[:n].copy()
+
+
+def qsgs_band_scratch_bytes(dims) -> int:
+    return int(load().qsgs_band_scratch_bytes(ctypes.byref(make_dims(dims))))
+
+
+def qsgs_band_sizes(dims, before, after, scratch, scratch_bytes: int, stream=None):
+    """(|band(F_t)|, |band(F_t u New_t)|) of the step that took grid `before` to `after`."""
+    out = (ctypes.c_uint64 * 2)()
+    _check(load().qsgs_band_sizes(ctypes.byref(make_dims(dims)), _ptr(before), _ptr(after),
+                                  _ptr(scratch), int(scratch_bytes), out, _stream(stream)))
+    return int(out[0]), int(out[1])
 
 
 def qsgs_batch_workspace_bytes(dims_list, params_list) -> int:

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqsgs.so")
-SOURCES = ["qsgs_kernels.hip", "qsgs_api.hip", "qsgs_server.hip"]
+SOURCES = ["qsgs_kernels.hip", "qsgs_api.hip", "qsgs_server.hip", "qsgs_measure.hip"]
 HEADERS = ["qsgs_device.h", "qsgs_internal.h", "qsgs_host.h"]
 
 HIPCC_FLAGS = [

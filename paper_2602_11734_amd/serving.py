@@ -39,10 +39,12 @@ class StreamResult:
 
 
 def serve_stream(requests, arena_bytes: int, max_slots: int = 64, steps_per_tick: int = 2,
-                 keep=None) -> StreamResult:
+                 keep=None, out=None) -> StreamResult:
     """Continuous batching: requests are submitted when they arrive; every tick admits
     what fits the arena, seeds it, advances all resident requests and retires the
-    finished ones.  `keep(rid, host_grid)` receives each result if given."""
+    finished ones.  `keep(rid, host_grid)` receives each result if given; with `out`
+    (request id -> device uint8 tensor of at least N bytes) each result is copied into
+    out[rid] on the device instead."""
     import torch
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
     srv = qsgs_server_create(arena, arena_bytes, max_slots, steps_per_tick)
@@ -85,11 +87,14 @@ def serve_stream(requests, arena_bytes: int, max_slots: int = 64, steps_per_tick
                         done_at[rid] = t_done
                         finished += 1
                         continue
-                    if keep is not None:
+                    if out is not None:
+                        dst = out[rid]
+                        qsgs_server_take(srv, rid, dst, dst.numel(), dst_on_host=False)
+                    elif keep is not None:
                         c = requests[rid].case
-                        out = np.empty(c.n, dtype=np.uint8)
-                        qsgs_server_take(srv, rid, out)
-                        keep(rid, out)
+                        host = np.empty(c.n, dtype=np.uint8)
+                        qsgs_server_take(srv, rid, host)
+                        keep(rid, host)
                     else:
                         qsgs_server_take(srv, rid, None)
                     done_at[rid] = t_done
@@ -102,8 +107,10 @@ def serve_stream(requests, arena_bytes: int, max_slots: int = 64, steps_per_tick
     return StreamResult(done_at - arrivals, makespan, grown, max_res, tuple(failed))
 
 
-def plain_stream(requests) -> StreamResult:
-    """The plain path: one qsgs_generate per request, first come first served."""
+def plain_stream(requests, out=None) -> StreamResult:
+    """The plain path: one qsgs_generate per request, first come first served.  With
+    `out` (request id -> device uint8 tensor of qsgs_grid_bytes(dims)) each request is
+    generated into out[rid]."""
     import torch
     n = len(requests)
     done_at = np.zeros(n)
@@ -119,7 +126,8 @@ def plain_stream(requests) -> StreamResult:
         now = time.perf_counter() - t0
         if r.arrival_s > now:
             time.sleep(r.arrival_s - now)
-        st, info = qsgs_generate(r.case.dims, params_of(r.case), grid, ws, wbytes)
+        st, info = qsgs_generate(r.case.dims, params_of(r.case),
+                                 grid if out is None else out[r.rid], ws, wbytes)
         done_at[k] = time.perf_counter() - t0
         grown += info.solid_count - info.n_seeds
     makespan = done_at.max() - requests[0].arrival_s

@@ -231,3 +231,19 @@ def test_noalloc_refuses_oversized_grids_before_touching_a_device(q):
     assert st == q.ERR_WORKSPACE
     assert "scratch" in q.qsgs_last_error()
     assert q.qsgs_workspace_bytes((400, 400, 400), p) > 128 << 20
+
+
+def test_band_sizes_arguments_checked(q):
+    """The band-size utility: scratch size query and argument checks before any launch."""
+    lib = q.load()
+    assert q.qsgs_band_scratch_bytes((10, 10, 10)) >= 1000 + 16
+    assert q.qsgs_band_scratch_bytes((0, 10, 10)) == 0
+    d = ctypes.byref(q.make_dims((10, 10, 10)))
+    out = (ctypes.c_uint64 * 2)()
+    sb = q.qsgs_band_scratch_bytes((10, 10, 10))
+    assert lib.qsgs_band_sizes(d, None, 256, 512, sb, out, None) == q.ERR_INVALID
+    assert lib.qsgs_band_sizes(d, 256, 256, 512, sb, None, None) == q.ERR_INVALID
+    assert lib.qsgs_band_sizes(d, 256, 256, 512, 16, out, None) == q.ERR_WORKSPACE
+    assert lib.qsgs_band_sizes(d, 256, 256, 516, sb, out, None) == q.ERR_INVALID  # alignment
+    bad = ctypes.byref(q.make_dims((0, 1, 1)))
+    assert lib.qsgs_band_sizes(bad, 256, 256, 512, sb, out, None) == q.ERR_INVALID
