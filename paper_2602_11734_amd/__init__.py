@@ -55,7 +55,7 @@ class qsgs_tuning(ctypes.Structure):
     _fields_ = [("grow_block", ctypes.c_int32), ("grow_grid", ctypes.c_int32),
                 ("prune_block", ctypes.c_int32), ("prune_grid", ctypes.c_int32),
                 ("seed_block", ctypes.c_int32), ("seed_grid", ctypes.c_int32),
-                ("steps_per_sync", ctypes.c_int32)]
+                ("steps_per_sync", ctypes.c_int32), ("graphs", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -371,7 +371,7 @@ def qsgs_server_destroy(server: int) -> None:
 
 def qsgs_set_tuning(tuning: qsgs_tuning | dict | None) -> None:
     if isinstance(tuning, dict):
-        tuning = qsgs_tuning(**tuning)
+        tuning = qsgs_tuning(**{"graphs": 1, **tuning})
     _check(load().qsgs_set_tuning(ctypes.byref(tuning) if tuning is not None else None))
 
 

@@ -489,6 +489,8 @@ qsgs_status qsgs_set_tuning(const qsgs_tuning* t) {
     }
     if (t->steps_per_sync < 0 || t->steps_per_sync > 1024)
       return fail(QSGS_ERR_INVALID, "steps_per_sync must be in [0, 1024]");
+    if (t->graphs != 0 && t->graphs != 1) return fail(QSGS_ERR_INVALID, "graphs must be 0 or 1");
+    n.graphs = t->graphs != 0;
     n.grow_block = blocks[0];
     n.prune_block = blocks[1];
     n.seed_block = blocks[2];
@@ -512,6 +514,7 @@ void qsgs_get_tuning(qsgs_tuning* t) {
   t->seed_block = (int32_t)c.seed_block;
   t->seed_grid = (int32_t)c.seed_grid;
   t->steps_per_sync = c.steps_per_sync;
+  t->graphs = c.graphs ? 1 : 0;
 }
 
 void qsgs_profile_enable(int32_t enable) {

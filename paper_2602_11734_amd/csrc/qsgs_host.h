@@ -14,6 +14,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -321,6 +322,7 @@ struct Tuning {
   uint32_t prune_block = kBlock, prune_grid = 2048;
   uint32_t seed_block = kBlock, seed_grid = 2048;
   int32_t steps_per_sync = 0;  // 0: adaptive
+  bool graphs = true;          // passes as launches of captured chunk graphs
 };
 
 // Workgroups of k_sweep (block threads each) that the current device holds at once:
@@ -383,6 +385,40 @@ inline hipEvent_t prof_event() {
 inline void prof_release_all() {
   std::lock_guard<std::mutex> lk(prof().mu);
   prof().used = 0;
+}
+
+// ----- captured pass chunks -----
+// Executable graphs of captured chunks of passes, keyed by everything the passes launch
+// with (device, kernel arguments, launch shapes, kernel choice, chunk length).  A graph
+// is reused only by launches identical to the ones it captured.  Kept for the life of
+// the process; at most kMaxGraphs, later configurations launch their kernels directly.
+constexpr size_t kMaxGraphs = 64;
+struct GraphCache {
+  std::mutex mu;
+  std::map<std::string, hipGraphExec_t> exec;
+};
+inline GraphCache& graph_cache() {
+  static GraphCache c;
+  return c;
+}
+// The calling thread's capture stream on the current device (a graph is captured on it
+// and launched on the caller's stream, which may be the null stream).
+inline hipStream_t capture_stream() {
+  thread_local std::map<int, hipStream_t> streams;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  streams[dev] = cs;
+  return cs;
 }
 
 // ----- the engine -----
@@ -778,6 +814,101 @@ struct Engine {
     return QSGS_OK;
   }
 
+  // n passes.  With graphs on (and no timing events), as launches of captured chunk
+  // graphs of 16, 8, 4, 2 and 1 passes; otherwise every kernel launched on its own.
+  qsgs_status run_passes(uint32_t n, std::vector<hipEvent_t>* ev, bool tiles, bool field) {
+    if (ev || !tune.graphs || no_events) {
+      for (uint32_t k = 0; k < n; ++k) QSGS_TRY(sweep_pass(ev, tiles, field));
+      return QSGS_OK;
+    }
+    for (uint32_t k = 16; k > 0; k >>= 1) {
+      while (n >= k) {
+        hipGraphExec_t g = nullptr;
+        QSGS_TRY(chunk_graph(k, tiles, field, &g));
+        if (g) {
+          QSGS_HIP(hipGraphLaunch(g, s));
+        } else {
+          for (uint32_t i = 0; i < k; ++i) QSGS_TRY(sweep_pass(nullptr, tiles, field));
+        }
+        n -= k;
+      }
+    }
+    return QSGS_OK;
+  }
+
+  // The cached executable graph of k passes with the current launch configuration,
+  // captured on first use; *out = nullptr when no graph can be had (capture refused,
+  // cache full): the caller then launches the passes directly.
+  qsgs_status chunk_graph(uint32_t k, bool tiles, bool field, hipGraphExec_t* out) {
+    *out = nullptr;
+    bool walls = false, literal = false;
+    for (const Real& R : reals) {
+      walls = walls || R.walls != 0;
+      literal = literal || R.literal != 0;
+    }
+    int dev = 0;
+    QSGS_HIP(hipGetDevice(&dev));
+    const uint32_t cfg[10] = {(uint32_t)dev, k, sweep_grid, tune.grow_block,
+                              (uint32_t)sweep_lds_bytes(tune.grow_block), tune.seed_grid,
+                              tune.seed_block,
+                              (tiles ? 1u : 0u) | (field ? 2u : 0u) | (walls ? 4u : 0u) |
+                                  (literal ? 8u : 0u),
+                              (uint32_t)reals.size(), 0u};
+    std::string key(reinterpret_cast<const char*>(cfg), sizeof cfg);
+    key.append(reinterpret_cast<const char*>(&args), sizeof args);
+    GraphCache& C = graph_cache();
+    {
+      std::lock_guard<std::mutex> lk(C.mu);
+      auto it = C.exec.find(key);
+      if (it != C.exec.end()) {
+        *out = it->second;
+        return QSGS_OK;
+      }
+      if (C.exec.size() >= kMaxGraphs) return QSGS_OK;
+    }
+    hipStream_t cs = capture_stream();
+    if (!cs) return QSGS_OK;
+    const hipStream_t caller = s;
+    s = cs;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      s = caller;
+      (void)hipGetLastError();
+      return QSGS_OK;
+    }
+    qsgs_status st = QSGS_OK;
+    for (uint32_t i = 0; i < k && st == QSGS_OK; ++i) st = sweep_pass(nullptr, tiles, field);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    s = caller;
+    if (st != QSGS_OK || ec != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      last_error().clear();
+      return QSGS_OK;  // launch directly instead
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess || !ex) {
+      (void)hipGetLastError();
+      return QSGS_OK;
+    }
+    std::lock_guard<std::mutex> lk(C.mu);
+    auto it = C.exec.find(key);
+    if (it != C.exec.end()) {  // another thread captured the same chunk meanwhile
+      (void)hipGraphExecDestroy(ex);
+      *out = it->second;
+      return QSGS_OK;
+    }
+    if (C.exec.size() >= kMaxGraphs) {
+      (void)hipGraphExecDestroy(ex);  // never launched
+      return QSGS_OK;
+    }
+    C.exec.emplace(key, ex);
+    *out = ex;
+    return QSGS_OK;
+  }
+
   // Fused-sweep loop until every record has stopped.  A realization takes steps + 1
   // passes (the last one only prunes and folds).  For a single realization the chunk
   // length follows the remaining count over the last step's growth, plus the final pass
@@ -805,8 +936,7 @@ struct Engine {
         else if (c.step > 0)
           chunk = 4;
       }
-      for (uint32_t k = 0; k < chunk; ++k)
-        QSGS_TRY(sweep_pass(profiling ? &ev : nullptr, tiles, field));
+      QSGS_TRY(run_passes(chunk, profiling ? &ev : nullptr, tiles, field));
       QSGS_TRY(read_state());
     }
     if (profiling && !ev.empty()) {

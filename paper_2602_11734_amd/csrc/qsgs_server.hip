@@ -258,7 +258,7 @@ qsgs_status qsgs_server_tick(qsgs_server* S, int32_t* n_resident, int32_t* n_que
     for (size_t slot = 0; slot < live.size(); ++slot) live[slot] = S->slot_req[slot] >= 0;
     bool tiles = false, field = false;
     E.forms_in_use(&tiles, &field, &live);
-    for (uint64_t k = 0; k < passes; ++k) QSGS_TRY(E.sweep_pass(nullptr, tiles, field));
+    QSGS_TRY(E.run_passes((uint32_t)passes, nullptr, tiles, field));
     QSGS_TRY(E.export_grids());  // the requests that stopped: byte grids from their planes
   }
 
