@@ -199,6 +199,30 @@ qsgs_status qsgs_generate_batch(int32_t count, const qsgs_dims* dims, const qsgs
                                 uint8_t* const* d_grids, void* d_ws, size_t ws_bytes,
                                 qsgs_info* infos, void* stream);
 
+/* Whole generations that never synchronise with the host, for capture into a HIP graph
+ * (Sec. 2.3, the same loop as qsgs_generate / qsgs_generate_batch and bit-identical
+ * results): every transfer, launch and decision is enqueued on `stream` and the results
+ * land in device memory, so the whole call can be recorded once and replayed.
+ *   d_grid(s), d_ws, ws_bytes  as for qsgs_generate / qsgs_generate_batch (same sizes).
+ *   d_info(s)   device, 8-byte aligned, one qsgs_info per realization; written by the
+ *               last kernel of the call.  status is DONE, EXHAUSTED or MAXSTEPS, or
+ *               QSGS_ERR_DEVICE (an internal list overflow, or a seed spacing that had
+ *               not settled after 64 priority rounds, which qsgs_generate never limits).
+ *   params[r].max_steps  must be in [1, 4096]: without host reads the call runs exactly
+ *               max(max_steps) + 1 sweep passes (passes after a realization has stopped
+ *               find nothing to do and cost two short launches each).
+ * The per-step log is readable afterwards with qsgs_read_step_log as usual.  Graph-
+ * captured pass chunks (qsgs_tuning.graphs) and kernel timing are not used.  Returns
+ * QSGS_OK once everything is enqueued, or QSGS_ERR_INVALID / QSGS_ERR_WORKSPACE (nothing
+ * launched) / QSGS_ERR_DEVICE (a launch failed).  Does not synchronise `stream`. */
+qsgs_status qsgs_generate_async(const qsgs_dims* dims, const qsgs_params* params,
+                                uint8_t* d_grid, void* d_ws, size_t ws_bytes, qsgs_info* d_info,
+                                void* stream);
+qsgs_status qsgs_generate_batch_async(int32_t count, const qsgs_dims* dims,
+                                      const qsgs_params* params, uint8_t* const* d_grids,
+                                      void* d_ws, size_t ws_bytes, qsgs_info* d_infos,
+                                      void* stream);
+
 /* Multi-phase generation (Sec. 2.1 steps 1-5): growing phases 1..n_phases are generated
  * one after another on one label grid, each with its own parameters (core probability
  * seed_prob, target fraction P^n = solid_fraction of the whole domain, growth

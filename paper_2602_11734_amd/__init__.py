@@ -85,6 +85,9 @@ SIGNATURES = {
                                                         _VP, _SZ, _VP, _VP]),
     "qsgs_read_step_log": (_I64, [_VP, _SZ, _I32, _VP, _VP, _VP, _I64, _VP]),
     "qsgs_read_step_work": (_I64, [_VP, _SZ, _I32, _VP, _VP, _I64, _VP]),
+    "qsgs_generate_async": (ctypes.c_int, [_P(qsgs_dims), _P(qsgs_params), _VP, _VP, _SZ,
+                                           _VP, _VP]),
+    "qsgs_generate_batch_async": (ctypes.c_int, [_I32, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
     "qsgs_band_scratch_bytes": (_SZ, [_P(qsgs_dims)]),
     "qsgs_band_sizes": (ctypes.c_int, [_P(qsgs_dims), _VP, _VP, _VP, _SZ, _VP, _VP]),
     "qsgs_server_reserved_bytes": (_SZ, [_I32]),
@@ -243,6 +246,35 @@ def qsgs_read_step_work(ws, ws_bytes: int, index: int = 0, max_entries: int = 65
                                    blocks.ctypes.data, int(max_entries), _stream(stream))
     n = _check(int(n))
     return draws[:n].copy(), blocks[:n].copy()
+
+
+INFO_BYTES = ctypes.sizeof(qsgs_info)
+
+
+def qsgs_generate_async(dims, params: qsgs_params, grid, ws, ws_bytes: int, d_info,
+                        stream=None) -> None:
+    """Enqueues a whole generation without host synchronisation; d_info is a device
+    buffer of at least INFO_BYTES bytes (read it with info_from_device)."""
+    _check(load().qsgs_generate_async(ctypes.byref(make_dims(dims)), ctypes.byref(params),
+                                      _ptr(grid), _ptr(ws), int(ws_bytes), _ptr(d_info),
+                                      _stream(stream)))
+
+
+def qsgs_generate_batch_async(dims_list, params_list, grids, ws, ws_bytes: int, d_infos,
+                              stream=None) -> None:
+    n = len(dims_list)
+    d = (qsgs_dims * n)(*[make_dims(x) for x in dims_list])
+    p = (qsgs_params * n)(*params_list)
+    g = (ctypes.c_void_p * n)(*[_ptr(x) for x in grids])
+    _check(load().qsgs_generate_batch_async(n, d, p, g, _ptr(ws), int(ws_bytes), _ptr(d_infos),
+                                            _stream(stream)))
+
+
+def info_from_device(d_info, index: int = 0) -> qsgs_info:
+    """The qsgs_info at `index` of a device buffer written by the async calls (copies it
+    to the host; the caller synchronises first)."""
+    raw = bytes(d_info[index * INFO_BYTES:(index + 1) * INFO_BYTES].cpu().numpy().tobytes())
+    return qsgs_info.from_buffer_copy(raw)
 
 
 def qsgs_band_scratch_bytes(dims) -> int:

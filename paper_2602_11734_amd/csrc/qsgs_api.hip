@@ -62,21 +62,37 @@ qsgs_status make_specs(int32_t count, const qsgs_dims* dims, const qsgs_params* 
 // events are recorded.
 // itab (walls only, may be null): the interaction table of the phase being grown, with
 // ihi_max[c] the largest high half of its thresholds per class.
+// async: the call never synchronises with the host (graph capture): infos is device
+// memory, written by the last kernel; every params[r].max_steps is in [1, 4096] and the
+// loop runs max(max_steps) + 1 passes.
 qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_params* params,
                           uint8_t* const* grids, void* ws, size_t ws_bytes, qsgs_info* infos,
                           hipStream_t s, bool walls = false, bool no_alloc = false,
                           const InteractTable* itab = nullptr,
-                          const uint32_t* ihi_max = nullptr) {
+                          const uint32_t* ihi_max = nullptr, bool async = false) {
   std::vector<Spec> specs;
   QSGS_TRY(make_specs(count, dims, params, grids, &specs));
   if (!ws || !infos) return fail(QSGS_ERR_INVALID, "d_ws and info must not be NULL");
+  int32_t steps_cap = 0;
+  if (async) {
+    for (int32_t r = 0; r < count; ++r) {
+      if (params[r].max_steps < 1 || params[r].max_steps > kMaxAsyncSteps)
+        return fail(QSGS_ERR_INVALID, "the calls without host synchronisation need max_steps "
+                                      "in [1, %d] (realization %d has %d)",
+                    kMaxAsyncSteps, r, params[r].max_steps);
+      steps_cap = std::max(steps_cap, params[r].max_steps);
+    }
+    if (((uintptr_t)infos & 7u) != 0) return fail(QSGS_ERR_INVALID, "d_info not 8-byte aligned");
+  }
   const GenLayout G = gen_layout(specs, true, walls);
   if (ws_bytes < G.total)
     return fail(QSGS_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", G.total, ws_bytes);
   Engine E;
   E.bind(ws, G.P, (size_t)count, s);
-  E.no_events = no_alloc;
-  E.stage = no_alloc ? nullptr : thread_pinned_stage(Engine::stage_bytes((size_t)count));
+  E.no_events = no_alloc || async;
+  E.async = async;
+  E.stage = (no_alloc || async) ? nullptr
+                                : thread_pinned_stage(Engine::stage_bytes((size_t)count));
   std::vector<size_t> group;
   for (int32_t r = 0; r < count; ++r) {
     E.init_sweep_record((size_t)r, specs[r], &params[r], grids[r], at<void>(ws, G.sweep[r]),
@@ -92,7 +108,7 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
     }
   }
   E.attach_scratch(group, at<void>(ws, G.seed), G.S);
-  const bool profiling = prof_on() && !no_alloc;
+  const bool profiling = prof_on() && !no_alloc && !async;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (profiling) {
     prof_release_all();
@@ -105,6 +121,13 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
   QSGS_TRY(E.upload(0, E.reals.size()));
   QSGS_TRY(E.seed_core(at<void>(ws, G.seed), G.S));
   QSGS_TRY(E.sweep_start(group));
+  if (async) {
+    QSGS_TRY(E.run_sweep_fixed((uint32_t)steps_cap + 1u));
+    QSGS_TRY(E.export_grids());
+    hipLaunchKernelGGL(k_info_out, dim3((count + 255) / 256), dim3(256), 0, s, E.args, infos);
+    QSGS_LAUNCHED("k_info_out");
+    return QSGS_OK;
+  }
   if (profiling) QSGS_HIP(hipEventRecord(e1, s));
   QSGS_TRY(E.run_sweep_loop());
   QSGS_TRY(E.export_grids());
@@ -293,6 +316,23 @@ qsgs_status qsgs_generate(const qsgs_dims* dims, const qsgs_params* params, uint
                           void* d_ws, size_t ws_bytes, qsgs_info* info, void* stream) {
   last_error().clear();
   return generate_impl(1, dims, params, &d_grid, d_ws, ws_bytes, info, (hipStream_t)stream);
+}
+
+qsgs_status qsgs_generate_async(const qsgs_dims* dims, const qsgs_params* params,
+                                uint8_t* d_grid, void* d_ws, size_t ws_bytes, qsgs_info* d_info,
+                                void* stream) {
+  last_error().clear();
+  return generate_impl(1, dims, params, &d_grid, d_ws, ws_bytes, d_info, (hipStream_t)stream,
+                       false, false, nullptr, nullptr, true);
+}
+
+qsgs_status qsgs_generate_batch_async(int32_t count, const qsgs_dims* dims,
+                                      const qsgs_params* params, uint8_t* const* d_grids,
+                                      void* d_ws, size_t ws_bytes, qsgs_info* d_infos,
+                                      void* stream) {
+  last_error().clear();
+  return generate_impl(count, dims, params, d_grids, d_ws, ws_bytes, d_infos,
+                       (hipStream_t)stream, false, false, nullptr, nullptr, true);
 }
 
 qsgs_status qsgs_generate_batch(int32_t count, const qsgs_dims* dims, const qsgs_params* params,

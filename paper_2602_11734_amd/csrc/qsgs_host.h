@@ -328,10 +328,19 @@ struct Tuning {
 // Workgroups of k_sweep (block threads each) that the current device holds at once:
 // one round of them takes every list share at the same time, and no share waits for a
 // slot.  2048 when the runtime cannot say.
+// Computed once per device and block size (the later calls may be under graph capture).
 inline uint32_t resident_sweep_grid(uint32_t block) {
+  static std::mutex mu;
+  static std::map<std::pair<int, uint32_t>, uint32_t> known;
   int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 2048;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  const auto it = known.find({dev, block});
+  if (it != known.end()) return it->second;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<false, false>,
                                                    (int)block,
                                                    sweep_lds_bytes(block)) != hipSuccess ||
@@ -340,7 +349,9 @@ inline uint32_t resident_sweep_grid(uint32_t block) {
     return 2048;
   }
   const uint32_t n = (uint32_t)cus * (uint32_t)per_cu;
-  return std::max<uint32_t>(kNumXcd, n / kNumXcd * kNumXcd);
+  const uint32_t g = std::max<uint32_t>(kNumXcd, n / kNumXcd * kNumXcd);
+  known[{dev, block}] = g;
+  return g;
 }
 
 inline std::mutex& tuning_mu() {
@@ -432,6 +443,10 @@ struct Engine {
   WsHeader hdr{};
   uint32_t sweep_grid = 2048;
   bool no_events = false;  // the call may not allocate: no timing events
+  // the call never synchronises with the host (it may be captured into a graph): host
+  // data reaches the device as kernel arguments, the spacing rounds run a fixed number
+  // of times and the passes a fixed number of times
+  bool async = false;
   // pinned staging (see thread_pinned_stage): uploads, then readbacks, each in its own
   // region; nullptr for pageable copies
   char* stage = nullptr;
@@ -478,12 +493,31 @@ struct Engine {
   }
 
   // Control block, plan index and the zeroed tail counters: once per engine.
+  // n bytes of host data to device address dst: a copy, or (async) kernel arguments
+  qsgs_status put(void* dst, const void* src, size_t n) {
+    if (!async) {
+      QSGS_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s));
+      return QSGS_OK;
+    }
+    const size_t words = (n + 3) / 4;
+    for (size_t w0 = 0; w0 < words; w0 += 256) {
+      WordBlob b{};
+      b.n = (uint32_t)std::min<size_t>(256, words - w0);
+      std::memcpy(b.w, static_cast<const char*>(src) + 4 * w0,
+                  std::min<size_t>(4 * (size_t)b.n, n - 4 * w0));
+      hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, s,
+                         reinterpret_cast<uint32_t*>(static_cast<char*>(dst) + 4 * w0), b);
+      QSGS_LAUNCHED("k_put_words");
+    }
+    return QSGS_OK;
+  }
+
   qsgs_status upload_control() {
     BatchCtl b{};
     b.grid = sweep_grid;
     const void* src = &b;
     if (stage) src = std::memcpy(st_up_ctl(), &b, sizeof b);
-    QSGS_HIP(hipMemcpyAsync(args.bctl, src, sizeof b, hipMemcpyHostToDevice, s));
+    QSGS_TRY(put(args.bctl, src, sizeof b));
     // (fill kernels rather than memsets, so that the stream's work stays kernels and copies)
     const uint32_t n = (uint32_t)reals.size();
     hipLaunchKernelGGL(k_fill_u32, dim3((n + 256) / 256), dim3(256), 0, s, args.tailfill, 0u, n);
@@ -543,7 +577,7 @@ struct Engine {
     hdr = WsHeader{kMagic, (uint32_t)reals.size(), P.log_cap, P.reals, P.logs};
     const void* src = &hdr;
     if (stage) src = std::memcpy(st_up_hdr(), &hdr, sizeof hdr);
-    QSGS_HIP(hipMemcpyAsync(at<void>(ws, P.hdr), src, sizeof hdr, hipMemcpyHostToDevice, s));
+    QSGS_TRY(put(at<void>(ws, P.hdr), src, sizeof hdr));
     return QSGS_OK;
   }
 
@@ -553,7 +587,7 @@ struct Engine {
     if (stage)
       src = std::memcpy(st_up_reals() + sizeof(Real) * first, reals.data() + first,
                         sizeof(Real) * n);
-    QSGS_HIP(hipMemcpyAsync(args.reals + first, src, sizeof(Real) * n, hipMemcpyHostToDevice, s));
+    QSGS_TRY(put(args.reals + first, src, sizeof(Real) * n));
     return QSGS_OK;
   }
 
@@ -617,7 +651,18 @@ struct Engine {
     }
     hipLaunchKernelGGL(k_bucket_scatter, sg, sb, 0, s, args, tb);
     QSGS_LAUNCHED("k_bucket_scatter");
-    if (tb > 0) {
+    if (tb > 0 && async) {  // a fixed number of rounds, checked on the device
+      for (uint32_t round = 0; round < kAsyncRounds; ++round) {
+        hipLaunchKernelGGL(k_luby_round, sg, sb, 0, s, args, round);
+        QSGS_LAUNCHED("k_luby_round");
+        hipLaunchKernelGGL(k_luby_kill, sg, sb, 0, s, args);
+        QSGS_LAUNCHED("k_luby_kill");
+      }
+      hipLaunchKernelGGL(k_seed_settled, dim3(1), dim3(256), 0, s, args, kAsyncRounds);
+      QSGS_LAUNCHED("k_seed_settled");
+      hipLaunchKernelGGL(k_collect_seeds, sg, sb, 0, s, args);
+      QSGS_LAUNCHED("k_collect_seeds");
+    } else if (tb > 0) {
       uint32_t round = 0;
       for (;;) {
         for (uint32_t k = 0; k < kRoundsPerCheck; ++k, ++round) {
@@ -906,6 +951,15 @@ struct Engine {
     }
     C.exec.emplace(key, ex);
     *out = ex;
+    return QSGS_OK;
+  }
+
+  // The sweep loop without host reads: `passes` passes (those after every record has
+  // stopped find nothing to do), launched one by one.
+  qsgs_status run_sweep_fixed(uint32_t passes) {
+    bool tiles = false, field = false;
+    forms_in_use(&tiles, &field);
+    for (uint32_t k = 0; k < passes; ++k) QSGS_TRY(sweep_pass(nullptr, tiles, field));
     return QSGS_OK;
   }
 

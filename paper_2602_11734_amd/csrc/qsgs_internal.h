@@ -7,6 +7,7 @@
 // multiple of the wavefront size, so every wavefront serves one realization.
 #pragma once
 
+#include "qsgs.h"
 #include "qsgs_device.h"
 
 namespace qsgs {
@@ -94,6 +95,8 @@ constexpr uint32_t kMaxSweepGrid = 8192;  // workgroups of a fused sweep launch 
 constexpr uint32_t kMaxBatch = 4096;      // realizations per batch / server slots
 constexpr int kScanBlock = 1024;       // items per workgroup of the bucket scan
 constexpr uint32_t kMaxRounds = 4096;  // spacing rounds (a safety cap; typical runs use < 40)
+constexpr uint32_t kAsyncRounds = 64;  // spacing rounds of the calls without host checks
+constexpr int32_t kMaxAsyncSteps = 4096;  // step cap of the calls without host checks
 
 // Loop state of one realization, carried between kernels.
 struct Ctl {
@@ -265,6 +268,14 @@ __global__ void k_sweep_prepare(BatchArgs A);
 __global__ void k_pack_planes(BatchArgs A);
 __global__ void k_export_planes(BatchArgs A);
 __global__ void k_export_done(BatchArgs A);
+// up to 256 words of host data carried in kernel arguments
+struct WordBlob {
+  uint32_t n;
+  uint32_t w[256];
+};
+__global__ void k_put_words(uint32_t* dst, WordBlob b);
+__global__ void k_seed_settled(BatchArgs A, uint32_t rounds);
+__global__ void k_info_out(BatchArgs A, qsgs_info* out);
 __global__ void k_field_step(BatchArgs A);
 __global__ void k_field_fold(BatchArgs A);
 __global__ void k_field_end(BatchArgs A, uint32_t reset_running);

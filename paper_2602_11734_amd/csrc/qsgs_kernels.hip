@@ -1199,6 +1199,38 @@ __global__ __launch_bounds__(kMaxBlock) void k_export_planes(BatchArgs A) {
   });
 }
 
+// ----- calls that never synchronise with the host (graph capture) -----
+
+// Host data carried by value in the kernel arguments: a copy node would read host memory
+// when a captured graph is replayed, a kernel argument is part of the graph.
+__global__ void k_put_words(uint32_t* __restrict__ dst, WordBlob b) {
+  for (uint32_t i = threadIdx.x; i < b.n; i += blockDim.x) dst[i] = b.w[i];
+}
+
+// After a fixed number of spacing rounds: if candidates are still undecided, every
+// realization of the call fails (its loop state reports an internal error).
+__global__ void k_seed_settled(BatchArgs A, uint32_t rounds) {
+  if (rounds == 0 || A.live[rounds - 1] == 0) return;
+  for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) A.reals[r].ctl.overflow = 1u;
+}
+
+// Each realization's loop state as a qsgs_info in device memory.
+__global__ void k_info_out(BatchArgs A, qsgs_info* __restrict__ out) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= A.count) return;
+  const Ctl& c = A.reals[r].ctl;
+  qsgs_info i;
+  i.n_candidates = c.n_cand;
+  i.n_seeds = c.n_seeds;
+  i.solid_count = (int64_t)c.cnt;
+  i.target_count = (int64_t)c.s_star;
+  i.front_size = c.front_size;
+  i.grown_last_step = c.last_new;
+  i.step = c.step;
+  i.status = (c.status == kStatusOverflow || c.bad_entry) ? (int32_t)QSGS_ERR_DEVICE : c.status;
+  out[r] = i;
+}
+
 // The grids of the realizations exported by the last k_export_planes are written.
 __global__ void k_export_done(BatchArgs A) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;

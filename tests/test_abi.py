@@ -247,3 +247,22 @@ def test_band_sizes_arguments_checked(q):
     assert lib.qsgs_band_sizes(d, 256, 256, 516, sb, out, None) == q.ERR_INVALID  # alignment
     bad = ctypes.byref(q.make_dims((0, 1, 1)))
     assert lib.qsgs_band_sizes(bad, 256, 256, 512, sb, out, None) == q.ERR_INVALID
+
+
+def test_async_arguments_checked(q):
+    """The calls without host synchronisation: a step cap outside [1, 4096], a NULL or
+    misaligned info, a short workspace: errors before any launch."""
+    lib = q.load()
+    d = ctypes.byref(q.make_dims((8, 8, 8)))
+    for steps in (0, -1, 4097):
+        p = q.make_params(0.7, 0.01, (0.1, 0.05, 0.01), 3, 1, max_steps=steps)
+        assert lib.qsgs_generate_async(d, ctypes.byref(p), 256, 256, 1 << 20, 1024,
+                                       None) == q.ERR_INVALID
+        assert "max_steps" in q.qsgs_last_error()
+    p = q.make_params(0.7, 0.01, (0.1, 0.05, 0.01), 3, 1, max_steps=10)
+    assert lib.qsgs_generate_async(d, ctypes.byref(p), 256, 256, 1 << 20, None,
+                                   None) == q.ERR_INVALID
+    assert lib.qsgs_generate_async(d, ctypes.byref(p), 256, 256, 1 << 20, 1028,
+                                   None) == q.ERR_INVALID  # misaligned info
+    assert lib.qsgs_generate_async(d, ctypes.byref(p), 256, 256, 16, 1024,
+                                   None) == q.ERR_WORKSPACE
