@@ -447,11 +447,16 @@ def main():
                     help="skip the list-indexed vs full-field comparison")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched vs plain realizations/s measurement")
+    ap.add_argument("--no-bands", action="store_true",
+                    help="skip the step-API runs that measure the band sizes (the algorithmic "
+                         "bytes then leave out the band terms; for profiled runs)")
     ap.add_argument("--no-phases", action="store_true",
                     help="skip the three-phase 400^3 generation")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the served vs plain request-stream measurement")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--alu-calibration", action="store_true",
+                    help="only measure the 32-bit vector ALU issue rate (1..8 waves per SIMD)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy kernel over BYTES bytes three times "
                          "(the reference kernel for scaling HBM byte counters)")
@@ -465,7 +470,7 @@ def main():
 
     # the CPU leg first, before anything touches the GPU (its workers are forks)
     cpu = None
-    if not args.no_cpu_baseline and not args.copy_calibration:
+    if not args.no_cpu_baseline and not args.copy_calibration and not args.alu_calibration:
         cpu = cpu_baseline(workloads.config3(), edge=args.cpu_edge)
 
     import torch
@@ -477,6 +482,12 @@ def main():
         build.build_library()
     q.load()
     torch.cuda.set_device(0)
+    if args.alu_calibration:
+        rates = {w: q.qsgs_alu_rate(w) / 1e12 for w in range(1, 9)}
+        print(json.dumps({"alu_lane_ops_per_s_T_by_waves_per_simd": rates,
+                          "peak_T": ALU_PEAK_TOPS,
+                          "best_frac_of_peak": max(rates.values()) / ALU_PEAK_TOPS}))
+        return
     if args.copy_calibration:
         # an elementwise kernel that reads and writes BYTES bytes (a DMA copy would
         # not show up as a kernel dispatch)
@@ -527,7 +538,8 @@ def main():
     ops = [sweep_pass_ops(lg[0], lg[3], lg[4], info["front_size"]) for _, info, lg in runs]
     launches = sum(len(x) for x in ops)
     assert launches == int(prof["grow_launches"]), (launches, prof)
-    bands = {c.name: step_api_bands(q, torch, c) for c in cases}
+    bands = ({c.name: step_api_bands(q, torch, c) for c in cases} if not args.no_bands else
+             {name: ([0] * len(lg[0]), [0] * len(lg[0])) for name, _, lg in runs})
     sbytes = 0.0
     for name, info, lg in runs:
         bf, bu = bands[name]
@@ -539,6 +551,9 @@ def main():
     sweep_tops = (sops / launches) / sweep_s / 1e12 if launches else 0.0
     sweep_gbs = (sbytes / launches) / sweep_s / 1e9 if launches else 0.0
     traffic = measured_traffic(launches_per_step=launches / args.steps)
+    # the issue rate of plain 32-bit ALU instructions measured on this device (five waves
+    # per SIMD, the sweep's occupancy), beside the peak derived from the unit counts
+    alu_measured = q.qsgs_alu_rate(5) / 1e12
 
     per_case = {}
     for name, info, lg in runs:
@@ -566,6 +581,7 @@ def main():
                                "one step = the three generations end to end",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": sweep_tops, "peak": ALU_PEAK_TOPS,
+                     "peak_measured_issue": alu_measured,
                      "unit": "Tops/s (int32)", "frac": sweep_tops / ALU_PEAK_TOPS,
                      "traffic": traffic, "kernel": "k_sweep",
                      "avg_launch_ms": sweep_avg_ms, "launches": launches,
@@ -574,6 +590,7 @@ def main():
                                          "unit": "GB/s", "frac": sweep_gbs / HBM_PEAK_GBS,
                                          "bytes_per_launch": sbytes / max(launches, 1),
                                          "occupancy_bytes_per_cell": OCC_BYTES,
+                                         "band_terms": not args.no_bands,
                                          "band_cells": {k: [sum(v[0]), sum(v[1])]
                                                         for k, v in bands.items()}}},
         "detail": {"sweep_ms_total": prof["grow_ms"], "seed_ms_total": prof["seed_ms"],

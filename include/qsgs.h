@@ -375,6 +375,16 @@ qsgs_status qsgs_band_sizes(const qsgs_dims* dims, const uint8_t* d_before,
                             const uint8_t* d_after, void* d_scratch, size_t scratch_bytes,
                             uint64_t* out, void* stream);
 
+/* Measured issue rate of plain 32-bit vector ALU instructions on the current device, for
+ * the ALU roof of the growth sweep (a measurement utility): eight independent chains of
+ * xor / add per lane, waves_per_simd (1..8) wavefronts per SIMD on every compute unit,
+ * best of two timed runs after a warm-up.  *lane_ops_per_s receives the 32-bit lane
+ * operations per second.  d_scratch: device, >= qsgs_alu_scratch_bytes(waves_per_simd)
+ * bytes (0 for a bad argument).  Synchronises `stream`. */
+size_t qsgs_alu_scratch_bytes(int32_t waves_per_simd);
+qsgs_status qsgs_alu_rate(int32_t waves_per_simd, void* d_scratch, size_t scratch_bytes,
+                          double* lane_ops_per_s, void* stream);
+
 /* Kernel timing for measurement.  While enabled (enable != 0), qsgs_generate records HIP
  * events around each growth-sweep and prune launch on its stream and accumulates their
  * durations; qsgs_profile_read returns (and with reset != 0 clears) the totals:

@@ -89,6 +89,8 @@ SIGNATURES = {
                                            _VP, _VP]),
     "qsgs_generate_batch_async": (ctypes.c_int, [_I32, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
     "qsgs_band_scratch_bytes": (_SZ, [_P(qsgs_dims)]),
+    "qsgs_alu_scratch_bytes": (_SZ, [_I32]),
+    "qsgs_alu_rate": (ctypes.c_int, [_I32, _VP, _SZ, _P(ctypes.c_double), _VP]),
     "qsgs_band_sizes": (ctypes.c_int, [_P(qsgs_dims), _VP, _VP, _VP, _SZ, _VP, _VP]),
     "qsgs_server_reserved_bytes": (_SZ, [_I32]),
     "qsgs_server_create": (ctypes.c_int, [_VP, _SZ, _I32, _I32, _VP, _P(_VP)]),
@@ -275,6 +277,19 @@ def info_from_device(d_info, index: int = 0) -> qsgs_info:
     to the host; the caller synchronises first)."""
     raw = bytes(d_info[index * INFO_BYTES:(index + 1) * INFO_BYTES].cpu().numpy().tobytes())
     return qsgs_info.from_buffer_copy(raw)
+
+
+def qsgs_alu_rate(waves_per_simd: int = 8, stream=None) -> float:
+    """32-bit vector ALU lane operations per second measured on the current device."""
+    import torch
+    n = int(load().qsgs_alu_scratch_bytes(int(waves_per_simd)))
+    if n == 0:
+        raise QsgsError(ERR_INVALID, "waves_per_simd must be in [1, 8]")
+    scratch = torch.empty(n, dtype=torch.uint8, device="cuda")
+    out = ctypes.c_double()
+    _check(load().qsgs_alu_rate(int(waves_per_simd), _ptr(scratch), n, ctypes.byref(out),
+                                _stream(stream)))
+    return out.value
 
 
 def qsgs_band_scratch_bytes(dims) -> int:

@@ -1,5 +1,8 @@
-// qsgs_measure.hip -- the occupancy one growth step reads, for the algorithmic byte count
-// of a step (C ABI qsgs_band_sizes in include/qsgs.h).  A step tests the 26 neighbours
+// qsgs_measure.hip -- measurement utilities (C ABI in include/qsgs.h): the occupancy one
+// growth step reads, and the issue rate of plain 32-bit vector ALU instructions.
+//
+// Band sizes (qsgs_band_sizes), for the algorithmic byte count of a step: a step tests the
+// 26 neighbours
 // of every front voxel a in F_t (Sec. 2.3 step 3) and then keeps the voxels of
 // F_t u New_t that still have a void neighbour (Sec. 2.3 step 4), so it reads the
 // occupancy of the one-voxel band (Chebyshev distance <= 1) around F_t, then around
@@ -101,6 +104,28 @@ __global__ void k_band_zero(unsigned long long* out) {
 
 size_t band_counter_offset(uint32_t n) { return align_up((size_t)n); }
 
+// Issue rate of plain 32-bit vector ALU instructions: eight independent chains of
+// v_xor_b32 / v_add_u32 per lane (written in assembly so that every instruction stays),
+// 16 instructions per iteration; one 32-bit result per thread keeps the chains live.
+constexpr uint32_t kAluIters = 20000;
+__global__ __launch_bounds__(256) void k_alu_rate(uint32_t* __restrict__ out, uint32_t seed) {
+  uint32_t a0 = threadIdx.x ^ seed, a1 = a0 + 1u, a2 = a0 + 2u, a3 = a0 + 3u, a4 = a0 + 4u,
+           a5 = a0 + 5u, a6 = a0 + 6u, a7 = a0 + 7u;
+  const uint32_t b = seed * 3u + 1u;
+  for (uint32_t i = 0; i < kAluIters; ++i) {
+    asm volatile(
+        "v_xor_b32 %0, %0, %8\n v_add_u32 %1, %1, %8\n v_xor_b32 %2, %2, %8\n"
+        " v_add_u32 %3, %3, %8\n v_xor_b32 %4, %4, %8\n v_add_u32 %5, %5, %8\n"
+        " v_xor_b32 %6, %6, %8\n v_add_u32 %7, %7, %8\n"
+        " v_add_u32 %0, %0, %8\n v_xor_b32 %1, %1, %8\n v_add_u32 %2, %2, %8\n"
+        " v_xor_b32 %3, %3, %8\n v_add_u32 %4, %4, %8\n v_xor_b32 %5, %5, %8\n"
+        " v_add_u32 %6, %6, %8\n v_xor_b32 %7, %7, %8"
+        : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
+        : "v"(b));
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
+}
+
 }  // namespace
 
 extern "C" {
@@ -139,6 +164,47 @@ qsgs_status qsgs_band_sizes(const qsgs_dims* dims, const uint8_t* d_before,
   QSGS_HIP(hipStreamSynchronize(s));
   out[0] = h[0];
   out[1] = h[1];
+  return QSGS_OK;
+}
+
+size_t qsgs_alu_scratch_bytes(int32_t waves_per_simd) {
+  int dev = 0, cus = 0;
+  if (waves_per_simd < 1 || waves_per_simd > 8 || hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return sizeof(uint32_t) * 256 * (size_t)cus * (size_t)waves_per_simd;
+}
+
+qsgs_status qsgs_alu_rate(int32_t waves_per_simd, void* d_scratch, size_t scratch_bytes,
+                          double* lane_ops_per_s, void* stream) {
+  last_error().clear();
+  if (!d_scratch || !lane_ops_per_s) return fail(QSGS_ERR_INVALID, "NULL pointer argument");
+  const size_t need = qsgs_alu_scratch_bytes(waves_per_simd);
+  if (need == 0) return fail(QSGS_ERR_INVALID, "waves_per_simd must be in [1, 8]");
+  if (scratch_bytes < need)
+    return fail(QSGS_ERR_WORKSPACE, "scratch needs %zu bytes, got %zu", need, scratch_bytes);
+  const uint32_t blocks = (uint32_t)(need / (sizeof(uint32_t) * 256));  // 4 waves each
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  QSGS_HIP(hipEventCreate(&e0));
+  QSGS_HIP(hipEventCreate(&e1));
+  float best = 0.f;
+  for (int rep = 0; rep < 3; ++rep) {
+    QSGS_HIP(hipEventRecord(e0, s));
+    hipLaunchKernelGGL(k_alu_rate, dim3(blocks), dim3(256), 0, s, (uint32_t*)d_scratch, 7u);
+    QSGS_LAUNCHED("k_alu_rate");
+    QSGS_HIP(hipEventRecord(e1, s));
+    QSGS_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    QSGS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (rep > 0 && (best == 0.f || ms < best)) best = ms;  // the first run warms up
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *lane_ops_per_s = (double)blocks * 256.0 * 16.0 * kAluIters / (best * 1e-3);
   return QSGS_OK;
 }
 

@@ -80,7 +80,7 @@ def serve_stream(requests, arena_bytes: int, max_slots: int = 64, steps_per_tick
             max_res = max(max_res, resident)
             if nready:
                 t_done = time.perf_counter() - t0
-                for rid, info in qsgs_server_ready(srv):
+                for rid, info in qsgs_server_ready(srv, nready):
                     if info.status < 0:  # failed: nothing to copy out
                         qsgs_server_take(srv, rid, None, check=False)
                         failed.append(rid)

@@ -89,3 +89,11 @@ def test_band_sizes_of_hand_made_grids(q):
     # an all-solid grid has no front
     full = torch.ones_like(before)
     assert q.qsgs_band_sizes(dims, full[:n].contiguous(), full, scratch, sb) == (0, 0)
+
+
+def test_alu_rate_is_plausible(q):
+    """The measured 32-bit ALU issue rate: positive, below the chip's unit-count peak
+    (256 compute units x 128 lanes x 2.4 GHz), rising with waves per SIMD."""
+    peak = 256 * 128 * 2.4e9
+    r1, r8 = q.qsgs_alu_rate(1), q.qsgs_alu_rate(8)
+    assert 0 < r1 < r8 <= 1.05 * peak
