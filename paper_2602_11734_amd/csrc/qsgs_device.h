@@ -80,38 +80,72 @@ __device__ __forceinline__ int dir_field(uint64_t table, int d) {
 }
 
 // Eq. (1) in integers: floor(t_ref * (20 S* - 19 cnt) / S*) capped at 2^32, for
-// cnt < S* < 2^31.  The product can reach 2^68, so it is formed in two 64-bit
-// pieces and divided by long division (one thread per step evaluates this).
+// cnt < S* < 2^31.  The product can reach 2^68: the quotient is estimated in double
+// precision (a relative error of at most 2^-52, so within 2^-19 of the exact quotient
+// while that is below 2^32 + 3) and its floor corrected once by the exact remainder,
+// which is formed modulo 2^64 (it lies in (-S*, 2 S*), far inside the signed range).
 __device__ __forceinline__ uint64_t eq1_threshold(uint64_t t_ref, uint64_t cnt, uint64_t s_star) {
   if (t_ref == 0) return 0;
   if (t_ref >= kOne32) return kOne32;  // factor >= 1 keeps probability 1
-  const uint64_t num = 20ull * s_star - 19ull * cnt;      // < 2^36
-  const uint64_t lo_prod = t_ref * (num & 0xFFFFFFFFull);  // < 2^64
-  const uint64_t p_hi = (lo_prod >> 32) + t_ref * (num >> 32);
-  const uint64_t p_lo = lo_prod & 0xFFFFFFFFull;
-  const uint64_t q_hi = p_hi / s_star;
-  const uint64_t r = p_hi % s_star;                        // < 2^31
-  if (q_hi != 0) return kOne32;                            // quotient >= 2^32
-  const uint64_t q_lo = ((r << 32) | p_lo) / s_star;       // < 2^32
-  return q_lo;
+  const uint64_t num = 20ull * s_star - 19ull * cnt;  // < 2^36
+  const double qd = (double)t_ref * (double)num / (double)s_star;
+  if (qd >= 4294967298.0) return kOne32;  // 2^32 + 2: the quotient is at least 2^32
+  uint64_t q = (uint64_t)qd;
+  const int64_t rem = (int64_t)(t_ref * num - q * s_star);
+  if (rem < 0)
+    --q;
+  else if (rem >= (int64_t)s_star)
+    ++q;
+  return q >= kOne32 ? kOne32 : q;
+}
+
+// floor(x / y) for x < 2^53 and y > 0: the correctly rounded double quotient lies
+// within x 2^-53 / y < 1 / y of x / y, closer than the next integer whenever x / y is
+// not one, so its floor is exact.
+__device__ __forceinline__ uint32_t floor_div53(uint64_t x, uint64_t y) {
+  return (uint32_t)((double)x / (double)y);
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Cross-lane steps through DPP: an operand read from another lane of the same row of
+// 16 lanes (row_shr), or the last lane of a row broadcast into later rows (row_bcast),
+// a few cycles each where a shuffle through the LDS crossbar takes tens.  Lanes with
+// no source read 0.  Every lane of the wavefront must be active.
+template <int kCtrl, int kRowMask = 0xF>
+__device__ __forceinline__ uint32_t dpp_take(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xF, true);
+}
+
+// Inclusive prefix sum (lane i: v_0 + ... + v_i) and prefix or over the wavefront.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+  v += dpp_take<0x111>(v);       // row_shr:1
+  v += dpp_take<0x112>(v);       // row_shr:2
+  v += dpp_take<0x114>(v);       // row_shr:4
+  v += dpp_take<0x118>(v);       // row_shr:8: prefixes within each row
+  v += dpp_take<0x142, 0xA>(v);  // row_bcast:15: row 0's total into row 1, row 2's into row 3
+  v += dpp_take<0x143, 0xC>(v);  // row_bcast:31: the total of rows 0-1 into rows 2 and 3
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_incl_or(uint32_t v) {
+  v |= dpp_take<0x111>(v);
+  v |= dpp_take<0x112>(v);
+  v |= dpp_take<0x114>(v);
+  v |= dpp_take<0x118>(v);
+  v |= dpp_take<0x142, 0xA>(v);
+  v |= dpp_take<0x143, 0xC>(v);
+  return v;
+}
 
 // Wave-wide exclusive prefix sum of `cnt` plus one atomicAdd per wave on *counter;
 // returns this lane's first slot.  Every lane of the wave must call it.
 __device__ __forceinline__ uint32_t wave_append(uint32_t cnt, uint32_t* counter) {
   const uint32_t lane = lane_id();
-  uint32_t incl = cnt;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const uint32_t v = __shfl_up(incl, off, kWave);
-    if (lane >= (uint32_t)off) incl += v;
-  }
-  const uint32_t total = __shfl(incl, kWave - 1, kWave);
+  const uint32_t incl = wave_incl_sum(cnt);
+  const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
   uint32_t base = 0;
   if (lane == kWave - 1 && total != 0) base = atomicAdd(counter, total);
-  base = __shfl(base, kWave - 1, kWave);
+  base = __builtin_amdgcn_readlane(base, kWave - 1);
   return base + incl - cnt;
 }
 

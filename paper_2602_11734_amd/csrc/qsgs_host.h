@@ -215,7 +215,7 @@ struct WsHeader {
 struct PersistLayout {
   size_t hdr = 0, bctl = 0, reals = 0, off = 0, live = 0, logs = 0, total = 0;
   size_t seg[2] = {0, 0}, segchunk[2] = {0, 0}, rseg[2] = {0, 0}, wgoff[2] = {0, 0};
-  size_t wgkept = 0, wggrown = 0, wgdraws = 0, wgblocks = 0, tailfill = 0;
+  size_t rec = 0, desc = 0, tailfill = 0;
   uint32_t log_cap = 0, seg_cap = 0;
 };
 
@@ -241,10 +241,8 @@ inline PersistLayout persist_layout(size_t count, uint32_t log_cap) {
     L.rseg[q] = take(sizeof(uint32_t) * (count + 1));
     L.wgoff[q] = take(sizeof(uint32_t) * (count + 1));
   }
-  L.wgkept = take(sizeof(uint32_t) * kMaxSweepGrid);
-  L.wggrown = take(sizeof(uint32_t) * kMaxSweepGrid);
-  L.wgdraws = take(sizeof(uint32_t) * kMaxSweepGrid);
-  L.wgblocks = take(sizeof(uint32_t) * kMaxSweepGrid);
+  L.rec = take(sizeof(WgRec) * kMaxSweepGrid);
+  L.desc = take(sizeof(WgDesc) * kMaxSweepGrid);
   L.tailfill = take(sizeof(uint32_t) * count);
   L.total = off;
   return L;
@@ -482,14 +480,13 @@ struct Engine {
       args.plan[q].wgoff = at<uint32_t>(base, L.wgoff[q]);
     }
     args.seg_cap = L.seg_cap;
-    args.wgkept = at<uint32_t>(base, L.wgkept);
-    args.wggrown = at<uint32_t>(base, L.wggrown);
-    args.wgdraws = at<uint32_t>(base, L.wgdraws);
-    args.wgblocks = at<uint32_t>(base, L.wgblocks);
+    args.rec = at<WgRec>(base, L.rec);
+    args.desc = at<WgDesc>(base, L.desc);
     args.tailfill = at<uint32_t>(base, L.tailfill);
     const uint32_t g = tune.grow_grid ? tune.grow_grid : resident_sweep_grid(tune.grow_block);
     const uint32_t want = std::max<uint32_t>(g, 2 * (uint32_t)count);
     sweep_grid = std::min<uint32_t>(kMaxSweepGrid, (want + kNumXcd - 1) / kNumXcd * kNumXcd);
+    args.sweep_grid = sweep_grid;
   }
 
   // Control block, plan index and the zeroed tail counters: once per engine.

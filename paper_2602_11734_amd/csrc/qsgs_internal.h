@@ -183,7 +183,8 @@ struct BatchCtl {
   uint32_t blocks_done; // workgroups of the current sweep that have finished
   uint32_t plan;        // which of the two sweep plans is the input of the next pass
   uint32_t grid;        // workgroups of every fused sweep launch
-  uint32_t pad[3];
+  uint32_t nwg;         // workgroups with a share in the current plan
+  uint32_t pad[2];
 };
 
 // Fused-sweep tile lists are read through a segment table: segment = a contiguous run
@@ -196,6 +197,31 @@ struct BatchCtl {
 // of a pass holds, per realization, its G_r parts and then its tail.
 struct SegEntry {
   uint32_t r, base, fill, pad;
+};
+
+// What one logical workgroup of a fused pass found and listed (written by the workgroup
+// at its end, summed per realization by k_sweep_end).
+struct WgRec {
+  uint32_t r;        // realization
+  uint32_t fill;     // entries in its part of the next list
+  uint32_t kept;     // front voxels found
+  uint32_t grown;    // voxels grown
+  uint32_t draws;    // draws made
+  uint32_t blocks;   // high-half Philox blocks computed
+  uint32_t pad[2];
+};
+
+// The share of one logical workgroup in the next fused pass, written with the plan so
+// that the workgroup starts from a single load.
+constexpr uint32_t kNoReal = 0xFFFFFFFFu;
+struct WgDesc {
+  uint32_t r;          // realization, or kNoReal: no share in this pass
+  uint32_t k;          // index among the realization's G_r workgroups
+  uint32_t e_lo, e_hi; // its entries [e_lo, e_hi) of the plan's entry prefix
+  uint32_t sgi;        // segment of entry e_lo: the last s with segchunk[s] <= e_lo
+  uint32_t se;         // end of the realization's segments in the table
+  uint32_t part_base;  // its part of the first half of the next list buffer
+  uint32_t part_cap;
 };
 
 // One sweep plan: an input segment table with its entry prefix, the realization
@@ -237,10 +263,9 @@ struct BatchArgs {
   // fused sweep
   SweepPlan plan[2];
   uint32_t seg_cap;     // entries of each segment table
-  uint32_t* wgkept;     // front voxels found per logical workgroup of the current pass
-  uint32_t* wggrown;    // voxels grown per logical workgroup of the current pass
-  uint32_t* wgdraws;    // draws per logical workgroup of the current pass
-  uint32_t* wgblocks;   // high-half Philox blocks per logical workgroup of the current pass
+  uint32_t sweep_grid;  // workgroups of every fused sweep launch (a multiple of 8)
+  WgRec* rec;           // per logical workgroup of the current pass (kMaxSweepGrid)
+  WgDesc* desc;         // per logical workgroup of the next pass (kMaxSweepGrid)
   uint32_t* tailfill;   // per realization: entries spilled into the tail half
 };
 

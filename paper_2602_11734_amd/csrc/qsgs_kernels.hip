@@ -234,22 +234,12 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(uint32_t* data, uint3
   const uint32_t i = blockIdx.x * kScanBlock + threadIdx.x;
   const uint32_t v = i < n ? data[i] : 0u;
   const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
-  uint32_t incl = v;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const uint32_t t = __shfl_up(incl, off, kWave);
-    if (lane >= (uint32_t)off) incl += t;
-  }
+  const uint32_t incl = wave_incl_sum(v);
   if (lane == kWave - 1) wave_tot[wv] = incl;
   __syncthreads();
   if (wv == 0) {
     const uint32_t t = lane < kScanBlock / kWave ? wave_tot[lane] : 0u;
-    uint32_t ti = t;
-#pragma unroll
-    for (int off = 1; off < kScanBlock / kWave; off <<= 1) {
-      const uint32_t u = __shfl_up(ti, off, kWave);
-      if (lane >= (uint32_t)off) ti += u;
-    }
+    const uint32_t ti = wave_incl_sum(t);
     if (lane < kScanBlock / kWave) wave_tot[lane] = ti - t;  // exclusive wave offsets
     if (lane == kScanBlock / kWave - 1) sums[blockIdx.x] = ti;
   }
@@ -265,14 +255,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(uint32_t* data, uint32_
 
 // Wave-wide exclusive prefix of cnt; *total receives the wave's sum.
 __device__ __forceinline__ uint32_t wave_prefix(uint32_t cnt, uint32_t* total) {
-  const uint32_t lane = lane_id();
-  uint32_t incl = cnt;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const uint32_t v = __shfl_up(incl, off, kWave);
-    if (lane >= (uint32_t)off) incl += v;
-  }
-  *total = __shfl(incl, kWave - 1, kWave);
+  const uint32_t incl = wave_incl_sum(cnt);
+  *total = __builtin_amdgcn_readlane(incl, kWave - 1);
   return incl - cnt;
 }
 
@@ -1004,16 +988,17 @@ __global__ __launch_bounds__(kBlock) void k_rollback(uint8_t* grid, uint32_t n) 
 // and builds the next plan.
 // ---------------------------------------------------------------------------
 
-// Bitwise or / sum of a value over the 64 lanes of the wavefront (every lane gets it).
+// Bitwise or / sum of a value over the 64 lanes of the wavefront (every lane gets it;
+// every lane must be active).  The 64-bit sum adds the low and high 16-bit halves apart.
 __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
-  return v;
+  return __builtin_amdgcn_readlane(wave_incl_or(v), kWave - 1);
 }
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  return __builtin_amdgcn_readlane(wave_incl_sum(v), kWave - 1);
+}
+__device__ __forceinline__ unsigned long long wave_sum64(uint32_t v) {
+  const uint32_t lo = wave_sum(v & 0xFFFFu), hi = wave_sum(v >> 16);
+  return ((unsigned long long)hi << 16) + lo;
 }
 
 // Block-wide exclusive scan of n values val(i), handing out(i, prefix); returns the
@@ -1028,22 +1013,12 @@ __device__ uint32_t block_scan_u32(uint32_t n, Val val, Out out) {
   for (uint32_t base = 0; base < n; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
     const uint32_t v = i < n ? val(i) : 0u;
-    uint32_t incl = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t t = __shfl_up(incl, o, kWave);
-      if (lane >= (uint32_t)o) incl += t;
-    }
+    const uint32_t incl = wave_incl_sum(v);
     if (lane == kWave - 1) wt[wv] = incl;
     __syncthreads();
     if (wv == 0) {  // the first wave scans the wave totals (at most 16)
       const uint32_t t = lane < nw ? wt[lane] : 0u;
-      uint32_t ti = t;
-#pragma unroll
-      for (int o = 1; o < 1024 / kWave; o <<= 1) {
-        const uint32_t u = __shfl_up(ti, o, kWave);
-        if (lane >= (uint32_t)o) ti += u;
-      }
+      const uint32_t ti = wave_incl_sum(t);
       const uint32_t c = carry;
       if (lane < nw) wt[lane] = c + ti - t;
       if (lane == nw - 1) carry = c + ti;
@@ -1089,12 +1064,7 @@ __device__ void plan_assign(const BatchArgs& A, uint32_t q) {
       const uint32_t total = wave_sum(n), busy = wave_sum(n > 0 ? 1u : 0u);
       const uint64_t avail = (uint64_t)A.bctl->grid - busy;
       const uint32_t g = n ? (uint32_t)max<uint64_t>(1, avail * n / total) : 0u;
-      uint32_t incl = g;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t v = __shfl_up(incl, o, kWave);
-        if (r >= (uint32_t)o) incl += v;
-      }
+      const uint32_t incl = wave_incl_sum(g);
       if (r < A.count) P.wgoff[r] = incl - g;
       if (r == (A.count ? A.count - 1u : 0u)) P.wgoff[A.count] = A.count ? incl : 0u;
     }
@@ -1237,6 +1207,43 @@ __global__ void k_export_done(BatchArgs A) {
   if (r < A.count && A.reals[r].ctl.export_state == 1u) A.reals[r].ctl.export_state = 2u;
 }
 
+// The share of every logical workgroup beta < grid in the pass over plan Q, from the
+// plan's workgroup assignment wgoff (nwg workgroups with a share), its realization
+// ranges rseg and its entry prefix segchunk, and the list sizes tn (accessors).
+// Workgroup k of realization r takes entries [e0 + ne k / G_r, e0 + ne (k + 1) / G_r)
+// of r's ne entries starting at e0, and part [tn k / G_r, tn (k + 1) / G_r) of the
+// first half of r's next list buffer.
+template <class Wgoff, class Rseg, class Segchunk, class Tn>
+__device__ void write_descs(const BatchArgs& A, uint32_t nwg, Wgoff wgoff, Rseg rseg,
+                            Segchunk segchunk, Tn tn) {
+  for (uint32_t beta = threadIdx.x; beta < A.sweep_grid; beta += blockDim.x) {
+    WgDesc d{kNoReal, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    if (beta < nwg) {
+      uint32_t lo = 0, hi = A.count;  // the last r with wgoff(r) <= beta
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (wgoff(mid) <= beta) lo = mid; else hi = mid;
+      }
+      const uint32_t r = lo, w0 = wgoff(r);
+      const uint32_t k = beta - w0, Gr = wgoff(r + 1) - w0;
+      const uint32_t sb = rseg(r), se = rseg(r + 1);
+      const uint32_t e0 = segchunk(sb);
+      const uint64_t ne = segchunk(se) - e0;
+      const uint32_t e_lo = e0 + floor_div53(ne * k, Gr);
+      uint32_t a = sb, b = se;  // the last s in [sb, se) with segchunk(s) <= e_lo
+      while (b - a > 1) {
+        const uint32_t mid = (a + b) >> 1;
+        if (segchunk(mid) <= e_lo) a = mid; else b = mid;
+      }
+      const uint64_t half = tn(r);
+      const uint32_t part_base = floor_div53(half * k, Gr);
+      d = WgDesc{r, k, e_lo, e0 + floor_div53(ne * (k + 1), Gr), a, se, part_base,
+                 floor_div53(half * (k + 1), Gr) - part_base};
+    }
+    A.desc[beta] = d;
+  }
+}
+
 // Loop state of step 0 for every freshly seeded realization (its list: the tiles of
 // its seeds, at the start of list buffer 0), and the input plan of the next pass: realizations
 // already growing keep their segments, new ones get one segment, finished ones none.
@@ -1305,51 +1312,98 @@ __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
   }
   __syncthreads();
   plan_assign(A, qo);
-  if (threadIdx.x == 0) A.bctl->plan = qo;
+  // plan_assign's writes are visible to the workgroup after its closing barrier
+  const uint32_t nwg = O.wgoff[A.count];
+  write_descs(
+      A, nwg, [&](uint32_t r) { return O.wgoff[r]; }, [&](uint32_t r) { return O.rseg[r]; },
+      [&](uint32_t s) { return O.segchunk[s]; }, [&](uint32_t r) { return A.reals[r].tl.n; });
+  if (threadIdx.x == 0) {
+    A.bctl->plan = qo;
+    A.bctl->nwg = nwg;
+  }
 }
 
-// End of a pass for realization r: kept = |F_t|, out = tiles listed for the next
-// pass, grown = voxels grown in the pass, draws and blocks = its work.
-__device__ void sweep_end(const BatchArgs& A, uint32_t r, uint32_t kept, uint32_t out,
-                          uint32_t grown, uint64_t draws, uint64_t blocks) {
-  Real& R = A.reals[r];
-  Ctl& c = R.ctl;
-  const uint32_t bad = atomic_load(&c.overflow) | atomic_load(&c.bad_entry);
-  if (bad) {
+// Loop state that the end of a pass reads for realization r, loaded at once (the sweep
+// that wrote it has finished).
+struct EndIn {
+  uint32_t active;   // a tile-sweep pass was pending (sweep_active)
+  uint32_t bad;      // overflow | bad_entry
+  uint32_t mode, cur, log_cap, tn, tail;
+  int32_t step, max_steps;
+  uint64_t cnt, s_star, t_ref[3];
+  uint64_t* log;
+  uint32_t w0[2], w1[2];  // wgoff[r], wgoff[r + 1] of either plan
+};
+
+__device__ __forceinline__ EndIn end_load(const BatchArgs& A, uint32_t r) {
+  const Real& R = A.reals[r];
+  const Ctl& c = R.ctl;
+  EndIn in;
+  in.active = sweep_active(R) ? 1u : 0u;
+  in.bad = c.overflow | c.bad_entry;
+  in.mode = c.mode;
+  in.cur = c.cur;
+  in.log_cap = R.log_cap;
+  in.tn = R.tl.n;
+  in.tail = A.tailfill[r];
+  in.step = c.step;
+  in.max_steps = c.max_steps;
+  in.cnt = c.cnt;
+  in.s_star = c.s_star;
+  for (int k = 0; k < 3; ++k) in.t_ref[k] = c.t_ref[k];
+  in.log = R.log;
+  for (int q = 0; q < 2; ++q) {
+    in.w0[q] = A.plan[q].wgoff[r];
+    in.w1[q] = A.plan[q].wgoff[r + 1];
+  }
+  return in;
+}
+
+// End of a pass for realization r (a6): kept = |F_t|, out = tiles listed for the next
+// pass, grown = voxels grown in the pass, draws and blocks = its work.  Writes the step
+// log, the count, the status and the Eq. (1) thresholds of the next step.  Returns
+// whether a pass is still pending (the realization keeps running, or a final pass
+// follows).
+__device__ bool pass_end(const BatchArgs& A, uint32_t r, const EndIn& in, uint32_t kept,
+                         uint32_t out, uint32_t grown, uint64_t draws, uint64_t blocks) {
+  Ctl& c = A.reals[r].ctl;
+  if (in.bad) {
     c.status = kStatusOverflow;
     c.mode = kModeIdle;
-    return;
+    return false;
   }
   c.front_size = kept;
   c.n_list = out;
-  c.cur ^= 1u;
-  if (c.mode == kModeRun && kept > 0) {
-    const uint32_t t = (uint32_t)c.step;
-    if (R.log && t < R.log_cap) {
-      uint64_t* e = R.log + kLogWords * (uint64_t)t;
+  c.cur = in.cur ^ 1u;
+  if (in.mode == kModeRun && kept > 0) {
+    const uint32_t t = (uint32_t)in.step;
+    if (in.log && t < in.log_cap) {
+      uint64_t* e = in.log + kLogWords * (uint64_t)t;
       e[0] = kept;
       e[1] = grown;
-      e[2] = c.cnt;
+      e[2] = in.cnt;
       e[3] = draws;
       e[4] = blocks;
     }
-    c.cnt += grown;
+    const uint64_t cnt = in.cnt + grown;
+    c.cnt = cnt;
     c.last_new = grown;
     c.step = (int32_t)t + 1;
-    if (c.cnt < c.s_star && c.step < c.max_steps) {
-      for (int k = 0; k < 3; ++k) c.T[k] = eq1_threshold(c.t_ref[k], c.cnt, c.s_star);
+    if (cnt < in.s_star && (int32_t)t + 1 < in.max_steps) {
+      for (int k = 0; k < 3; ++k) c.T[k] = eq1_threshold(in.t_ref[k], cnt, in.s_star);
     } else {
       c.mode = kModeFinal;  // one more pass: fold this step's marks, report F_T
     }
-    atomicAdd(&A.bctl->running, 1u);
-  } else {
-    // a final pass, or a running pass that found F_t empty: the loop has stopped, and
-    // the grid is written from the solid plane
-    c.status = c.cnt >= c.s_star ? kStatusDone : (kept == 0 ? kStatusExhausted : kStatusMaxSteps);
-    c.mode = kModeIdle;
-    c.export_state = 1u;
+    return true;
   }
+  // a final pass, or a running pass that found F_t empty: the loop has stopped, and the
+  // grid is written from the solid plane
+  c.status = in.cnt >= in.s_star ? kStatusDone : (kept == 0 ? kStatusExhausted : kStatusMaxSteps);
+  c.mode = kModeIdle;
+  c.export_state = 1u;
+  return false;
 }
+
 
 
 // Directions (26-bit masks) whose step leaves the voxel's tile on each side.
@@ -1555,7 +1609,7 @@ void k_sweep(BatchArgs A) {
   const SweepPlan& Q = A.plan[p ^ 1u];
   // logical workgroup index: XCD x (workgroups b with b % 8 == x) holds [x G/8, (x+1) G/8)
   const uint32_t beta = (blockIdx.x % kNumXcd) * (G / kNumXcd) + blockIdx.x / kNumXcd;
-  const uint32_t nwg = uniform(P.wgoff[A.count]);
+  const WgDesc D = A.desc[beta];  // (uniform) this workgroup's share, written with the plan
   const uint32_t lane = lane_id(), wib = uniform(threadIdx.x / kWave);
   TileImage& T = reinterpret_cast<TileImage*>(sweep_lds)[wib];
   if (threadIdx.x == 0) {
@@ -1566,16 +1620,9 @@ void k_sweep(BatchArgs A) {
     s_draws = 0;
     s_blocks = 0;
   }
-  uint32_t r = 0, k = 0, part_base = 0;
-  if (beta < nwg) {
-    uint32_t a = 0, b = A.count;  // largest r with wgoff[r] <= beta
-    while (b - a > 1) {
-      const uint32_t mid = (a + b) >> 1;
-      if (uniform(P.wgoff[mid]) <= beta) a = mid; else b = mid;
-    }
-    r = a;
-    k = beta - uniform(P.wgoff[r]);
-    const uint32_t Gr = uniform(P.wgoff[r + 1]) - uniform(P.wgoff[r]);
+  const uint32_t r = uniform(D.r);
+  const uint32_t part_base = uniform(D.part_base), part_cap = uniform(D.part_cap);
+  if (r != kNoReal) {
     Real& R = A.reals[r];
     Ctl& c = R.ctl;
     const Geometry g = R.g;
@@ -1593,14 +1640,9 @@ void k_sweep(BatchArgs A) {
       s_key[0] = k0;
       s_key[1] = k1;
     }
-    const uint32_t sb = uniform(P.rseg[r]), se = uniform(P.rseg[r + 1]);
-    const uint32_t e0 = uniform(P.segchunk[sb]);
-    const uint64_t ne = uniform(P.segchunk[se]) - e0;
-    const uint32_t e_lo = e0 + (uint32_t)(ne * k / Gr);
-    const uint32_t e_hi = e0 + (uint32_t)(ne * (k + 1) / Gr);
-    const uint64_t half = tl.n;
-    part_base = (uint32_t)(half * k / Gr);
-    const uint32_t part_cap = (uint32_t)(half * (k + 1) / Gr) - part_base;
+    const uint32_t se = uniform(D.se);
+    const uint32_t e_lo = uniform(D.e_lo), e_hi = uniform(D.e_hi);
+    uint32_t cur_sg = uniform(D.sgi);  // a segment whose start is at or below the next block
     const uint32_t t = uniform((uint32_t)c.step);
     const bool run = uniform(c.mode) == kModeRun;
     // the planes: S, the previous step's marks M[(t - 1) & 1] (folded into S by the
@@ -1657,38 +1699,40 @@ void k_sweep(BatchArgs A) {
     for (uint32_t base = e_lo; base < e_hi; base += kWave) {
       __syncthreads();  // the previous block of entries is consumed
       if (threadIdx.x < (uint32_t)kWave) {
-        // segment of the block's first entry (largest s with segchunk[s] <= base): a
-        // 64-way search, each round narrowing the range 64-fold with one load per lane
-        uint32_t lo = sb, hi = se;  // segchunk[lo] <= base < segchunk[hi]
-        while (hi - lo > 1) {
-          const uint32_t step = (hi - lo + kWave - 1) / kWave;
-          const uint32_t c = lo + lane * step;
-          const uint64_t ok = __ballot(c < hi && P.segchunk[c] <= base);
-          const uint32_t last = 63u - (uint32_t)__builtin_clzll(ok);  // lane 0 probes lo
-          lo = lo + last * step;
-          hi = min(hi, lo + step);
-        }
-        // the block's entries run through segments lo, lo + 1, ...: each lane takes the
-        // last segment whose start is at or below its entry (empty segments share their
-        // successor's start; the walk reads the starts 64 at a time until one passes the
-        // block's last entry)
+        // the block's entries run through segments cur_sg, cur_sg + 1, ... (segchunk of
+        // cur_sg is at or below base): each lane takes the last segment whose start is at
+        // or below its entry (empty segments share their successor's start).  The walk
+        // reads starts and bases 64 segments at a time until a start passes the block's
+        // last entry.
         const uint32_t e = base + lane;
         const uint32_t last_e = min(e_hi, base + (uint32_t)kWave) - 1u;
-        uint32_t sgi = lo;
-        for (uint32_t s0 = lo + 1u; s0 < se; s0 += kWave) {  // (uniform)
-          const uint32_t nxt = s0 + lane < se ? P.segchunk[s0 + lane] : 0xFFFFFFFFu;
+        uint32_t sgi = cur_sg, start = 0, sbase = 0;
+        for (uint32_t s0 = cur_sg; s0 < se; s0 += kWave) {  // (uniform)
+          const bool in = s0 + lane < se;
+          const uint32_t st = in ? P.segchunk[s0 + lane] : 0xFFFFFFFFu;
+          const uint32_t bs = in ? P.seg[s0 + lane].base : 0u;
           bool past = false;
+          uint32_t isel = kWave;
           for (uint32_t i = 0; i < (uint32_t)kWave; ++i) {
-            const uint32_t b = (uint32_t)__builtin_amdgcn_readlane(nxt, i);
+            const uint32_t b = (uint32_t)__builtin_amdgcn_readlane(st, i);
             if (b > last_e) {
               past = true;
               break;
             }
-            if (b <= e) sgi = s0 + i;
+            if (b <= e) isel = i;
+          }
+          const uint32_t src = isel < (uint32_t)kWave ? isel : lane;
+          const uint32_t st_sel = (uint32_t)__shfl(st, (int)src, kWave);
+          const uint32_t bs_sel = (uint32_t)__shfl(bs, (int)src, kWave);
+          if (isel < (uint32_t)kWave) {
+            sgi = s0 + isel;
+            start = st_sel;
+            sbase = bs_sel;
           }
           if (past) break;
         }
-        if (e < e_hi) s_tiles[lane] = (uint32_t)lin[P.seg[sgi].base + e - P.segchunk[sgi]];
+        if (e < e_hi) s_tiles[lane] = (uint32_t)lin[sbase + e - start];
+        cur_sg = (uint32_t)__builtin_amdgcn_readlane(sgi, (int)(last_e - base));
       }
       if (threadIdx.x == 0) s_next = 0;
       __syncthreads();
@@ -1830,12 +1874,7 @@ void k_sweep(BatchArgs A) {
         wave_sync();
         {
           const uint32_t hc = lane < 32u ? T.hist[lane] : 0u;
-          uint32_t hin = hc;
-#pragma unroll
-          for (int o = 1; o < 32; o <<= 1) {
-            const uint32_t v = __shfl_up(hin, o, kWave);
-            if (lane >= (uint32_t)o) hin += v;
-          }
+          const uint32_t hin = wave_incl_sum(hc);
           if (lane < 32u) T.hist[lane] = hin - hc;
         }
         wave_sync();
@@ -1946,17 +1985,13 @@ void k_sweep(BatchArgs A) {
     }
   }
   __syncthreads();
-  if (beta < nwg && threadIdx.x == 0) {
-    // the full-field form keeps every tile listed: each part of the identity list is full
-    const uint32_t tn = A.reals[r].tl.n, Gr = P.wgoff[r + 1] - P.wgoff[r];
-    const uint32_t fill =
-        A.reals[r].form == kFormAllTiles ? (uint32_t)((uint64_t)tn * (k + 1) / Gr) - part_base
-                                         : s_commit;
-    Q.seg[P.wgoff[r] + r + k] = SegEntry{r, part_base, fill, 0u};
-    A.wgkept[beta] = s_kept;
-    A.wggrown[beta] = s_grown;
-    A.wgdraws[beta] = s_draws;
-    A.wgblocks[beta] = s_blocks;
+  if (r != kNoReal && threadIdx.x == 0) {
+    // the all-tiles form keeps every tile listed: each part of the identity list is full
+    const uint32_t fill = A.reals[r].form == kFormAllTiles ? part_cap : s_commit;
+    // the workgroups of realization r are logical indices wgoff[r] .. wgoff[r + 1] - 1,
+    // and its parts are segments wgoff[r] + r onward of the output table
+    Q.seg[beta + r] = SegEntry{r, part_base, fill, 0u};
+    A.rec[beta] = WgRec{r, fill, s_kept, s_grown, s_draws, s_blocks, {0u, 0u}};
   }
 }
 
@@ -1965,92 +2000,173 @@ template __global__ void k_sweep<true, false>(BatchArgs A);
 template __global__ void k_sweep<false, true>(BatchArgs A);
 template __global__ void k_sweep<true, true>(BatchArgs A);
 
-// End of a fused pass (one workgroup of 1024 threads, launched after k_sweep): sums
-// every workgroup's kept count and part fill per realization in LDS, writes the tail
-// segments, ends the step for every active realization (a6: log, count, status,
-// Eq. (1) thresholds of the next step) and builds the next plan.
+// Exclusive prefix sums of a[0..n) in place (LDS), with a[n] = the total, which is
+// returned.  One workgroup, every thread calling; each thread takes a contiguous run.
+__device__ uint32_t lds_exclusive_scan(uint32_t* a, uint32_t n) {
+  __shared__ uint32_t wt[1024 / kWave];
+  __shared__ uint32_t s_total;
+  __syncthreads();  // a[] is complete
+  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+  const uint32_t lo = min(n, threadIdx.x * per), hi = min(n, lo + per);
+  uint32_t sum = 0;
+  for (uint32_t i = lo; i < hi; ++i) sum += a[i];
+  const uint32_t incl = wave_incl_sum(sum);
+  if (lane == kWave - 1) wt[wv] = incl;
+  __syncthreads();
+  if (wv == 0) {  // the first wave scans the wave totals (at most 16)
+    const uint32_t t = lane < nw ? wt[lane] : 0u;
+    const uint32_t ti = wave_incl_sum(t);
+    if (lane < nw) wt[lane] = ti - t;
+    if (lane == nw - 1) s_total = ti;
+  }
+  __syncthreads();
+  uint32_t run = wt[wv] + incl - sum;
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  const uint32_t total = s_total;
+  if (threadIdx.x == 0) a[n] = total;
+  __syncthreads();
+  return total;
+}
+
+// End of a fused pass (one workgroup of 1024 threads, launched after k_sweep): sums the
+// workgroup records per realization in LDS, ends the step of every realization with a
+// pending pass (a6: log, count, status, Eq. (1) thresholds of the next step), writes
+// the tail segments and builds the next plan with every workgroup's share.  Its global
+// loads are issued together at the start (one round trip for up to 1024 realizations);
+// the rest runs in LDS.
 __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
-  __shared__ uint32_t acc_kept[kMaxBatch];
-  __shared__ uint32_t acc_out[kMaxBatch];
-  __shared__ uint32_t acc_grown[kMaxBatch];
-  __shared__ unsigned long long acc_draws[kMaxBatch];
-  __shared__ unsigned long long acc_blocks[kMaxBatch];
-  const uint32_t p = A.bctl->plan;
-  const SweepPlan& P = A.plan[p];
-  const SweepPlan& Q = A.plan[p ^ 1u];
-  for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) {
+  constexpr uint32_t kRecPerThread = kMaxSweepGrid / 1024;
+  __shared__ uint32_t acc_kept[kMaxBatch];   // then: list size (tiles) of r
+  __shared__ uint32_t acc_out[kMaxBatch];    // then: entries of r's next pass (0: none)
+  __shared__ uint32_t acc_grown[kMaxBatch];  // then: first segment of r in the next table
+  __shared__ unsigned long long acc_wide[2][kMaxBatch];  // draws, blocks; then segchunk
+  __shared__ uint32_t s_wg[kMaxBatch + 1];   // tail fills; then the next wgoff
+  __shared__ uint32_t s_sum[3];              // pending passes, entries, busy realizations
+  static_assert(sizeof(acc_wide) >= sizeof(uint32_t) * (kMaxSweepGrid + kMaxBatch + 1),
+                "the next entry prefix fits in the draw and block sums");
+  uint32_t* s_segchunk = reinterpret_cast<uint32_t*>(&acc_wide[0][0]);
+  const uint32_t tid = threadIdx.x, lane = lane_id();
+  const uint32_t count = A.count, G = A.sweep_grid;
+  // one round of loads: control, the first 1024 realizations, every workgroup record
+  const uint32_t p = A.bctl->plan, nwg = A.bctl->nwg;
+  EndIn in0{};
+  if (tid < count) in0 = end_load(A, tid);
+  WgRec rec[kRecPerThread];
+#pragma unroll
+  for (uint32_t u = 0; u < kRecPerThread; ++u) {
+    const uint32_t w = tid + 1024u * u;
+    rec[u] = WgRec{kNoReal, 0u, 0u, 0u, 0u, 0u, {0u, 0u}};
+    if (w < G) rec[u] = A.rec[w];
+  }
+  for (uint32_t r = tid; r < count; r += blockDim.x) {
     acc_kept[r] = 0;
+    acc_out[r] = 0;
     acc_grown[r] = 0;
-    acc_draws[r] = 0;
-    acc_blocks[r] = 0;
-    acc_out[r] = A.tailfill[r];
+    acc_wide[0][r] = 0;
+    acc_wide[1][r] = 0;
   }
-  if (threadIdx.x == 0) A.bctl->running = 0;
+  if (tid < 3) s_sum[tid] = 0;
   __syncthreads();
-  const uint32_t nwg = P.wgoff[A.count];
-  // workgroups are ordered by realization: a wavefront whose 64 entries belong to one
-  // realization sums them first and adds once.  Each thread loads kU entries before
-  // reducing any, so their loads are in flight together.
-  constexpr int kU = 4;
-  for (uint32_t base = threadIdx.x & ~(uint32_t)(kWave - 1); base < nwg;
-       base += blockDim.x * kU) {
-    uint32_t a[kU], kept[kU], grown[kU], draws[kU], blocks[kU], out[kU];
-    bool in[kU];
+  // per-realization sums (the records of workgroups w < nwg): workgroups are ordered by
+  // realization, so a wavefront whose records belong to one realization adds once
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const uint32_t w = base + u * blockDim.x + lane_id();
-      in[u] = w < nwg;
-      a[u] = kept[u] = grown[u] = draws[u] = blocks[u] = out[u] = 0;
-      if (in[u]) {
-        uint32_t lo = 0, hi = A.count;  // realization of logical workgroup w
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (P.wgoff[mid] <= w) lo = mid; else hi = mid;
-        }
-        a[u] = lo;
-        kept[u] = A.wgkept[w];
-        grown[u] = A.wggrown[w];
-        draws[u] = A.wgdraws[w];
-        blocks[u] = A.wgblocks[w];
-        out[u] = Q.seg[w + lo].fill;
+  for (uint32_t u = 0; u < kRecPerThread; ++u) {
+    if (1024u * u >= nwg) break;  // (uniform)
+    const bool in = tid + 1024u * u < nwg;
+    if (__ballot(in) == 0) continue;  // (uniform)
+    const uint32_t rr = in ? rec[u].r : kNoReal;
+    const uint32_t kept = in ? rec[u].kept : 0u, grown = in ? rec[u].grown : 0u;
+    const uint32_t draws = in ? rec[u].draws : 0u, blocks = in ? rec[u].blocks : 0u;
+    const uint32_t out = in ? rec[u].fill : 0u;
+    const uint32_t a0 = __shfl(rr, 0, kWave);  // lane 0 holds the wave's first record
+    if (__ballot(in && rr != a0) == 0) {
+      const uint32_t sk = wave_sum(kept), sg = wave_sum(grown), so = wave_sum(out);
+      const unsigned long long sd = wave_sum64(draws), sb = wave_sum64(blocks);
+      if (lane == 0) {
+        atomicAdd(&acc_kept[a0], sk);
+        atomicAdd(&acc_grown[a0], sg);
+        atomicAdd(&acc_out[a0], so);
+        atomicAdd(&acc_wide[0][a0], sd);
+        atomicAdd(&acc_wide[1][a0], sb);
       }
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      if (__ballot(in[u]) == 0) break;  // (uniform) the entries end here
-      const uint32_t a0 = __shfl(a[u], 0, kWave);
-      if (__ballot(in[u] && a[u] != a0) == 0) {  // one realization: per-wave sums
-        const uint32_t sk = wave_sum(kept[u]), sg = wave_sum(grown[u]),
-                       sd = wave_sum(draws[u]), sb = wave_sum(blocks[u]), so = wave_sum(out[u]);
-        if (lane_id() == 0) {
-          atomicAdd(&acc_kept[a0], sk);
-          atomicAdd(&acc_grown[a0], sg);
-          atomicAdd(&acc_draws[a0], (unsigned long long)sd);
-          atomicAdd(&acc_blocks[a0], (unsigned long long)sb);
-          atomicAdd(&acc_out[a0], so);
-        }
-      } else if (in[u]) {
-        atomicAdd(&acc_kept[a[u]], kept[u]);
-        atomicAdd(&acc_grown[a[u]], grown[u]);
-        atomicAdd(&acc_draws[a[u]], (unsigned long long)draws[u]);
-        atomicAdd(&acc_blocks[a[u]], (unsigned long long)blocks[u]);
-        atomicAdd(&acc_out[a[u]], out[u]);
-      }
+    } else if (in) {
+      atomicAdd(&acc_kept[rr], kept);
+      atomicAdd(&acc_grown[rr], grown);
+      atomicAdd(&acc_out[rr], out);
+      atomicAdd(&acc_wide[0][rr], (unsigned long long)draws);
+      atomicAdd(&acc_wide[1][rr], (unsigned long long)blocks);
     }
   }
   __syncthreads();
-  for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) {
-    const uint32_t w0 = P.wgoff[r], w1 = P.wgoff[r + 1];
-    Q.seg[w1 + r] = SegEntry{r, A.reals[r].tl.n, A.tailfill[r], 0u};
-    A.tailfill[r] = 0;
+  // the step ends, the tail segments and the next plan's per-realization inputs (each
+  // thread rewrites only the LDS entries of its own realizations)
+  const SweepPlan& Q = A.plan[p ^ 1u];
+  uint32_t pending_n = 0;
+  for (uint32_t r = tid; r < count; r += blockDim.x) {
+    const EndIn in = r == tid ? in0 : end_load(A, r);
+    const uint32_t w0 = p ? in.w0[1] : in.w0[0], w1 = p ? in.w1[1] : in.w1[0];
+    const uint32_t out = acc_out[r] + in.tail;
+    const bool pending = in.active && pass_end(A, r, in, acc_kept[r], out, acc_grown[r],
+                                                acc_wide[0][r], acc_wide[1][r]);
+    pending_n += pending ? 1u : 0u;
+    Q.seg[w1 + r] = SegEntry{r, in.tn, in.tail, 0u};
     Q.rseg[r] = w0 + r;
-    if (sweep_active(A.reals[r]))
-      sweep_end(A, r, acc_kept[r], acc_out[r], acc_grown[r], acc_draws[r], acc_blocks[r]);
+    A.tailfill[r] = 0;
+    acc_kept[r] = in.tn;
+    acc_out[r] = pending ? out : 0u;
+    acc_grown[r] = w0 + r;
+    s_wg[r] = in.tail;
   }
-  if (threadIdx.x == 0) Q.rseg[A.count] = nwg + A.count;
+  pending_n = wave_sum(pending_n);
+  if (lane == 0 && pending_n) atomicAdd(&s_sum[0], pending_n);
   __syncthreads();
-  plan_assign(A, p ^ 1u);
-  if (threadIdx.x == 0) A.bctl->plan = p ^ 1u;
+  // the next table's fills: realization r holds segments rseg[r] .. rseg[r + 1] - 1, the
+  // parts of its workgroups and then its tail
+  const uint32_t S = nwg + count;
+#pragma unroll
+  for (uint32_t u = 0; u < kRecPerThread; ++u) {
+    const uint32_t w = tid + 1024u * u;
+    if (w < nwg) s_segchunk[w + rec[u].r] = rec[u].fill;
+  }
+  uint32_t tot = 0, busy = 0;
+  for (uint32_t r = tid; r < count; r += blockDim.x) {
+    s_segchunk[(r + 1u < count ? acc_grown[r + 1] : S) - 1u] = s_wg[r];
+    tot += acc_out[r];
+    busy += acc_out[r] ? 1u : 0u;
+  }
+  tot = wave_sum(tot);
+  busy = wave_sum(busy);
+  if (lane == 0) {
+    if (tot) atomicAdd(&s_sum[1], tot);
+    if (busy) atomicAdd(&s_sum[2], busy);
+  }
+  lds_exclusive_scan(s_segchunk, S);
+  // workgroups of the next pass: G_r = max(1, floor((G - B) n_r / n)) for an active
+  // realization with n_r > 0 entries (B of them, n entries in all), so sum G_r <= G
+  const uint32_t total = s_sum[1];
+  const uint64_t avail = (uint64_t)G - s_sum[2];
+  for (uint32_t r = tid; r < count; r += blockDim.x) {
+    const uint32_t n = acc_out[r];
+    s_wg[r] = n ? max(1u, floor_div53(avail * n, total)) : 0u;
+  }
+  const uint32_t nwg_next = lds_exclusive_scan(s_wg, count);
+  for (uint32_t i = tid; i <= S; i += blockDim.x) Q.segchunk[i] = s_segchunk[i];
+  for (uint32_t r = tid; r <= count; r += blockDim.x) Q.wgoff[r] = s_wg[r];
+  if (tid == 0) Q.rseg[count] = S;
+  write_descs(
+      A, nwg_next, [&](uint32_t r) { return s_wg[r]; },
+      [&](uint32_t r) { return r < count ? acc_grown[r] : S; },
+      [&](uint32_t s) { return s_segchunk[s]; }, [&](uint32_t r) { return acc_kept[r]; });
+  if (tid == 0) {
+    A.bctl->plan = p ^ 1u;
+    A.bctl->nwg = nwg_next;
+    A.bctl->running = s_sum[0];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2222,7 +2338,8 @@ __global__ __launch_bounds__(1024) void k_field_end(BatchArgs A, uint32_t reset_
     c.ff_draws = 0;
     // the step's high-half blocks: four for every cell of the field
     const uint64_t blocks = c.mode == kModeRun ? 4ull * R.g.n : 0ull;
-    sweep_end(A, r, front, 0u, grown, draws, blocks);
+    if (pass_end(A, r, end_load(A, r), front, 0u, grown, draws, blocks))
+      atomicAdd(&A.bctl->running, 1u);
   }
 }
 
