@@ -1406,6 +1406,22 @@ __device__ bool pass_end(const BatchArgs& A, uint32_t r, const EndIn& in, uint32
 
 
 
+// Global and LDS views of generic pointers.  A generic (flat) access counts against both
+// the vector-memory and the LDS wait counters, so every later wait for an LDS access
+// would also wait for it; the fused sweep keeps its global stores and atomics in flight
+// across LDS work, so it makes them global accesses, and its LDS reads LDS ones.
+typedef __attribute__((address_space(1))) uint8_t g_u8;
+typedef __attribute__((address_space(1))) int32_t g_i32;
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) uint64_t g_u64;
+typedef __attribute__((address_space(3))) uint32_t l_u32;
+__device__ __forceinline__ uint32_t global_or(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_or((g_u32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t global_max(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_max((g_u32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Directions (26-bit masks) whose step leaves the voxel's tile on each side.
 constexpr uint32_t dir_mask_where(int field, int val) {
   uint32_t m = 0;
@@ -1465,10 +1481,11 @@ __device__ __forceinline__ uint32_t sweep_block(uint32_t* __restrict__ mark32, u
         if (kInteract && itab) {  // the target's own threshold
           const int32_t off = (dir_field(kDirDX, d) - 1) + (dir_field(kDirDY, d) - 1) * g.nx +
                               (dir_field(kDirDZ, d) - 1) * (int32_t)g.nxy;
-          const uint32_t b = labels[(uint32_t)((int32_t)a + off)];
+          const uint32_t b = ((const g_u8*)labels)[(uint32_t)((int32_t)a + off)];
           if (b != kVoid) {
-            hi = itab->thr[6u * b + cls];
-            lo = itab->thr[6u * b + 3u + cls];
+            const g_u32* thr = (const g_u32*)itab->thr;
+            hi = thr[6u * b + cls];
+            lo = thr[6u * b + 3u + cls];
           } else {
             hi = cls == 2u ? th.hi_corner : (cls == 1u ? th.hi_edge : th.hi_face);
           }
@@ -1476,8 +1493,8 @@ __device__ __forceinline__ uint32_t sweep_block(uint32_t* __restrict__ mark32, u
         bool pass = h < hi;
         if (h == hi) {  // high halves tie (rare): decide on the low half
           if (!have_lo) {
-            const uint32_t kl0 = *(const volatile uint32_t*)&lds_key[0];
-            const uint32_t kl1 = *(const volatile uint32_t*)&lds_key[1];
+            const uint32_t kl0 = *(const volatile l_u32*)&lds_key[0];
+            const uint32_t kl1 = *(const volatile l_u32*)&lds_key[1];
             L = philox10(a, t, blk, kTagGrowLo, kl0, kl1);
             have_lo = true;
           }
@@ -1488,7 +1505,7 @@ __device__ __forceinline__ uint32_t sweep_block(uint32_t* __restrict__ mark32, u
         if (pass) {
           const uint32_t xq = xa + (uint32_t)dir_field(kDirDX, d) - 1u;  // in the domain
           bits[sl] = 1u << (xq & 31u);
-          old[sl] = atomicOr(mark32 + (uint32_t)((int32_t)rb + drow[d]) + (xq >> 5), bits[sl]);
+          old[sl] = global_or(mark32 + (uint32_t)((int32_t)rb + drow[d]) + (xq >> 5), bits[sl]);
           dirs |= 1u << d;
         }
       }
@@ -1684,12 +1701,12 @@ void k_sweep(BatchArgs A) {
       if (pend && pend_old < t + 2u) {
         const uint32_t pos = atomicAdd(&s_fill, 1u);
         if (pos < part_cap) {
-          lout[part_base + pos] = (int32_t)pend_un;
+          ((g_i32*)lout)[part_base + pos] = (int32_t)pend_un;
           atomicMax(&s_commit, pos + 1u);
         } else {  // the part is full: spill into the tail half
           const uint32_t tb = atomicAdd(&A.tailfill[r], 1u);
           if (tb < tl.n)
-            lout[tl.n + tb] = (int32_t)pend_un;
+            ((g_i32*)lout)[tl.n + tb] = (int32_t)pend_un;
           else
             atomicOr(&c.overflow, 1u);
         }
@@ -1731,7 +1748,7 @@ void k_sweep(BatchArgs A) {
           }
           if (past) break;
         }
-        if (e < e_hi) s_tiles[lane] = (uint32_t)lin[sbase + e - start];
+        if (e < e_hi) s_tiles[lane] = (uint32_t)((const g_i32*)lin)[sbase + e - start];
         cur_sg = (uint32_t)__builtin_amdgcn_readlane(sgi, (int)(last_e - base));
       }
       if (threadIdx.x == 0) s_next = 0;
@@ -1823,7 +1840,7 @@ void k_sweep(BatchArgs A) {
             uint64_t sm = (s_i | p_i) & xin;
             if (kLiteral) sm = (fresh & lit) | (sm & ~lit);
             T.S[lane] = in_i ? sm : 0ull;
-            if (in_i && fresh != 0ull) plS[wb_i] = s_i | p_i;
+            if (in_i && fresh != 0ull) ((g_u64*)plS)[wb_i] = s_i | p_i;
           }
         }
         wave_sync();
@@ -1970,7 +1987,7 @@ void k_sweep(BatchArgs A) {
         if (lane < 27u && ((tmask >> lane) & 1u)) {
           const int ox = (int)lane % 3 - 1, oy = (int)(lane / 3) % 3 - 1, oz = (int)lane / 9 - 1;
           pend_un = (uint32_t)((int32_t)u + ox + (int32_t)tl.ntx * (oy + (int32_t)tl.nty * oz));
-          pend_old = atomicMax(&stamp[pend_un], t + 2u);
+          pend_old = global_max(stamp + pend_un, t + 2u);
           pend = true;
         }
       }
@@ -2213,10 +2230,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_field_step(BatchArgs A) {
     const uint32_t k0 = uniform(R.k0), k1 = uniform(R.k1);
     const DrawThresholds th = draw_thresholds(uniform64(R.ctl.T[0]), uniform64(R.ctl.T[1]),
                                               uniform64(R.ctl.T[2]));
-    const uint64_t* __restrict__ S = (const uint64_t*)uniform64((uint64_t)R.planes);
-    const uint64_t* __restrict__ W =
-        uniform(R.walls) != 0 ? S + (size_t)pw * kPlaneW : nullptr;
-    uint32_t* __restrict__ mark32 = (uint32_t*)(S + (size_t)pw * kPlaneM0);
+    uint64_t* const planes = (uint64_t*)uniform64((uint64_t)R.planes);
+    const g_u64* __restrict__ S = (const g_u64*)planes;
+    const g_u64* __restrict__ W = uniform(R.walls) != 0 ? S + (size_t)pw * kPlaneW : nullptr;
+    uint32_t* __restrict__ mark32 = (uint32_t*)(planes + (size_t)pw * kPlaneM0);
     // occupied (solid or another phase's cell) word of the plane(s)
     auto occ = [&](uint32_t w) -> uint64_t { return W ? (S[w] | W[w]) : S[w]; };
     for (uint32_t j = 0; j < nw; ++j) {
@@ -2296,7 +2313,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_field_step(BatchArgs A) {
         const uint32_t zq = z + (uint32_t)dir_field(kDirDZ, d) - 1u;
         const uint32_t q32 = ((yq + (uint32_t)g.ny * zq) * ntx) * 2u + (xq >> 5);
         const uint32_t bit = 1u << (xq & 31u);
-        grown_l += (atomicOr(mark32 + q32, bit) & bit) == 0u;
+        grown_l += (global_or(mark32 + q32, bit) & bit) == 0u;
       }
     }
   });
@@ -2309,7 +2326,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_field_fold(BatchArgs A) {
     const Real& R = A.reals[r];
     const uint32_t pw = R.pwords;
     if (i >= pw) return;
-    uint64_t* P = R.planes;
+    g_u64* P = (g_u64*)R.planes;
     const uint64_t m = P[(size_t)kPlaneM0 * pw + i];
     if (m) {
       P[(size_t)kPlaneS * pw + i] |= m;
