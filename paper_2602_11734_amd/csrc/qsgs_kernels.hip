@@ -1459,61 +1459,86 @@ __device__ __forceinline__ uint32_t sweep_block(uint32_t* __restrict__ mark32, u
                                                 uint32_t* passed, const Geometry& g,
                                                 const uint8_t* __restrict__ labels,
                                                 const InteractTable* __restrict__ itab) {
-  const uint32_t lf = th.lo_face, le = th.lo_edge, lc = th.lo_corner;
-  uint32_t grown = 0, dirs = 0;
   const U4 H = philox10(a, t, blk, kTagGrowHi, k0, k1);
-  uint32_t old[8], bits[8];  // a rank's old word and its target's bit in it
-  bool have_lo = false;
-  U4 L{0, 0, 0, 0};
+  const bool inter = kInteract && itab != nullptr;
+  // 1. every rank of the block against dhi of its direction, without branches: with
+  // independent phases a high half below it passes and one equal to it ties; with
+  // interacting phases every rank at or below it is decided in step 2 (slot mask `slow`)
+  uint32_t pass = 0, slow = 0;
+  uint32_t mm = m;
 #pragma unroll
   for (int sl = 0; sl < 8; ++sl) {
-    old[sl] = 0xFFFFFFFFu;
-    bits[sl] = 0xFFFFFFFFu;  // (old & bits) == 0 only for a claim that set its bit first
-    if (m) {
-      const int d = __builtin_ctz(m);
-      m &= m - 1u;
+    const uint32_t d = (uint32_t)__builtin_ctz(mm | 0x80000000u);  // 31: no rank left
+    mm &= mm - 1u;
+    const bool valid = d < 26u;
+    const uint32_t w = sl < 2 ? H.x : (sl < 4 ? H.y : (sl < 6 ? H.z : H.w));
+    const uint32_t h = (sl & 1) ? (w >> 16) : (w & 0xFFFFu);
+    const uint32_t hi = dhi[d];
+    if (!inter) pass |= valid && h < hi ? 1u << d : 0u;
+    slow |= valid && (inter ? h <= hi : h == hi) ? 1u << sl : 0u;
+  }
+  // 2. (rare) high-half ties, decided on the low half, and interacting targets
+  if (slow) {
+    const uint32_t lf = th.lo_face, le = th.lo_edge, lc = th.lo_corner;
+    bool have_lo = false;
+    U4 L{0, 0, 0, 0};
+    uint32_t m2 = m;
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) {
+      const uint32_t d = (uint32_t)__builtin_ctz(m2 | 0x80000000u);
+      m2 &= m2 - 1u;
+      if (((slow >> sl) & 1u) == 0u) continue;
       const uint32_t w = sl < 2 ? H.x : (sl < 4 ? H.y : (sl < 6 ? H.z : H.w));
       const uint32_t h = (sl & 1) ? (w >> 16) : (w & 0xFFFFu);
-      uint32_t hi = dhi[d];
-      if (h <= hi) {
-        const uint32_t cls = ((kCornerDirs >> d) & 1u) ? 2u : (((kEdgeDirs >> d) & 1u) ? 1u : 0u);
-        uint32_t lo = cls == 2u ? lc : (cls == 1u ? le : lf);
-        if (kInteract && itab) {  // the target's own threshold
-          const int32_t off = (dir_field(kDirDX, d) - 1) + (dir_field(kDirDY, d) - 1) * g.nx +
-                              (dir_field(kDirDZ, d) - 1) * (int32_t)g.nxy;
-          const uint32_t b = ((const g_u8*)labels)[(uint32_t)((int32_t)a + off)];
-          if (b != kVoid) {
-            const g_u32* thr = (const g_u32*)itab->thr;
-            hi = thr[6u * b + cls];
-            lo = thr[6u * b + 3u + cls];
-          } else {
-            hi = cls == 2u ? th.hi_corner : (cls == 1u ? th.hi_edge : th.hi_face);
-          }
-        }
-        bool pass = h < hi;
-        if (h == hi) {  // high halves tie (rare): decide on the low half
-          if (!have_lo) {
-            const uint32_t kl0 = *(const volatile l_u32*)&lds_key[0];
-            const uint32_t kl1 = *(const volatile l_u32*)&lds_key[1];
-            L = philox10(a, t, blk, kTagGrowLo, kl0, kl1);
-            have_lo = true;
-          }
-          const uint32_t wl = sl < 2 ? L.x : (sl < 4 ? L.y : (sl < 6 ? L.z : L.w));
-          const uint32_t l = (sl & 1) ? (wl >> 16) : (wl & 0xFFFFu);
-          pass = l < lo;
-        }
-        if (pass) {
-          const uint32_t xq = xa + (uint32_t)dir_field(kDirDX, d) - 1u;  // in the domain
-          bits[sl] = 1u << (xq & 31u);
-          old[sl] = global_or(mark32 + (uint32_t)((int32_t)rb + drow[d]) + (xq >> 5), bits[sl]);
-          dirs |= 1u << d;
+      const uint32_t cls = ((kCornerDirs >> d) & 1u) ? 2u : (((kEdgeDirs >> d) & 1u) ? 1u : 0u);
+      uint32_t hi = cls == 2u ? th.hi_corner : (cls == 1u ? th.hi_edge : th.hi_face);
+      uint32_t lo = cls == 2u ? lc : (cls == 1u ? le : lf);
+      if (inter) {  // the target's own threshold
+        const int32_t off = (dir_field(kDirDX, (int)d) - 1) +
+                            (dir_field(kDirDY, (int)d) - 1) * g.nx +
+                            (dir_field(kDirDZ, (int)d) - 1) * (int32_t)g.nxy;
+        const uint32_t b = ((const g_u8*)labels)[(uint32_t)((int32_t)a + off)];
+        if (b != kVoid) {
+          const g_u32* thr = (const g_u32*)itab->thr;
+          hi = thr[6u * b + cls];
+          lo = thr[6u * b + 3u + cls];
         }
       }
+      bool ok = h < hi;
+      if (h == hi) {  // high halves tie: decide on the low half
+        if (!have_lo) {
+          const uint32_t kl0 = *(const volatile l_u32*)&lds_key[0];
+          const uint32_t kl1 = *(const volatile l_u32*)&lds_key[1];
+          L = philox10(a, t, blk, kTagGrowLo, kl0, kl1);
+          have_lo = true;
+        }
+        const uint32_t wl = sl < 2 ? L.x : (sl < 4 ? L.y : (sl < 6 ? L.z : L.w));
+        const uint32_t l = (sl & 1) ? (wl >> 16) : (wl & 0xFFFFu);
+        ok = l < lo;
+      }
+      if (ok) pass |= 1u << d;
     }
   }
+  // 3. the claims of the passing ranks, issued together; a claim's old word is checked
+  // once all are out (a slot without a claim keeps an all-ones word, which never counts)
+  uint32_t old[8], bits[8];
+  uint32_t pm = pass;
 #pragma unroll
-  for (int sl = 0; sl < 8; ++sl) grown += (old[sl] & bits[sl]) == 0u;
-  *passed = dirs;
+  for (int k = 0; k < 8; ++k) {
+    old[k] = 0xFFFFFFFFu;
+    bits[k] = 0xFFFFFFFFu;
+    if (pm) {
+      const uint32_t d = (uint32_t)__builtin_ctz(pm);
+      pm &= pm - 1u;
+      const uint32_t xq = xa + (uint32_t)dir_field(kDirDX, (int)d) - 1u;  // in the domain
+      bits[k] = 1u << (xq & 31u);
+      old[k] = global_or(mark32 + (uint32_t)((int32_t)rb + drow[d]) + (xq >> 5), bits[k]);
+    }
+  }
+  uint32_t grown = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) grown += (old[k] & bits[k]) == 0u;
+  *passed = pass;
   return grown;
 }
 
@@ -1617,7 +1642,7 @@ void k_sweep(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char sweep_lds[];
   __shared__ uint32_t s_tiles[kWave];
   __shared__ int32_t s_drow[26];
-  __shared__ uint32_t s_dhi[26];
+  __shared__ uint32_t s_dhi[32];  // 26..31: 0, read for the empty slots of a block
   __shared__ uint32_t s_key[2];
   __shared__ uint32_t s_fill, s_commit, s_kept, s_grown, s_draws, s_blocks, s_next;
   const uint32_t G = gridDim.x;
@@ -1688,6 +1713,8 @@ void k_sweep(BatchArgs A) {
       }
       const uint32_t d = threadIdx.x;
       s_dhi[d] = ((kCornerDirs >> d) & 1u) ? hc : (((kEdgeDirs >> d) & 1u) ? he : hf);
+    } else if (threadIdx.x < 32u) {
+      s_dhi[threadIdx.x] = 0u;
     }
     const int32_t* __restrict__ lin = uniform(c.cur) ? R.f1 : R.f0;
     int32_t* __restrict__ lout = uniform(c.cur) ? R.f0 : R.f1;
