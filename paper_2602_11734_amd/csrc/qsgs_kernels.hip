@@ -1213,9 +1213,11 @@ __global__ void k_export_done(BatchArgs A) {
 // Workgroup k of realization r takes entries [e0 + ne k / G_r, e0 + ne (k + 1) / G_r)
 // of r's ne entries starting at e0, and part [tn k / G_r, tn (k + 1) / G_r) of the
 // first half of r's next list buffer.
-template <class Wgoff, class Rseg, class Segchunk, class Tn>
+// sgi(beta, sb, se, e_lo): the segment of entry e_lo (the last s in [sb, se) with
+// segchunk(s) <= e_lo).
+template <class Wgoff, class Rseg, class Segchunk, class Tn, class Sgi>
 __device__ void write_descs(const BatchArgs& A, uint32_t nwg, Wgoff wgoff, Rseg rseg,
-                            Segchunk segchunk, Tn tn) {
+                            Segchunk segchunk, Tn tn, Sgi sgi) {
   for (uint32_t beta = threadIdx.x; beta < A.sweep_grid; beta += blockDim.x) {
     WgDesc d{kNoReal, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     if (beta < nwg) {
@@ -1230,11 +1232,7 @@ __device__ void write_descs(const BatchArgs& A, uint32_t nwg, Wgoff wgoff, Rseg 
       const uint32_t e0 = segchunk(sb);
       const uint64_t ne = segchunk(se) - e0;
       const uint32_t e_lo = e0 + floor_div53(ne * k, Gr);
-      uint32_t a = sb, b = se;  // the last s in [sb, se) with segchunk(s) <= e_lo
-      while (b - a > 1) {
-        const uint32_t mid = (a + b) >> 1;
-        if (segchunk(mid) <= e_lo) a = mid; else b = mid;
-      }
+      const uint32_t a = sgi(beta, sb, se, e_lo);
       const uint64_t half = tn(r);
       const uint32_t part_base = floor_div53(half * k, Gr);
       d = WgDesc{r, k, e_lo, e0 + floor_div53(ne * (k + 1), Gr), a, se, part_base,
@@ -1316,7 +1314,15 @@ __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
   const uint32_t nwg = O.wgoff[A.count];
   write_descs(
       A, nwg, [&](uint32_t r) { return O.wgoff[r]; }, [&](uint32_t r) { return O.rseg[r]; },
-      [&](uint32_t s) { return O.segchunk[s]; }, [&](uint32_t r) { return A.reals[r].tl.n; });
+      [&](uint32_t s) { return O.segchunk[s]; }, [&](uint32_t r) { return A.reals[r].tl.n; },
+      [&](uint32_t, uint32_t sb, uint32_t se, uint32_t e) {
+        uint32_t a = sb, b = se;
+        while (b - a > 1) {
+          const uint32_t mid = (a + b) >> 1;
+          if (O.segchunk[mid] <= e) a = mid; else b = mid;
+        }
+        return a;
+      });
   if (threadIdx.x == 0) {
     A.bctl->plan = qo;
     A.bctl->nwg = nwg;
@@ -2202,10 +2208,36 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
   for (uint32_t i = tid; i <= S; i += blockDim.x) Q.segchunk[i] = s_segchunk[i];
   for (uint32_t r = tid; r <= count; r += blockDim.x) Q.wgoff[r] = s_wg[r];
   if (tid == 0) Q.rseg[count] = S;
+  // the first segment of every next-pass share, found from the segments' side: a
+  // non-empty segment s of realization r, [segchunk[s], segchunk[s + 1]), holds the first
+  // entry e0 + floor(ne k / G_r) of exactly the shares k in [ceil(A G_r / ne),
+  // ceil(B G_r / ne)), A and B its bounds relative to r's first entry e0
+  uint16_t* s_sgi = reinterpret_cast<uint16_t*>(acc_out);  // (the entry counts are used)
+  static_assert(sizeof(acc_out) >= sizeof(uint16_t) * kMaxSweepGrid &&
+                    kMaxSweepGrid + kMaxBatch <= 65536u,
+                "a share's first segment fits in 16 bits");
+  for (uint32_t sg = tid; sg < S; sg += blockDim.x) {
+    const uint32_t a0 = s_segchunk[sg], b0 = s_segchunk[sg + 1];
+    if (a0 == b0) continue;
+    uint32_t lo = 0, hi = count;  // the realization: the last r with rseg(r) <= sg
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (acc_grown[mid] <= sg) lo = mid; else hi = mid;
+    }
+    const uint32_t r = lo, w0 = s_wg[r], Gr = s_wg[r + 1] - w0;
+    if (Gr == 0) continue;
+    const uint32_t e0 = s_segchunk[acc_grown[r]];
+    const uint64_t ne = s_segchunk[r + 1 < count ? acc_grown[r + 1] : S] - e0;
+    const uint32_t k0 = floor_div53((uint64_t)(a0 - e0) * Gr + ne - 1u, ne);
+    const uint32_t k1 = min(Gr, floor_div53((uint64_t)(b0 - e0) * Gr + ne - 1u, ne));
+    for (uint32_t k = k0; k < k1; ++k) s_sgi[w0 + k] = (uint16_t)sg;
+  }
+  __syncthreads();
   write_descs(
       A, nwg_next, [&](uint32_t r) { return s_wg[r]; },
       [&](uint32_t r) { return r < count ? acc_grown[r] : S; },
-      [&](uint32_t s) { return s_segchunk[s]; }, [&](uint32_t r) { return acc_kept[r]; });
+      [&](uint32_t s) { return s_segchunk[s]; }, [&](uint32_t r) { return acc_kept[r]; },
+      [&](uint32_t beta, uint32_t, uint32_t, uint32_t) { return (uint32_t)s_sgi[beta]; });
   if (tid == 0) {
     A.bctl->plan = p ^ 1u;
     A.bctl->nwg = nwg_next;
