@@ -150,11 +150,12 @@ inline Tiles make_tiles(const Geometry& g) {
   return t;
 }
 
-// Device memory of the fused sweep per realization: two tile lists of 2 x tiles
-// entries (parts, then spills), the tile stamps and the occupancy planes (S, M0, M1,
-// and W on a multi-phase grid) of ntx * ny * nz 64-bit words each.
-inline size_t list_bytes(const Geometry& g) { return 2 * sizeof(int32_t) * (size_t)make_tiles(g).n; }
-inline size_t stamp_bytes(const Geometry& g) { return sizeof(uint32_t) * (size_t)make_tiles(g).n; }
+// Device memory of the fused sweep per realization: the two tile maps (one bit per tile
+// each) and the occupancy planes (S, M0, M1, and W and X on a multi-phase grid) of
+// ntx * ny * nz 64-bit words each.
+inline size_t map_bytes(const Geometry& g) {
+  return 2 * sizeof(uint32_t) * (size_t)tile_map_words(make_tiles(g).n);
+}
 inline uint32_t plane_words(const Geometry& g) {
   return make_tiles(g).ntx * (uint32_t)g.ny * (uint32_t)g.nz;
 }
@@ -163,7 +164,7 @@ inline size_t plane_bytes(const Geometry& g, bool walls) {
   return sizeof(uint64_t) * (size_t)plane_words(g) * (walls ? 5 : 3);
 }
 inline size_t sweep_state_bytes(const Geometry& g, bool walls) {
-  return 2 * align_up(list_bytes(g)) + align_up(stamp_bytes(g)) + align_up(plane_bytes(g, walls));
+  return align_up(map_bytes(g)) + align_up(plane_bytes(g, walls));
 }
 
 inline Buckets make_buckets(const Geometry& g, int32_t spacing) {
@@ -214,9 +215,8 @@ struct WsHeader {
 // table, round counters and per-step logs.
 struct PersistLayout {
   size_t hdr = 0, bctl = 0, reals = 0, off = 0, live = 0, logs = 0, total = 0;
-  size_t seg[2] = {0, 0}, segchunk[2] = {0, 0}, rseg[2] = {0, 0}, wgoff[2] = {0, 0};
-  size_t rec = 0, desc = 0, tailfill = 0;
-  uint32_t log_cap = 0, seg_cap = 0;
+  size_t rec = 0, desc = 0;
+  uint32_t log_cap = 0;
 };
 
 inline PersistLayout persist_layout(size_t count, uint32_t log_cap) {
@@ -234,16 +234,8 @@ inline PersistLayout persist_layout(size_t count, uint32_t log_cap) {
   L.off = take(sizeof(uint64_t) * (count + 1));
   L.live = take(sizeof(uint32_t) * kMaxRounds);
   L.logs = take(sizeof(uint64_t) * kLogWords * (size_t)log_cap * count);
-  L.seg_cap = kMaxSweepGrid + 2 * (uint32_t)count + 8;
-  for (int q = 0; q < 2; ++q) {
-    L.seg[q] = take(sizeof(SegEntry) * L.seg_cap);
-    L.segchunk[q] = take(sizeof(uint32_t) * (L.seg_cap + 1));
-    L.rseg[q] = take(sizeof(uint32_t) * (count + 1));
-    L.wgoff[q] = take(sizeof(uint32_t) * (count + 1));
-  }
   L.rec = take(sizeof(WgRec) * kMaxSweepGrid);
   L.desc = take(sizeof(WgDesc) * kMaxSweepGrid);
-  L.tailfill = take(sizeof(uint32_t) * count);
   L.total = off;
   return L;
 }
@@ -473,16 +465,8 @@ struct Engine {
     args.off = at<uint64_t>(base, L.off);
     args.bctl = at<BatchCtl>(base, L.bctl);
     args.live = at<uint32_t>(base, L.live);
-    for (int q = 0; q < 2; ++q) {
-      args.plan[q].seg = at<SegEntry>(base, L.seg[q]);
-      args.plan[q].segchunk = at<uint32_t>(base, L.segchunk[q]);
-      args.plan[q].rseg = at<uint32_t>(base, L.rseg[q]);
-      args.plan[q].wgoff = at<uint32_t>(base, L.wgoff[q]);
-    }
-    args.seg_cap = L.seg_cap;
     args.rec = at<WgRec>(base, L.rec);
     args.desc = at<WgDesc>(base, L.desc);
-    args.tailfill = at<uint32_t>(base, L.tailfill);
     const uint32_t g = tune.grow_grid ? tune.grow_grid : resident_sweep_grid(tune.grow_block);
     const uint32_t want = std::max<uint32_t>(g, 2 * (uint32_t)count);
     sweep_grid = std::min<uint32_t>(kMaxSweepGrid, (want + kNumXcd - 1) / kNumXcd * kNumXcd);
@@ -515,13 +499,6 @@ struct Engine {
     const void* src = &b;
     if (stage) src = std::memcpy(st_up_ctl(), &b, sizeof b);
     QSGS_TRY(put(args.bctl, src, sizeof b));
-    // (fill kernels rather than memsets, so that the stream's work stays kernels and copies)
-    const uint32_t n = (uint32_t)reals.size();
-    hipLaunchKernelGGL(k_fill_u32, dim3((n + 256) / 256), dim3(256), 0, s, args.tailfill, 0u, n);
-    QSGS_LAUNCHED("k_fill_u32");
-    hipLaunchKernelGGL(k_fill_u32, dim3((n + 256) / 256), dim3(256), 0, s, args.plan[0].rseg, 0u,
-                       n + 1);
-    QSGS_LAUNCHED("k_fill_u32");
     return QSGS_OK;
   }
 
@@ -559,11 +536,9 @@ struct Engine {
 
   void init_sweep_record(size_t r, const Spec& sp, const qsgs_params* p, uint8_t* grid,
                          void* sweep, bool walls) {
-    const size_t lb = align_up(list_bytes(sp.g));
-    init_record(r, sp, p, grid, at<int32_t>(sweep, 0), at<int32_t>(sweep, lb),
-                2 * make_tiles(sp.g).n);
-    reals[r].stamp = at<uint32_t>(sweep, 2 * lb);
-    reals[r].planes = at<uint64_t>(sweep, 2 * lb + align_up(stamp_bytes(sp.g)));
+    init_record(r, sp, p, grid, nullptr, nullptr, 0);
+    reals[r].maps = at<uint32_t>(sweep, 0);
+    reals[r].planes = at<uint64_t>(sweep, align_up(map_bytes(sp.g)));
     reals[r].pwords = plane_words(sp.g);
     reals[r].walls = walls ? 1u : 0u;
     reals[r].form = (uint32_t)p->sweep_form;

@@ -147,9 +147,10 @@ struct Real {
   Geometry g;
   Buckets bk;
   uint8_t* grid;        // caller's grid, qsgs_grid_bytes bytes
-  int32_t* f0;          // front buffers, cap entries each (fused sweep: tile lists)
+  int32_t* f0;          // front buffers, cap entries each (step API)
   int32_t* f1;
-  uint32_t* stamp;      // fused sweep: per tile, 1 + the last pass whose list holds it
+  uint32_t* maps;       // fused sweep: two tile bitmaps of tile_map_words(tiles) words each,
+                        // the tiles listed for the pass (half cur) and for the next
   Tiles tl;
   uint32_t form;        // kFormList, kFormField (full-field steps) or kFormAllTiles
   int32_t* cand;        // candidates, then the seed list (N entries)
@@ -181,57 +182,37 @@ struct BatchCtl {
   uint32_t running;     // realizations still growing after the last step end
   uint32_t n_sorted;    // bucket-sorted candidates of the spacing rounds
   uint32_t blocks_done; // workgroups of the current sweep that have finished
-  uint32_t plan;        // which of the two sweep plans is the input of the next pass
+  uint32_t pad0;
   uint32_t grid;        // workgroups of every fused sweep launch
   uint32_t nwg;         // workgroups with a share in the current plan
   uint32_t pad[2];
 };
 
-// Fused-sweep tile lists are read through a segment table: segment = a contiguous run
-// of `fill` entries at `base` of realization r's current list buffer.  A
-// realization's segments are consecutive in the table.  Each pass gives every active
-// realization G_r workgroups; workgroup k of r takes the k-th equal share of r's
-// entries and writes the tiles it activates into the k-th equal part of the first
-// half of r's other list buffer (an LDS counter, no global atomic); a part that fills
-// up spills into the buffer's second half through r's tail counter.  The output table
-// of a pass holds, per realization, its G_r parts and then its tail.
-struct SegEntry {
-  uint32_t r, base, fill, pad;
-};
-
-// What one logical workgroup of a fused pass found and listed (written by the workgroup
-// at its end, summed per realization by k_sweep_end).
+// What one logical workgroup of a fused pass found (written by the workgroup at its end,
+// summed per realization by k_sweep_end).
 struct WgRec {
   uint32_t r;        // realization
-  uint32_t fill;     // entries in its part of the next list
   uint32_t kept;     // front voxels found
   uint32_t grown;    // voxels grown
   uint32_t draws;    // draws made
   uint32_t blocks;   // high-half Philox blocks computed
-  uint32_t pad[2];
+  uint32_t pad[3];
 };
 
 // The share of one logical workgroup in the next fused pass, written with the plan so
-// that the workgroup starts from a single load.
+// that the workgroup starts from a single load: the listed tiles of realization r with
+// index in [u_lo, u_hi), n of them (every tile of the range for the all-tiles form).
 constexpr uint32_t kNoReal = 0xFFFFFFFFu;
 struct WgDesc {
-  uint32_t r;          // realization, or kNoReal: no share in this pass
-  uint32_t k;          // index among the realization's G_r workgroups
-  uint32_t e_lo, e_hi; // its entries [e_lo, e_hi) of the plan's entry prefix
-  uint32_t sgi;        // segment of entry e_lo: the last s with segchunk[s] <= e_lo
-  uint32_t se;         // end of the realization's segments in the table
-  uint32_t part_base;  // its part of the first half of the next list buffer
-  uint32_t part_cap;
+  uint32_t r;  // realization, or kNoReal: no share in this pass
+  uint32_t u_lo, u_hi;
+  uint32_t n;
 };
 
-// One sweep plan: an input segment table with its entry prefix, the realization
-// ranges in the table, and the workgroup assignment (exclusive prefix of G_r).
-struct SweepPlan {
-  SegEntry* seg;        // seg_cap entries
-  uint32_t* segchunk;   // seg_cap + 1: entries before each segment
-  uint32_t* rseg;       // count + 1
-  uint32_t* wgoff;      // count + 1
-};
+// 32-bit words of one tile bitmap of a realization with `tiles` tiles.
+__host__ __device__ constexpr uint32_t tile_map_words(uint32_t tiles) {
+  return (tiles + 31u) / 32u;
+}
 
 // What an offset table counts per realization.
 enum ItemKind : uint32_t {
@@ -240,7 +221,7 @@ enum ItemKind : uint32_t {
   kItemsSeeds = 2,   // accepted seeds (front construction)
   kItemsGrow = 3,    // F_t of running realizations
   kItemsPrune = 4,   // F_t + New_t of running realizations
-  kItemsList = 5,    // L_t of realizations with a pending fused pass
+  kItemsList = 5,    // listed tiles of realizations with a pending fused pass
   kItemsQuads = 6,   // every aligned group of four voxels (seed draw)
   kItemsPack = 7,    // plane words of freshly seeded realizations (byte grid -> planes)
   kItemsExport = 8,  // plane words of stopped realizations whose grid is not yet written
@@ -261,12 +242,9 @@ struct BatchArgs {
   uint64_t* sorted_prio;
   uint8_t* status;
   // fused sweep
-  SweepPlan plan[2];
-  uint32_t seg_cap;     // entries of each segment table
   uint32_t sweep_grid;  // workgroups of every fused sweep launch (a multiple of 8)
   WgRec* rec;           // per logical workgroup of the current pass (kMaxSweepGrid)
   WgDesc* desc;         // per logical workgroup of the next pass (kMaxSweepGrid)
-  uint32_t* tailfill;   // per realization: entries spilled into the tail half
 };
 
 __global__ void k_ctl_init(BatchArgs A, uint32_t zero_live);

@@ -21,6 +21,23 @@ __device__ __forceinline__ uint32_t atomic_load(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Global and LDS views of generic pointers.  A generic (flat) access counts against both
+// the vector-memory and the LDS wait counters, so every later wait for an LDS access
+// would also wait for it; the fused sweep keeps its global stores and atomics in flight
+// across LDS work, so it makes them global accesses, and its LDS reads LDS ones.
+typedef __attribute__((address_space(1))) uint8_t g_u8;
+typedef __attribute__((address_space(1))) int32_t g_i32;
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) uint64_t g_u64;
+typedef __attribute__((address_space(3))) uint32_t l_u32;
+__device__ __forceinline__ uint32_t global_or(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_or((g_u32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// (the old value unused: a fire-and-forget atomic)
+__device__ __forceinline__ void global_or_nr(uint32_t* p, uint32_t v) {
+  (void)__hip_atomic_fetch_or((g_u32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Items of one realization for an offset table of the given kind.
 __device__ __forceinline__ uint64_t items_of(const Real& R, uint32_t kind) {
   const Ctl& c = R.ctl;
@@ -284,7 +301,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
   bool walls = false;
   uint64_t t_seed = 0;
   gbyte* grid = nullptr;
-  gword* stamp = nullptr;
+  gword* maps = nullptr;
   int32_t* cand_list = nullptr;
   uint32_t* n_cand = nullptr;
   // Candidates collect in a per-wavefront LDS buffer and go to the realization's list
@@ -316,8 +333,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
       k1 = uniform(R.k1);
       t_seed = uniform64(R.t_seed);
       grid = (gbyte*)uniform64((uint64_t)R.grid);
-      stamp = (gword*)uniform64((uint64_t)R.stamp);
-      tiles = uniform(R.tl.n);
+      maps = (gword*)uniform64((uint64_t)R.maps);
+      tiles = 2u * tile_map_words(uniform(R.tl.n));  // map words (both halves)
       walls = uniform(R.walls) != 0;
       cand_list = (int32_t*)uniform64((uint64_t)R.cand);
       n_cand = &R.ctl.n_cand;
@@ -348,8 +365,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_seed_draw(BatchArgs A) {
       } else {
         for (uint32_t k = 0; v0 + k < n; ++k) grid[v0 + k] = kVoid;
       }
-      if (stamp)  // fused sweep: no tile listed yet
-        for (uint32_t k = 0; k < 4u && v0 + k < tiles; ++k) stamp[v0 + k] = 0;
+      if (maps)  // fused sweep: no tile listed yet (both map halves; fewer words than voxels)
+        for (uint32_t k = 0; k < 4u && v0 + k < tiles; ++k) maps[v0 + k] = 0;
     }
     if (__ballot(cand != 0)) {
       uint32_t tot;
@@ -545,34 +562,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_collect_seeds(BatchArgs A) {
   }
 }
 
-// A full-field realization lists every tile, in both list buffers (written by the
-// items of its voxel range: tiles <= N).
+// The all-tiles form lists every tile, in every pass (no map is kept).
 __global__ __launch_bounds__(kMaxBlock) void k_full_tiles(BatchArgs A) {
   for_each_chunk(A, kItemsVoxels, [&](uint32_t r, uint32_t i) {
     Real& R = A.reals[r];
-    if (R.form != kFormAllTiles || i >= R.tl.n) return;
-    R.f0[i] = (int32_t)i;
-    R.f1[i] = (int32_t)i;
-    if (i == 0) R.ctl.n_list = R.tl.n;
+    if (R.form == kFormAllTiles && i == 0) R.ctl.n_list = R.tl.n;
   });
 }
 
-// The fused sweep's first list: the tiles holding a seed, each once (stamp 1 = listed
-// for pass 0), appended to list buffer 0 with one atomic per wavefront.
+// The fused sweep's first list: the tiles holding a seed, as bits of map half 0 (zeroed
+// with the grid), and their number (a tile counts once: for the first seed that set
+// its bit).
 __global__ __launch_bounds__(kMaxBlock) void k_seed_tiles(BatchArgs A) {
   for_each_chunk(A, kItemsSeeds, [&](uint32_t r, uint32_t i) {
     Real& R = A.reals[r];
     if (R.form != kFormList) return;  // (uniform per wavefront)
     bool fresh = false;
-    uint32_t u = 0;
     if (i < R.ctl.n_seeds) {
       uint32_t x, y, z;
       coords_of(R.g, (uint32_t)R.cand[i], x, y, z);
-      u = x / kTileX + R.tl.ntx * (y / kTileY + R.tl.nty * (z / kTileZ));
-      fresh = atomicMax(&R.stamp[u], 1u) == 0u;
+      const uint32_t u = x / kTileX + R.tl.ntx * (y / kTileY + R.tl.nty * (z / kTileZ));
+      const uint32_t bit = 1u << (u & 31u);
+      fresh = (atomicOr(&R.maps[u >> 5], bit) & bit) == 0u;
     }
-    const uint32_t pos = wave_append_flag(fresh, &R.ctl.n_list);
-    if (fresh) R.f0[pos] = (int32_t)u;
+    wave_append_flag(fresh, &R.ctl.n_list);
   });
 }
 
@@ -1042,51 +1055,6 @@ __device__ __forceinline__ bool field_active(const Real& R) {
          R.form == kFormField;
 }
 
-// Entry prefix and workgroup assignment of plan q, whose segment table and
-// realization ranges are complete.  G_r = max(1, floor((G - B) n_r / n)) for an
-// active realization with n_r > 0 entries (B of them, n entries in all), so that
-// sum G_r <= G.  One workgroup.
-__device__ void plan_assign(const BatchArgs& A, uint32_t q) {
-  const SweepPlan& P = A.plan[q];
-  const uint32_t S = P.rseg[A.count];
-  const uint32_t chunks = block_scan_u32(
-      S, [&](uint32_t i) { return atomic_load(&P.seg[i].fill); },
-      [&](uint32_t i, uint32_t x) { P.segchunk[i] = x; });
-  if (threadIdx.x == 0) P.segchunk[S] = chunks;
-  __syncthreads();
-  auto nch = [&](uint32_t r) -> uint32_t {
-    return sweep_active(A.reals[r]) ? P.segchunk[P.rseg[r + 1]] - P.segchunk[P.rseg[r]] : 0u;
-  };
-  if (A.count <= (uint32_t)kWave) {  // one wavefront: sums and prefix without barriers
-    if (threadIdx.x < (uint32_t)kWave) {
-      const uint32_t r = threadIdx.x;
-      const uint32_t n = r < A.count ? nch(r) : 0u;
-      const uint32_t total = wave_sum(n), busy = wave_sum(n > 0 ? 1u : 0u);
-      const uint64_t avail = (uint64_t)A.bctl->grid - busy;
-      const uint32_t g = n ? (uint32_t)max<uint64_t>(1, avail * n / total) : 0u;
-      const uint32_t incl = wave_incl_sum(g);
-      if (r < A.count) P.wgoff[r] = incl - g;
-      if (r == (A.count ? A.count - 1u : 0u)) P.wgoff[A.count] = A.count ? incl : 0u;
-    }
-    __syncthreads();
-    return;
-  }
-  const uint32_t total = block_scan_u32(A.count, nch, [](uint32_t, uint32_t) {});
-  const uint32_t busy = block_scan_u32(
-      A.count, [&](uint32_t r) { return nch(r) > 0 ? 1u : 0u; }, [](uint32_t, uint32_t) {});
-  const uint64_t avail = (uint64_t)A.bctl->grid - busy;
-  const uint32_t nwg = block_scan_u32(
-      A.count,
-      [&](uint32_t r) -> uint32_t {
-        const uint32_t n = nch(r);
-        if (n == 0) return 0u;
-        return (uint32_t)max<uint64_t>(1, avail * n / total);
-      },
-      [&](uint32_t r, uint32_t x) { P.wgoff[r] = x; });
-  if (threadIdx.x == 0) P.wgoff[A.count] = nwg;
-  __syncthreads();
-}
-
 // Byte grid <-> occupancy planes of the fused sweep.  Items are plane words; a chunk of
 // 64 words is handled word by word, lane b taking voxel x = 64 ix + b of the word's row,
 // so every grid access of the wavefront is one coalesced 64-byte row piece.
@@ -1207,49 +1175,208 @@ __global__ void k_export_done(BatchArgs A) {
   if (r < A.count && A.reals[r].ctl.export_state == 1u) A.reals[r].ctl.export_state = 2u;
 }
 
-// The share of every logical workgroup beta < grid in the pass over plan Q, from the
-// plan's workgroup assignment wgoff (nwg workgroups with a share), its realization
-// ranges rseg and its entry prefix segchunk, and the list sizes tn (accessors).
-// Workgroup k of realization r takes entries [e0 + ne k / G_r, e0 + ne (k + 1) / G_r)
-// of r's ne entries starting at e0, and part [tn k / G_r, tn (k + 1) / G_r) of the
-// first half of r's next list buffer.
-// sgi(beta, sb, se, e_lo): the segment of entry e_lo (the last s in [sb, se) with
-// segchunk(s) <= e_lo).
-template <class Wgoff, class Rseg, class Segchunk, class Tn, class Sgi>
-__device__ void write_descs(const BatchArgs& A, uint32_t nwg, Wgoff wgoff, Rseg rseg,
-                            Segchunk segchunk, Tn tn, Sgi sgi) {
-  for (uint32_t beta = threadIdx.x; beta < A.sweep_grid; beta += blockDim.x) {
-    WgDesc d{kNoReal, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+// Exclusive prefix sums of a[0..n) in place (LDS), with a[n] = the total, which is
+// returned.  One workgroup, every thread calling; each thread takes a contiguous run.
+__device__ uint32_t lds_exclusive_scan(uint32_t* a, uint32_t n) {
+  __shared__ uint32_t wt[1024 / kWave];
+  __shared__ uint32_t s_total;
+  __syncthreads();  // a[] is complete
+  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+  const uint32_t lo = min(n, threadIdx.x * per), hi = min(n, lo + per);
+  uint32_t sum = 0;
+  for (uint32_t i = lo; i < hi; ++i) sum += a[i];
+  const uint32_t incl = wave_incl_sum(sum);
+  if (lane == kWave - 1) wt[wv] = incl;
+  __syncthreads();
+  if (wv == 0) {  // the first wave scans the wave totals (at most 16)
+    const uint32_t t = lane < nw ? wt[lane] : 0u;
+    const uint32_t ti = wave_incl_sum(t);
+    if (lane < nw) wt[lane] = ti - t;
+    if (lane == nw - 1) s_total = ti;
+  }
+  __syncthreads();
+  uint32_t run = wt[wv] + incl - sum;
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  const uint32_t total = s_total;
+  if (threadIdx.x == 0) a[n] = total;
+  __syncthreads();
+  return total;
+}
+
+// Position of the j-th (from 0) set bit of w (j < popcount(w)): a binary search for the
+// lowest q with j + 1 set bits at or below it, on popcounts of prefixes.
+__device__ __forceinline__ uint32_t select_bit(uint32_t w, uint32_t j) {
+  uint32_t q = 0;  // invariant: at most j set bits below q
+#pragma unroll
+  for (uint32_t s = 16; s; s >>= 1)
+    if ((uint32_t)__builtin_popcount(w & ((1u << (q + s)) - 1u)) <= j) q += s;
+  return q;
+}
+
+// LDS arrays of plan_shares (one workgroup).  info[r]: bit 0 a tile pass of r is pending,
+// bit 1 the all-tiles form, bit 2 the map half that lists the pass's tiles; tn[r]: its
+// tiles.  The rest is plan_shares' own: n (listed tiles), wo (first word of r in the
+// scanned word space), np (listed tiles before r in that space), wg (first logical
+// workgroup of r), ulo (first tile of each share of a mapped realization).
+struct PlanArrays {
+  uint32_t* info;
+  uint32_t* tn;
+  uint32_t* n;
+  uint32_t* wo;
+  uint32_t* np;
+  uint32_t* wg;
+  uint32_t* ulo;
+  uint32_t* sum;  // 4 words
+};
+
+// The next pass's shares (one workgroup of 1 024 threads, every thread calling).  A
+// pending realization's listed tiles are the set bits of its map half; its G_r
+// workgroups (G_r = max(1, floor((G - B) n_r / n)) for n_r > 0 listed tiles, B such
+// realizations, n tiles in all, so sum G_r <= G) take equal shares of them in index
+// order: share k holds listed tiles floor(n_r k / G_r) .. floor(n_r (k + 1) / G_r) - 1,
+// from the tile of its first one to the tile of the next share's first one.  The
+// all-tiles form takes equal ranges of every tile.  With clear_other the other map half
+// of each pending realization (the previous pass's list) is cleared for the pass after.
+// Writes every logical workgroup's WgDesc and each pending realization's n_list; returns
+// the number of workgroups with a share.
+__device__ uint32_t plan_shares(const BatchArgs& A, const PlanArrays& L, bool clear_other) {
+  const uint32_t tid = threadIdx.x, count = A.count, G = A.sweep_grid;
+  auto mapped = [&](uint32_t r) { return (L.info[r] & 3u) == 1u; };
+  // words of every mapped realization in one space, realization by realization
+  for (uint32_t r = tid; r < count; r += blockDim.x) {
+    L.wo[r] = mapped(r) ? tile_map_words(L.tn[r]) : 0u;
+    L.n[r] = (L.info[r] & 3u) == 3u ? L.tn[r] : 0u;
+  }
+  const uint32_t W = lds_exclusive_scan(L.wo, count);
+  const uint32_t per = (W + blockDim.x - 1u) / blockDim.x;
+  const uint32_t g0 = min(W, tid * per), g1 = min(W, g0 + per);
+  auto realization_of = [&](uint32_t g) {  // the last r with wo[r] <= g (g < W)
+    uint32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (L.wo[mid] <= g) lo = mid; else hi = mid;
+    }
+    while (L.wo[lo + 1] <= g) ++lo;  // (realizations without words share their start)
+    return lo;
+  };
+  // 1. listed tiles per realization, from this thread's run of words
+  uint32_t run_total = 0;
+  if (g0 < g1) {
+    uint32_t r = realization_of(g0), part = 0;
+    const uint32_t* maps = A.reals[r].maps;
+    for (uint32_t g = g0; g < g1; ++g) {
+      while (g >= L.wo[r + 1]) {
+        if (part) atomicAdd(&L.n[r], part);
+        part = 0;
+        ++r;
+        maps = A.reals[r].maps;
+      }
+      const uint32_t mw = tile_map_words(L.tn[r]), half = (L.info[r] >> 2) & 1u;
+      const uint32_t w = g - L.wo[r];
+      const uint32_t pop = (uint32_t)__builtin_popcount(((const g_u32*)maps)[half * mw + w]);
+      part += pop;
+      run_total += pop;
+      if (clear_other) ((g_u32*)maps)[(half ^ 1u) * mw + w] = 0u;
+    }
+    if (part) atomicAdd(&L.n[r], part);
+  }
+  __syncthreads();
+  // 2. workgroups per realization, listed tiles before each mapped realization
+  for (uint32_t r = tid; r < count; r += blockDim.x) {
+    L.np[r] = mapped(r) ? L.n[r] : 0u;
+    if (L.info[r] & 1u) A.reals[r].ctl.n_list = L.n[r];
+  }
+  if (tid < 4) L.sum[tid] = 0;
+  __syncthreads();
+  {
+    uint32_t tot = 0, busy = 0;
+    for (uint32_t r = tid; r < count; r += blockDim.x) {
+      const uint32_t nr = (L.info[r] & 1u) ? L.n[r] : 0u;
+      tot += nr;
+      busy += nr ? 1u : 0u;
+    }
+    tot = wave_sum(tot);
+    busy = wave_sum(busy);
+    if (lane_id() == 0) {
+      if (tot) atomicAdd(&L.sum[0], tot);
+      if (busy) atomicAdd(&L.sum[1], busy);
+    }
+  }
+  lds_exclusive_scan(L.np, count);
+  const uint32_t total = L.sum[0];
+  const uint64_t avail = (uint64_t)G - L.sum[1];
+  for (uint32_t r = tid; r < count; r += blockDim.x) {
+    const uint32_t nr = (L.info[r] & 1u) ? L.n[r] : 0u;
+    L.wg[r] = nr ? max(1u, floor_div53(avail * nr, total)) : 0u;
+  }
+  const uint32_t nwg = lds_exclusive_scan(L.wg, count);
+  // 3. the first tile of every share of a mapped realization, from the words' side: the
+  // word holding listed tiles [pre, pre + pop) of r holds the first one of exactly the
+  // shares k in [ceil(pre G_r / n_r), ceil((pre + pop) G_r / n_r))
+  const uint32_t before = wave_incl_sum(run_total) - run_total;
+  __shared__ uint32_t s_wave_tot[1024 / kWave];
+  if (lane_id() == kWave - 1) s_wave_tot[tid / kWave] = before + run_total;
+  __syncthreads();
+  uint32_t gp = before;  // listed tiles of mapped realizations before this thread's run
+  for (uint32_t v = 0; v < tid / kWave; ++v) gp += s_wave_tot[v];
+  if (g0 < g1) {
+    uint32_t r = realization_of(g0);
+    const uint32_t* maps = A.reals[r].maps;
+    for (uint32_t g = g0; g < g1; ++g) {
+      while (g >= L.wo[r + 1]) {
+        ++r;
+        maps = A.reals[r].maps;
+      }
+      const uint32_t mw = tile_map_words(L.tn[r]), half = (L.info[r] >> 2) & 1u;
+      const uint32_t w = g - L.wo[r];
+      const uint32_t word = ((const g_u32*)maps)[half * mw + w];
+      const uint32_t pop = (uint32_t)__builtin_popcount(word);
+      const uint32_t nr = L.n[r], w0 = L.wg[r], Gr = L.wg[r + 1] - w0;
+      if (pop && Gr) {
+        const uint32_t pre = gp - L.np[r];
+        const uint32_t k0 = floor_div53((uint64_t)pre * Gr + nr - 1u, nr);
+        const uint32_t k1 = min(Gr, floor_div53((uint64_t)(pre + pop) * Gr + nr - 1u, nr));
+        for (uint32_t k = k0; k < k1; ++k)
+          L.ulo[w0 + k] = 32u * w + select_bit(word, floor_div53((uint64_t)nr * k, Gr) - pre);
+      }
+      gp += pop;
+    }
+  }
+  __syncthreads();
+  // 4. the share of every logical workgroup
+  for (uint32_t beta = tid; beta < G; beta += blockDim.x) {
+    WgDesc d{kNoReal, 0u, 0u, 0u};
     if (beta < nwg) {
-      uint32_t lo = 0, hi = A.count;  // the last r with wgoff(r) <= beta
+      uint32_t lo = 0, hi = count;  // the last r with wg[r] <= beta
       while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (wgoff(mid) <= beta) lo = mid; else hi = mid;
+        if (L.wg[mid] <= beta) lo = mid; else hi = mid;
       }
-      const uint32_t r = lo, w0 = wgoff(r);
-      const uint32_t k = beta - w0, Gr = wgoff(r + 1) - w0;
-      const uint32_t sb = rseg(r), se = rseg(r + 1);
-      const uint32_t e0 = segchunk(sb);
-      const uint64_t ne = segchunk(se) - e0;
-      const uint32_t e_lo = e0 + floor_div53(ne * k, Gr);
-      const uint32_t a = sgi(beta, sb, se, e_lo);
-      const uint64_t half = tn(r);
-      const uint32_t part_base = floor_div53(half * k, Gr);
-      d = WgDesc{r, k, e_lo, e0 + floor_div53(ne * (k + 1), Gr), a, se, part_base,
-                 floor_div53(half * (k + 1), Gr) - part_base};
+      const uint32_t r = lo, k = beta - L.wg[r], Gr = L.wg[r + 1] - L.wg[r];
+      const uint64_t nr = L.n[r], tn = L.tn[r];
+      const uint32_t c0 = floor_div53(nr * k, Gr), c1 = floor_div53(nr * (k + 1), Gr);
+      if (L.info[r] & 2u)  // all tiles
+        d = WgDesc{r, c0, c1, c1 - c0};
+      else
+        d = WgDesc{r, L.ulo[beta], k + 1 < Gr ? L.ulo[beta + 1] : (uint32_t)tn, c1 - c0};
     }
     A.desc[beta] = d;
   }
+  return nwg;
 }
 
-// Loop state of step 0 for every freshly seeded realization (its list: the tiles of
-// its seeds, at the start of list buffer 0), and the input plan of the next pass: realizations
-// already growing keep their segments, new ones get one segment, finished ones none.
-// One workgroup.
+// Loop state of step 0 for every freshly seeded realization (its first map: the tiles of
+// its seeds, in half 0), and the shares of the next pass over every realization with a
+// pending one.  One workgroup.
 __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
-  const uint32_t qi = A.bctl->plan, qo = qi ^ 1u;
-  const SweepPlan& I = A.plan[qi];
-  const SweepPlan& O = A.plan[qo];
+  __shared__ uint32_t s_info[kMaxBatch], s_tn[kMaxBatch], s_n[kMaxBatch];
+  __shared__ uint32_t s_wo[kMaxBatch + 1], s_np[kMaxBatch + 1], s_wg[kMaxBatch + 1];
+  __shared__ uint32_t s_ulo[kMaxSweepGrid], s_sum[4];
   if (threadIdx.x == 0) {
     A.bctl->blocks_done = 0;
     A.bctl->running = 0;
@@ -1257,88 +1384,50 @@ __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
   __syncthreads();
   for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) {
     Real& R = A.reals[r];
-    if (R.phase != kPhaseSeed) continue;
-    R.phase = kPhaseGrow;
-    Ctl& c = R.ctl;
-    c.cnt = c.n_seeds;
-    c.cur = 0;
-    c.step = 0;
-    c.kept = 0;
-    c.out_count = 0;
-    c.new_count = 0;
-    c.front_size = 0;
-    c.status = c.overflow ? kStatusOverflow : 0;
-    c.mode = kModeIdle;
-    if (c.status == 0) {
-      if (c.cnt < c.s_star && c.max_steps > 0) {
-        c.mode = kModeRun;
-        for (int k = 0; k < 3; ++k) c.T[k] = eq1_threshold(c.t_ref[k], c.cnt, c.s_star);
-      } else {
-        c.mode = kModeFinal;
-      }
-      c.bad_entry = 0;
-      c.last_new = 0;
-      c.pad0 = 1;  // new: one segment in the table rebuild below
-    }
-  }
-  __syncthreads();
-  auto entries = [&](uint32_t r) -> uint32_t {
-    const Real& R = A.reals[r];
-    if (!sweep_active(R)) return 0u;
-    return R.ctl.pad0 ? 1u : I.rseg[r + 1] - I.rseg[r];
-  };
-  const uint32_t S = block_scan_u32(A.count, entries,
-                                    [&](uint32_t r, uint32_t x) { O.rseg[r] = x; });
-  if (threadIdx.x == 0) O.rseg[A.count] = S;
-  __syncthreads();
-  for (uint32_t r = threadIdx.x; r < A.count; r += blockDim.x) {
-    Real& R = A.reals[r];
-    if (field_active(R)) {  // full-field form: no tile list
-      R.ctl.pad0 = 0;
-      atomicAdd(&A.bctl->running, 1u);
-      continue;
-    }
-    if (!sweep_active(R)) continue;
-    atomicAdd(&A.bctl->running, 1u);
-    uint32_t o = O.rseg[r];
-    if (R.ctl.pad0) {
-      O.seg[o] = SegEntry{r, 0u, R.ctl.n_list, 0u};
-      R.ctl.pad0 = 0;
-    } else {
-      for (uint32_t e = I.rseg[r]; e < I.rseg[r + 1]; ++e) O.seg[o++] = I.seg[e];
-    }
-  }
-  __syncthreads();
-  plan_assign(A, qo);
-  // plan_assign's writes are visible to the workgroup after its closing barrier
-  const uint32_t nwg = O.wgoff[A.count];
-  write_descs(
-      A, nwg, [&](uint32_t r) { return O.wgoff[r]; }, [&](uint32_t r) { return O.rseg[r]; },
-      [&](uint32_t s) { return O.segchunk[s]; }, [&](uint32_t r) { return A.reals[r].tl.n; },
-      [&](uint32_t, uint32_t sb, uint32_t se, uint32_t e) {
-        uint32_t a = sb, b = se;
-        while (b - a > 1) {
-          const uint32_t mid = (a + b) >> 1;
-          if (O.segchunk[mid] <= e) a = mid; else b = mid;
+    if (R.phase == kPhaseSeed) {
+      R.phase = kPhaseGrow;
+      Ctl& c = R.ctl;
+      c.cnt = c.n_seeds;
+      c.cur = 0;
+      c.step = 0;
+      c.kept = 0;
+      c.out_count = 0;
+      c.new_count = 0;
+      c.front_size = 0;
+      c.status = c.overflow ? kStatusOverflow : 0;
+      c.mode = kModeIdle;
+      if (c.status == 0) {
+        if (c.cnt < c.s_star && c.max_steps > 0) {
+          c.mode = kModeRun;
+          for (int k = 0; k < 3; ++k) c.T[k] = eq1_threshold(c.t_ref[k], c.cnt, c.s_star);
+        } else {
+          c.mode = kModeFinal;
         }
-        return a;
-      });
-  if (threadIdx.x == 0) {
-    A.bctl->plan = qo;
-    A.bctl->nwg = nwg;
+        c.bad_entry = 0;
+        c.last_new = 0;
+      }
+    }
+    const bool tiles = sweep_active(R);
+    if (tiles || field_active(R)) atomicAdd(&A.bctl->running, 1u);
+    s_info[r] = (tiles ? 1u : 0u) | (R.form == kFormAllTiles ? 2u : 0u) | (R.ctl.cur & 1u) << 2;
+    s_tn[r] = R.tl.n;
   }
+  __syncthreads();
+  const PlanArrays L{s_info, s_tn, s_n, s_wo, s_np, s_wg, s_ulo, s_sum};
+  const uint32_t nwg = plan_shares(A, L, false);
+  if (threadIdx.x == 0) A.bctl->nwg = nwg;
 }
 
 // Loop state that the end of a pass reads for realization r, loaded at once (the sweep
 // that wrote it has finished).
 struct EndIn {
   uint32_t active;   // a tile-sweep pass was pending (sweep_active)
+  uint32_t all;      // the all-tiles form
   uint32_t bad;      // overflow | bad_entry
-  uint32_t mode, cur, log_cap, tn, tail;
+  uint32_t mode, cur, log_cap, tn;
   int32_t step, max_steps;
   uint64_t cnt, s_star, t_ref[3];
   uint64_t* log;
-  uint32_t w0[2], w1[2];  // wgoff[r], wgoff[r + 1] of either plan
 };
 
 __device__ __forceinline__ EndIn end_load(const BatchArgs& A, uint32_t r) {
@@ -1346,32 +1435,27 @@ __device__ __forceinline__ EndIn end_load(const BatchArgs& A, uint32_t r) {
   const Ctl& c = R.ctl;
   EndIn in;
   in.active = sweep_active(R) ? 1u : 0u;
+  in.all = R.form == kFormAllTiles ? 1u : 0u;
   in.bad = c.overflow | c.bad_entry;
   in.mode = c.mode;
   in.cur = c.cur;
   in.log_cap = R.log_cap;
   in.tn = R.tl.n;
-  in.tail = A.tailfill[r];
   in.step = c.step;
   in.max_steps = c.max_steps;
   in.cnt = c.cnt;
   in.s_star = c.s_star;
   for (int k = 0; k < 3; ++k) in.t_ref[k] = c.t_ref[k];
   in.log = R.log;
-  for (int q = 0; q < 2; ++q) {
-    in.w0[q] = A.plan[q].wgoff[r];
-    in.w1[q] = A.plan[q].wgoff[r + 1];
-  }
   return in;
 }
 
-// End of a pass for realization r (a6): kept = |F_t|, out = tiles listed for the next
-// pass, grown = voxels grown in the pass, draws and blocks = its work.  Writes the step
-// log, the count, the status and the Eq. (1) thresholds of the next step.  Returns
-// whether a pass is still pending (the realization keeps running, or a final pass
-// follows).
+// End of a pass for realization r (a6): kept = |F_t|, grown = voxels grown in the pass,
+// draws and blocks = its work.  Writes the step log, the count, the status and the
+// Eq. (1) thresholds of the next step.  Returns whether a pass is still pending (the
+// realization keeps running, or a final pass follows).
 __device__ bool pass_end(const BatchArgs& A, uint32_t r, const EndIn& in, uint32_t kept,
-                         uint32_t out, uint32_t grown, uint64_t draws, uint64_t blocks) {
+                         uint32_t grown, uint64_t draws, uint64_t blocks) {
   Ctl& c = A.reals[r].ctl;
   if (in.bad) {
     c.status = kStatusOverflow;
@@ -1379,7 +1463,6 @@ __device__ bool pass_end(const BatchArgs& A, uint32_t r, const EndIn& in, uint32
     return false;
   }
   c.front_size = kept;
-  c.n_list = out;
   c.cur = in.cur ^ 1u;
   if (in.mode == kModeRun && kept > 0) {
     const uint32_t t = (uint32_t)in.step;
@@ -1408,24 +1491,6 @@ __device__ bool pass_end(const BatchArgs& A, uint32_t r, const EndIn& in, uint32
   c.mode = kModeIdle;
   c.export_state = 1u;
   return false;
-}
-
-
-
-// Global and LDS views of generic pointers.  A generic (flat) access counts against both
-// the vector-memory and the LDS wait counters, so every later wait for an LDS access
-// would also wait for it; the fused sweep keeps its global stores and atomics in flight
-// across LDS work, so it makes them global accesses, and its LDS reads LDS ones.
-typedef __attribute__((address_space(1))) uint8_t g_u8;
-typedef __attribute__((address_space(1))) int32_t g_i32;
-typedef __attribute__((address_space(1))) uint32_t g_u32;
-typedef __attribute__((address_space(1))) uint64_t g_u64;
-typedef __attribute__((address_space(3))) uint32_t l_u32;
-__device__ __forceinline__ uint32_t global_or(uint32_t* p, uint32_t v) {
-  return __hip_atomic_fetch_or((g_u32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t global_max(uint32_t* p, uint32_t v) {
-  return __hip_atomic_fetch_max((g_u32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Directions (26-bit masks) whose step leaves the voxel's tile on each side.
@@ -1650,32 +1715,25 @@ void k_sweep(BatchArgs A) {
   __shared__ int32_t s_drow[26];
   __shared__ uint32_t s_dhi[32];  // 26..31: 0, read for the empty slots of a block
   __shared__ uint32_t s_key[2];
-  __shared__ uint32_t s_fill, s_commit, s_kept, s_grown, s_draws, s_blocks, s_next;
+  __shared__ uint32_t s_kept, s_grown, s_draws, s_blocks, s_next, s_nb;
   const uint32_t G = gridDim.x;
-  const uint32_t p = uniform(A.bctl->plan);
-  const SweepPlan& P = A.plan[p];
-  const SweepPlan& Q = A.plan[p ^ 1u];
   // logical workgroup index: XCD x (workgroups b with b % 8 == x) holds [x G/8, (x+1) G/8)
   const uint32_t beta = (blockIdx.x % kNumXcd) * (G / kNumXcd) + blockIdx.x / kNumXcd;
   const WgDesc D = A.desc[beta];  // (uniform) this workgroup's share, written with the plan
   const uint32_t lane = lane_id(), wib = uniform(threadIdx.x / kWave);
   TileImage& T = reinterpret_cast<TileImage*>(sweep_lds)[wib];
   if (threadIdx.x == 0) {
-    s_fill = 0;
-    s_commit = 0;
     s_kept = 0;
     s_grown = 0;
     s_draws = 0;
     s_blocks = 0;
   }
   const uint32_t r = uniform(D.r);
-  const uint32_t part_base = uniform(D.part_base), part_cap = uniform(D.part_cap);
   if (r != kNoReal) {
     Real& R = A.reals[r];
     Ctl& c = R.ctl;
     const Geometry g = R.g;
     const Tiles tl = R.tl;
-    uint32_t* __restrict__ stamp = R.stamp;
     const uint32_t ntx = tl.ntx;
     if (threadIdx.x < 26u) {  // plane row offset of direction d in 32-bit words (read after
                               // the first barrier)
@@ -1688,9 +1746,7 @@ void k_sweep(BatchArgs A) {
       s_key[0] = k0;
       s_key[1] = k1;
     }
-    const uint32_t se = uniform(D.se);
-    const uint32_t e_lo = uniform(D.e_lo), e_hi = uniform(D.e_hi);
-    uint32_t cur_sg = uniform(D.sgi);  // a segment whose start is at or below the next block
+    const uint32_t u_lo = uniform(D.u_lo), u_hi = uniform(D.u_hi), n_share = uniform(D.n);
     const uint32_t t = uniform((uint32_t)c.step);
     const bool run = uniform(c.mode) == kModeRun;
     // the planes: S, the previous step's marks M[(t - 1) & 1] (folded into S by the
@@ -1722,71 +1778,30 @@ void k_sweep(BatchArgs A) {
     } else if (threadIdx.x < 32u) {
       s_dhi[threadIdx.x] = 0u;
     }
-    const int32_t* __restrict__ lin = uniform(c.cur) ? R.f1 : R.f0;
-    int32_t* __restrict__ lout = uniform(c.cur) ? R.f0 : R.f1;
+    // the tile maps: listed for this pass (read), listed for the next (set here)
+    const bool full = uniform(R.form) == kFormAllTiles;
+    const uint32_t mw = tile_map_words(tl.n);
+    uint32_t* const maps = (uint32_t*)uniform64((uint64_t)R.maps);
+    const g_u32* __restrict__ map_in = (const g_u32*)(maps + (uniform(c.cur) ? mw : 0u));
+    uint32_t* __restrict__ map_out = maps + (uniform(c.cur) ? 0u : mw);
     uint32_t kept_w = 0, grown_w = 0, draws_l = 0, blocks_l = 0;
-    // A tile's stamp atomics are issued at the end of its turn; their old values are
-    // used once the next tile's first row loads are out (or after the last tile): the
-    // first raiser of a stamp appends the tile to its part of the next list.
-    uint32_t pend_un = 0, pend_old = 0;
-    bool pend = false;
-    auto append = [&]() {
-      if (pend && pend_old < t + 2u) {
-        const uint32_t pos = atomicAdd(&s_fill, 1u);
-        if (pos < part_cap) {
-          ((g_i32*)lout)[part_base + pos] = (int32_t)pend_un;
-          atomicMax(&s_commit, pos + 1u);
-        } else {  // the part is full: spill into the tail half
-          const uint32_t tb = atomicAdd(&A.tailfill[r], 1u);
-          if (tb < tl.n)
-            ((g_i32*)lout)[tl.n + tb] = (int32_t)pend_un;
-          else
-            atomicOr(&c.overflow, 1u);
-        }
-      }
-      pend = false;
-    };
-    for (uint32_t base = e_lo; base < e_hi; base += kWave) {
-      __syncthreads();  // the previous block of entries is consumed
+    uint32_t taken = 0;  // listed tiles of the share in the blocks before this one
+    for (uint32_t ub = u_lo; ub < u_hi; ub += kWave) {
+      __syncthreads();  // the previous block of tiles is consumed
       if (threadIdx.x < (uint32_t)kWave) {
-        // the block's entries run through segments cur_sg, cur_sg + 1, ... (segchunk of
-        // cur_sg is at or below base): each lane takes the last segment whose start is at
-        // or below its entry (empty segments share their successor's start).  The walk
-        // reads starts and bases 64 segments at a time until a start passes the block's
-        // last entry.
-        const uint32_t e = base + lane;
-        const uint32_t last_e = min(e_hi, base + (uint32_t)kWave) - 1u;
-        uint32_t sgi = cur_sg, start = 0, sbase = 0;
-        for (uint32_t s0 = cur_sg; s0 < se; s0 += kWave) {  // (uniform)
-          const bool in = s0 + lane < se;
-          const uint32_t st = in ? P.segchunk[s0 + lane] : 0xFFFFFFFFu;
-          const uint32_t bs = in ? P.seg[s0 + lane].base : 0u;
-          bool past = false;
-          uint32_t isel = kWave;
-          for (uint32_t i = 0; i < (uint32_t)kWave; ++i) {
-            const uint32_t b = (uint32_t)__builtin_amdgcn_readlane(st, i);
-            if (b > last_e) {
-              past = true;
-              break;
-            }
-            if (b <= e) isel = i;
-          }
-          const uint32_t src = isel < (uint32_t)kWave ? isel : lane;
-          const uint32_t st_sel = (uint32_t)__shfl(st, (int)src, kWave);
-          const uint32_t bs_sel = (uint32_t)__shfl(bs, (int)src, kWave);
-          if (isel < (uint32_t)kWave) {
-            sgi = s0 + isel;
-            start = st_sel;
-            sbase = bs_sel;
-          }
-          if (past) break;
-        }
-        if (e < e_hi) s_tiles[lane] = (uint32_t)((const g_i32*)lin)[sbase + e - start];
-        cur_sg = (uint32_t)__builtin_amdgcn_readlane(sgi, (int)(last_e - base));
+        // the block's listed tiles, in index order (every tile for the all-tiles form)
+        const uint32_t u = ub + lane;
+        bool listed = u < u_hi;
+        if (listed && !full) listed = ((map_in[u >> 5] >> (u & 31u)) & 1u) != 0u;
+        const uint64_t lm = __ballot(listed);
+        if (listed)
+          s_tiles[__builtin_amdgcn_mbcnt_hi((uint32_t)(lm >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)lm, 0u))] = u;
+        if (lane == 0) s_nb = (uint32_t)__popcll(lm);
       }
       if (threadIdx.x == 0) s_next = 0;
       __syncthreads();
-      const uint32_t nb = min((uint32_t)kWave, e_hi - base);
+      const uint32_t nb = uniform(s_nb);
       // each wavefront takes the block's next tile when it is done with one
       for (;;) {
         uint32_t jn = 0;
@@ -1797,7 +1812,7 @@ void k_sweep(BatchArgs A) {
         // the last dispatched would finish long after the first.  A wave's priority
         // falls as its workgroup's share is taken, so workgroups that are behind get
         // issue slots first and all finish together.
-        set_wave_priority(3u - min(3u, 4u * j / nb));
+        set_wave_priority(3u - min(3u, 4u * (taken + j) / max(n_share, 1u)));
         const uint32_t u = uniform(s_tiles[j]);
         if (u >= tl.n) {
           if (lane == 0) atomicOr(&c.bad_entry, 1u);
@@ -1844,7 +1859,6 @@ void k_sweep(BatchArgs A) {
           oL |= wL;
           oR |= wR;
         }
-        append();  // the previous tile's stamps, while the loads are out
         {
           const uint64_t vm = rin ? ~oC & xin : 0ull;
           const uint32_t vl = rin && has_l ? (uint32_t)(~oL >> 63) : 0u;
@@ -1905,7 +1919,6 @@ void k_sweep(BatchArgs A) {
         const uint32_t nq = uniform(nq_l);
         kept_w += nq;
         if (!run || nq == 0) continue;
-        const bool full = R.form == kFormAllTiles;
         for (uint32_t c = piece; c; c &= c - 1u)
           T.qo[pos++] = (uint16_t)((lane >> 2) << 6 | (lane & 3u) * 16u | (uint32_t)__builtin_ctz(c));
         wave_sync();
@@ -2014,18 +2027,19 @@ void k_sweep(BatchArgs A) {
         if (ncand) drain();
         grown_w += wave_sum(grown);
         if (full) continue;  // the all-tiles form lists every tile anyway
-        // 6. list the tiles that may hold F_{t+1} for the next pass, each once: this
-        // tile (it has front voxels) and every tile that received a claim
+        // 6. list the tiles that may hold F_{t+1} for the next pass: this tile (it has
+        // front voxels) and every tile that received a claim, by setting their bits in
+        // the next map (an atomic whose old value is not needed: nothing waits for it)
         const uint32_t tmask = wave_or(tm) | 1u << 13;
         if (lane < 27u && ((tmask >> lane) & 1u)) {
           const int ox = (int)lane % 3 - 1, oy = (int)(lane / 3) % 3 - 1, oz = (int)lane / 9 - 1;
-          pend_un = (uint32_t)((int32_t)u + ox + (int32_t)tl.ntx * (oy + (int32_t)tl.nty * oz));
-          pend_old = global_max(stamp + pend_un, t + 2u);
-          pend = true;
+          const uint32_t un =
+              (uint32_t)((int32_t)u + ox + (int32_t)tl.ntx * (oy + (int32_t)tl.nty * oz));
+          global_or_nr(map_out + (un >> 5), 1u << (un & 31u));
         }
       }
+      taken += nb;
     }
-    append();
     const uint32_t draws_w = wave_sum(draws_l), blocks_w = wave_sum(blocks_l);
     if (lane == 0) {
       if (kept_w) atomicAdd(&s_kept, kept_w);
@@ -2035,14 +2049,8 @@ void k_sweep(BatchArgs A) {
     }
   }
   __syncthreads();
-  if (r != kNoReal && threadIdx.x == 0) {
-    // the all-tiles form keeps every tile listed: each part of the identity list is full
-    const uint32_t fill = A.reals[r].form == kFormAllTiles ? part_cap : s_commit;
-    // the workgroups of realization r are logical indices wgoff[r] .. wgoff[r + 1] - 1,
-    // and its parts are segments wgoff[r] + r onward of the output table
-    Q.seg[beta + r] = SegEntry{r, part_base, fill, 0u};
-    A.rec[beta] = WgRec{r, fill, s_kept, s_grown, s_draws, s_blocks, {0u, 0u}};
-  }
+  if (r != kNoReal && threadIdx.x == 0)
+    A.rec[beta] = WgRec{r, s_kept, s_grown, s_draws, s_blocks, {0u, 0u, 0u}};
 }
 
 template __global__ void k_sweep<false, false>(BatchArgs A);
@@ -2050,77 +2058,49 @@ template __global__ void k_sweep<true, false>(BatchArgs A);
 template __global__ void k_sweep<false, true>(BatchArgs A);
 template __global__ void k_sweep<true, true>(BatchArgs A);
 
-// Exclusive prefix sums of a[0..n) in place (LDS), with a[n] = the total, which is
-// returned.  One workgroup, every thread calling; each thread takes a contiguous run.
-__device__ uint32_t lds_exclusive_scan(uint32_t* a, uint32_t n) {
-  __shared__ uint32_t wt[1024 / kWave];
-  __shared__ uint32_t s_total;
-  __syncthreads();  // a[] is complete
-  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
-  const uint32_t lo = min(n, threadIdx.x * per), hi = min(n, lo + per);
-  uint32_t sum = 0;
-  for (uint32_t i = lo; i < hi; ++i) sum += a[i];
-  const uint32_t incl = wave_incl_sum(sum);
-  if (lane == kWave - 1) wt[wv] = incl;
-  __syncthreads();
-  if (wv == 0) {  // the first wave scans the wave totals (at most 16)
-    const uint32_t t = lane < nw ? wt[lane] : 0u;
-    const uint32_t ti = wave_incl_sum(t);
-    if (lane < nw) wt[lane] = ti - t;
-    if (lane == nw - 1) s_total = ti;
-  }
-  __syncthreads();
-  uint32_t run = wt[wv] + incl - sum;
-  for (uint32_t i = lo; i < hi; ++i) {
-    const uint32_t v = a[i];
-    a[i] = run;
-    run += v;
-  }
-  const uint32_t total = s_total;
-  if (threadIdx.x == 0) a[n] = total;
-  __syncthreads();
-  return total;
-}
 
 // End of a fused pass (one workgroup of 1024 threads, launched after k_sweep): sums the
 // workgroup records per realization in LDS, ends the step of every realization with a
-// pending pass (a6: log, count, status, Eq. (1) thresholds of the next step), writes
-// the tail segments and builds the next plan with every workgroup's share.  Its global
-// loads are issued together at the start (one round trip for up to 1024 realizations);
-// the rest runs in LDS.
+// pending pass (a6: log, count, status, Eq. (1) thresholds of the next step) and writes
+// the shares of the next pass (plan_shares, which also clears each continuing
+// realization's map of this pass).  Its loads of records and loop state are issued
+// together at the start.
 __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
   constexpr uint32_t kRecPerThread = kMaxSweepGrid / 1024;
-  __shared__ uint32_t acc_kept[kMaxBatch];   // then: list size (tiles) of r
-  __shared__ uint32_t acc_out[kMaxBatch];    // then: entries of r's next pass (0: none)
-  __shared__ uint32_t acc_grown[kMaxBatch];  // then: first segment of r in the next table
-  __shared__ unsigned long long acc_wide[2][kMaxBatch];  // draws, blocks; then segchunk
-  __shared__ uint32_t s_wg[kMaxBatch + 1];   // tail fills; then the next wgoff
-  __shared__ uint32_t s_sum[3];              // pending passes, entries, busy realizations
-  static_assert(sizeof(acc_wide) >= sizeof(uint32_t) * (kMaxSweepGrid + kMaxBatch + 1),
-                "the next entry prefix fits in the draw and block sums");
-  uint32_t* s_segchunk = reinterpret_cast<uint32_t*>(&acc_wide[0][0]);
+  __shared__ uint32_t s_info[kMaxBatch], s_tn[kMaxBatch], s_sum[4];
+  // the per-realization sums, then plan_shares' arrays
+  constexpr size_t kSumBytes = (2 * sizeof(uint32_t) + 2 * sizeof(unsigned long long)) * kMaxBatch;
+  constexpr size_t kPlanBytes = sizeof(uint32_t) * (kMaxBatch + 3 * (kMaxBatch + 1) + kMaxSweepGrid);
+  __shared__ __align__(16) unsigned char s_raw[kSumBytes > kPlanBytes ? kSumBytes : kPlanBytes];
+  unsigned long long* acc_draws = reinterpret_cast<unsigned long long*>(s_raw);
+  unsigned long long* acc_blocks = acc_draws + kMaxBatch;
+  uint32_t* acc_kept = reinterpret_cast<uint32_t*>(acc_blocks + kMaxBatch);
+  uint32_t* acc_grown = acc_kept + kMaxBatch;
+  uint32_t* p_n = reinterpret_cast<uint32_t*>(s_raw);
+  uint32_t* p_wo = p_n + kMaxBatch;
+  uint32_t* p_np = p_wo + kMaxBatch + 1;
+  uint32_t* p_wg = p_np + kMaxBatch + 1;
+  uint32_t* p_ulo = p_wg + kMaxBatch + 1;
   const uint32_t tid = threadIdx.x, lane = lane_id();
   const uint32_t count = A.count, G = A.sweep_grid;
   // one round of loads: control, the first 1024 realizations, every workgroup record
-  const uint32_t p = A.bctl->plan, nwg = A.bctl->nwg;
+  const uint32_t nwg = A.bctl->nwg;
   EndIn in0{};
   if (tid < count) in0 = end_load(A, tid);
   WgRec rec[kRecPerThread];
 #pragma unroll
   for (uint32_t u = 0; u < kRecPerThread; ++u) {
     const uint32_t w = tid + 1024u * u;
-    rec[u] = WgRec{kNoReal, 0u, 0u, 0u, 0u, 0u, {0u, 0u}};
+    rec[u] = WgRec{kNoReal, 0u, 0u, 0u, 0u, {0u, 0u, 0u}};
     if (w < G) rec[u] = A.rec[w];
   }
   for (uint32_t r = tid; r < count; r += blockDim.x) {
     acc_kept[r] = 0;
-    acc_out[r] = 0;
     acc_grown[r] = 0;
-    acc_wide[0][r] = 0;
-    acc_wide[1][r] = 0;
+    acc_draws[r] = 0;
+    acc_blocks[r] = 0;
   }
-  if (tid < 3) s_sum[tid] = 0;
+  if (tid < 4) s_sum[tid] = 0;
   __syncthreads();
   // per-realization sums (the records of workgroups w < nwg): workgroups are ordered by
   // realization, so a wavefront whose records belong to one realization adds once
@@ -2132,116 +2112,43 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
     const uint32_t rr = in ? rec[u].r : kNoReal;
     const uint32_t kept = in ? rec[u].kept : 0u, grown = in ? rec[u].grown : 0u;
     const uint32_t draws = in ? rec[u].draws : 0u, blocks = in ? rec[u].blocks : 0u;
-    const uint32_t out = in ? rec[u].fill : 0u;
     const uint32_t a0 = __shfl(rr, 0, kWave);  // lane 0 holds the wave's first record
     if (__ballot(in && rr != a0) == 0) {
-      const uint32_t sk = wave_sum(kept), sg = wave_sum(grown), so = wave_sum(out);
+      const uint32_t sk = wave_sum(kept), sg = wave_sum(grown);
       const unsigned long long sd = wave_sum64(draws), sb = wave_sum64(blocks);
       if (lane == 0) {
         atomicAdd(&acc_kept[a0], sk);
         atomicAdd(&acc_grown[a0], sg);
-        atomicAdd(&acc_out[a0], so);
-        atomicAdd(&acc_wide[0][a0], sd);
-        atomicAdd(&acc_wide[1][a0], sb);
+        atomicAdd(&acc_draws[a0], sd);
+        atomicAdd(&acc_blocks[a0], sb);
       }
     } else if (in) {
       atomicAdd(&acc_kept[rr], kept);
       atomicAdd(&acc_grown[rr], grown);
-      atomicAdd(&acc_out[rr], out);
-      atomicAdd(&acc_wide[0][rr], (unsigned long long)draws);
-      atomicAdd(&acc_wide[1][rr], (unsigned long long)blocks);
+      atomicAdd(&acc_draws[rr], (unsigned long long)draws);
+      atomicAdd(&acc_blocks[rr], (unsigned long long)blocks);
     }
   }
   __syncthreads();
-  // the step ends, the tail segments and the next plan's per-realization inputs (each
-  // thread rewrites only the LDS entries of its own realizations)
-  const SweepPlan& Q = A.plan[p ^ 1u];
+  // the step ends
   uint32_t pending_n = 0;
   for (uint32_t r = tid; r < count; r += blockDim.x) {
     const EndIn in = r == tid ? in0 : end_load(A, r);
-    const uint32_t w0 = p ? in.w0[1] : in.w0[0], w1 = p ? in.w1[1] : in.w1[0];
-    const uint32_t out = acc_out[r] + in.tail;
-    const bool pending = in.active && pass_end(A, r, in, acc_kept[r], out, acc_grown[r],
-                                                acc_wide[0][r], acc_wide[1][r]);
+    const bool pending = in.active && pass_end(A, r, in, acc_kept[r], acc_grown[r],
+                                                acc_draws[r], acc_blocks[r]);
     pending_n += pending ? 1u : 0u;
-    Q.seg[w1 + r] = SegEntry{r, in.tn, in.tail, 0u};
-    Q.rseg[r] = w0 + r;
-    A.tailfill[r] = 0;
-    acc_kept[r] = in.tn;
-    acc_out[r] = pending ? out : 0u;
-    acc_grown[r] = w0 + r;
-    s_wg[r] = in.tail;
+    s_info[r] = (pending ? 1u : 0u) | (in.all ? 2u : 0u) | ((in.cur ^ 1u) & 1u) << 2;
+    s_tn[r] = in.tn;
   }
   pending_n = wave_sum(pending_n);
   if (lane == 0 && pending_n) atomicAdd(&s_sum[0], pending_n);
   __syncthreads();
-  // the next table's fills: realization r holds segments rseg[r] .. rseg[r + 1] - 1, the
-  // parts of its workgroups and then its tail
-  const uint32_t S = nwg + count;
-#pragma unroll
-  for (uint32_t u = 0; u < kRecPerThread; ++u) {
-    const uint32_t w = tid + 1024u * u;
-    if (w < nwg) s_segchunk[w + rec[u].r] = rec[u].fill;
-  }
-  uint32_t tot = 0, busy = 0;
-  for (uint32_t r = tid; r < count; r += blockDim.x) {
-    s_segchunk[(r + 1u < count ? acc_grown[r + 1] : S) - 1u] = s_wg[r];
-    tot += acc_out[r];
-    busy += acc_out[r] ? 1u : 0u;
-  }
-  tot = wave_sum(tot);
-  busy = wave_sum(busy);
-  if (lane == 0) {
-    if (tot) atomicAdd(&s_sum[1], tot);
-    if (busy) atomicAdd(&s_sum[2], busy);
-  }
-  lds_exclusive_scan(s_segchunk, S);
-  // workgroups of the next pass: G_r = max(1, floor((G - B) n_r / n)) for an active
-  // realization with n_r > 0 entries (B of them, n entries in all), so sum G_r <= G
-  const uint32_t total = s_sum[1];
-  const uint64_t avail = (uint64_t)G - s_sum[2];
-  for (uint32_t r = tid; r < count; r += blockDim.x) {
-    const uint32_t n = acc_out[r];
-    s_wg[r] = n ? max(1u, floor_div53(avail * n, total)) : 0u;
-  }
-  const uint32_t nwg_next = lds_exclusive_scan(s_wg, count);
-  for (uint32_t i = tid; i <= S; i += blockDim.x) Q.segchunk[i] = s_segchunk[i];
-  for (uint32_t r = tid; r <= count; r += blockDim.x) Q.wgoff[r] = s_wg[r];
-  if (tid == 0) Q.rseg[count] = S;
-  // the first segment of every next-pass share, found from the segments' side: a
-  // non-empty segment s of realization r, [segchunk[s], segchunk[s + 1]), holds the first
-  // entry e0 + floor(ne k / G_r) of exactly the shares k in [ceil(A G_r / ne),
-  // ceil(B G_r / ne)), A and B its bounds relative to r's first entry e0
-  uint16_t* s_sgi = reinterpret_cast<uint16_t*>(acc_out);  // (the entry counts are used)
-  static_assert(sizeof(acc_out) >= sizeof(uint16_t) * kMaxSweepGrid &&
-                    kMaxSweepGrid + kMaxBatch <= 65536u,
-                "a share's first segment fits in 16 bits");
-  for (uint32_t sg = tid; sg < S; sg += blockDim.x) {
-    const uint32_t a0 = s_segchunk[sg], b0 = s_segchunk[sg + 1];
-    if (a0 == b0) continue;
-    uint32_t lo = 0, hi = count;  // the realization: the last r with rseg(r) <= sg
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (acc_grown[mid] <= sg) lo = mid; else hi = mid;
-    }
-    const uint32_t r = lo, w0 = s_wg[r], Gr = s_wg[r + 1] - w0;
-    if (Gr == 0) continue;
-    const uint32_t e0 = s_segchunk[acc_grown[r]];
-    const uint64_t ne = s_segchunk[r + 1 < count ? acc_grown[r + 1] : S] - e0;
-    const uint32_t k0 = floor_div53((uint64_t)(a0 - e0) * Gr + ne - 1u, ne);
-    const uint32_t k1 = min(Gr, floor_div53((uint64_t)(b0 - e0) * Gr + ne - 1u, ne));
-    for (uint32_t k = k0; k < k1; ++k) s_sgi[w0 + k] = (uint16_t)sg;
-  }
-  __syncthreads();
-  write_descs(
-      A, nwg_next, [&](uint32_t r) { return s_wg[r]; },
-      [&](uint32_t r) { return r < count ? acc_grown[r] : S; },
-      [&](uint32_t s) { return s_segchunk[s]; }, [&](uint32_t r) { return acc_kept[r]; },
-      [&](uint32_t beta, uint32_t, uint32_t, uint32_t) { return (uint32_t)s_sgi[beta]; });
+  const uint32_t running = s_sum[0];
+  const PlanArrays L{s_info, s_tn, p_n, p_wo, p_np, p_wg, p_ulo, s_sum};
+  const uint32_t nwg_next = plan_shares(A, L, true);
   if (tid == 0) {
-    A.bctl->plan = p ^ 1u;
     A.bctl->nwg = nwg_next;
-    A.bctl->running = s_sum[0];
+    A.bctl->running = running;
   }
 }
 
@@ -2414,7 +2321,7 @@ __global__ __launch_bounds__(1024) void k_field_end(BatchArgs A, uint32_t reset_
     c.ff_draws = 0;
     // the step's high-half blocks: four for every cell of the field
     const uint64_t blocks = c.mode == kModeRun ? 4ull * R.g.n : 0ull;
-    if (pass_end(A, r, end_load(A, r), front, 0u, grown, draws, blocks))
+    if (pass_end(A, r, end_load(A, r), front, grown, draws, blocks))
       atomicAdd(&A.bctl->running, 1u);
   }
 }
