@@ -181,8 +181,7 @@ struct Real {
 struct BatchCtl {
   uint32_t running;     // realizations still growing after the last step end
   uint32_t n_sorted;    // bucket-sorted candidates of the spacing rounds
-  uint32_t blocks_done; // workgroups of the current sweep that have finished
-  uint32_t pad0;
+  uint32_t pad0[2];
   uint32_t grid;        // workgroups of every fused sweep launch
   uint32_t nwg;         // workgroups with a share in the current plan
   uint32_t pad[2];

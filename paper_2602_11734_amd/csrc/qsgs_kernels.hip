@@ -189,7 +189,6 @@ __global__ void k_ctl_init(BatchArgs A, uint32_t zero_live) {
   if (tid == 0) {
     A.bctl->running = 0;
     A.bctl->n_sorted = 0;
-    A.bctl->blocks_done = 0;
   }
   if (zero_live)
     for (uint32_t i = tid; i < kMaxRounds; i += nthr) A.live[i] = 0;
@@ -1014,36 +1013,6 @@ __device__ __forceinline__ unsigned long long wave_sum64(uint32_t v) {
   return ((unsigned long long)hi << 16) + lo;
 }
 
-// Block-wide exclusive scan of n values val(i), handing out(i, prefix); returns the
-// total.  Every thread of the block calls it; blockDim.x <= 1024.
-template <typename Val, typename Out>
-__device__ uint32_t block_scan_u32(uint32_t n, Val val, Out out) {
-  __shared__ uint32_t wt[1024 / kWave];
-  __shared__ uint32_t carry;
-  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t base = 0; base < n; base += blockDim.x) {
-    const uint32_t i = base + threadIdx.x;
-    const uint32_t v = i < n ? val(i) : 0u;
-    const uint32_t incl = wave_incl_sum(v);
-    if (lane == kWave - 1) wt[wv] = incl;
-    __syncthreads();
-    if (wv == 0) {  // the first wave scans the wave totals (at most 16)
-      const uint32_t t = lane < nw ? wt[lane] : 0u;
-      const uint32_t ti = wave_incl_sum(t);
-      const uint32_t c = carry;
-      if (lane < nw) wt[lane] = c + ti - t;
-      if (lane == nw - 1) carry = c + ti;
-    }
-    __syncthreads();
-    if (i < n) out(i, wt[wv] + incl - v);
-    __syncthreads();
-  }
-  const uint32_t total = carry;
-  __syncthreads();
-  return total;
-}
 
 // A realization with a pending tile-sweep pass, or (field_active) a pending full-field step.
 __device__ __forceinline__ bool sweep_active(const Real& R) {
@@ -1208,6 +1177,54 @@ __device__ uint32_t lds_exclusive_scan(uint32_t* a, uint32_t n) {
   return total;
 }
 
+// Exclusive prefix sums of a[0..n) and b[0..n) in place, as lds_exclusive_scan (one pass,
+// one set of barriers); a[n], b[n] = the totals.
+__device__ void lds_exclusive_scan2(uint32_t* a, uint32_t* b, uint32_t n) {
+  __shared__ uint32_t wt[2][1024 / kWave];
+  __shared__ uint32_t s_total[2];
+  __syncthreads();  // a[], b[] are complete
+  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+  const uint32_t lo = min(n, threadIdx.x * per), hi = min(n, lo + per);
+  uint32_t sa = 0, sb = 0;
+  for (uint32_t i = lo; i < hi; ++i) {
+    sa += a[i];
+    sb += b[i];
+  }
+  const uint32_t ia = wave_incl_sum(sa), ib = wave_incl_sum(sb);
+  if (lane == kWave - 1) {
+    wt[0][wv] = ia;
+    wt[1][wv] = ib;
+  }
+  __syncthreads();
+  if (wv == 0) {  // the first wave scans the wave totals (at most 16)
+    const uint32_t ta = lane < nw ? wt[0][lane] : 0u, tb = lane < nw ? wt[1][lane] : 0u;
+    const uint32_t xa = wave_incl_sum(ta), xb = wave_incl_sum(tb);
+    if (lane < nw) {
+      wt[0][lane] = xa - ta;
+      wt[1][lane] = xb - tb;
+    }
+    if (lane == nw - 1) {
+      s_total[0] = xa;
+      s_total[1] = xb;
+    }
+  }
+  __syncthreads();
+  uint32_t ra = wt[0][wv] + ia - sa, rb = wt[1][wv] + ib - sb;
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint32_t va = a[i], vb = b[i];
+    a[i] = ra;
+    b[i] = rb;
+    ra += va;
+    rb += vb;
+  }
+  if (threadIdx.x == 0) {
+    a[n] = s_total[0];
+    b[n] = s_total[1];
+  }
+  __syncthreads();
+}
+
 // Position of the j-th (from 0) set bit of w (j < popcount(w)): a binary search for the
 // lowest q with j + 1 set bits at or below it, on popcounts of prefixes.
 __device__ __forceinline__ uint32_t select_bit(uint32_t w, uint32_t j) {
@@ -1218,14 +1235,16 @@ __device__ __forceinline__ uint32_t select_bit(uint32_t w, uint32_t j) {
   return q;
 }
 
-// LDS arrays of plan_shares (one workgroup).  info[r]: bit 0 a tile pass of r is pending,
-// bit 1 the all-tiles form, bit 2 the map half that lists the pass's tiles; tn[r]: its
-// tiles.  The rest is plan_shares' own: n (listed tiles), wo (first word of r in the
-// scanned word space), np (listed tiles before r in that space), wg (first logical
-// workgroup of r), ulo (first tile of each share of a mapped realization).
+// LDS arrays of plan_shares (one workgroup).  info[r]: bit 0 a tile pass of r is
+// pending, bit 1 the all-tiles form, bit 2 the map half that lists the pass's tiles;
+// tn[r]: its tiles; maps[r]: its maps.  The rest is plan_shares' own: n (listed tiles),
+// wo (first word of r in the scanned word space), np (listed tiles before r in that
+// space), wg (first logical workgroup of r), ulo (first tile of each share of a mapped
+// realization).
 struct PlanArrays {
-  uint32_t* info;
+  uint8_t* info;
   uint32_t* tn;
+  uint32_t** maps;
   uint32_t* n;
   uint32_t* wo;
   uint32_t* np;
@@ -1243,8 +1262,10 @@ struct PlanArrays {
 // all-tiles form takes equal ranges of every tile.  With clear_other the other map half
 // of each pending realization (the previous pass's list) is cleared for the pass after.
 // Writes every logical workgroup's WgDesc and each pending realization's n_list; returns
-// the number of workgroups with a share.
+// the number of workgroups with a share.  Each thread reads a contiguous run of the map
+// words, kChunk at a time with the loads issued together.
 __device__ uint32_t plan_shares(const BatchArgs& A, const PlanArrays& L, bool clear_other) {
+  constexpr uint32_t kChunk = 8;
   const uint32_t tid = threadIdx.x, count = A.count, G = A.sweep_grid;
   auto mapped = [&](uint32_t r) { return (L.info[r] & 3u) == 1u; };
   // words of every mapped realization in one space, realization by realization
@@ -1255,35 +1276,64 @@ __device__ uint32_t plan_shares(const BatchArgs& A, const PlanArrays& L, bool cl
   const uint32_t W = lds_exclusive_scan(L.wo, count);
   const uint32_t per = (W + blockDim.x - 1u) / blockDim.x;
   const uint32_t g0 = min(W, tid * per), g1 = min(W, g0 + per);
-  auto realization_of = [&](uint32_t g) {  // the last r with wo[r] <= g (g < W)
-    uint32_t lo = 0, hi = count;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (L.wo[mid] <= g) lo = mid; else hi = mid;
-    }
-    while (L.wo[lo + 1] <= g) ++lo;  // (realizations without words share their start)
-    return lo;
-  };
-  // 1. listed tiles per realization, from this thread's run of words
-  uint32_t run_total = 0;
+  uint32_t r0 = 0;  // the realization of word g0: the last r with wo[r] <= g0 < wo[r + 1]
   if (g0 < g1) {
-    uint32_t r = realization_of(g0), part = 0;
-    const uint32_t* maps = A.reals[r].maps;
-    for (uint32_t g = g0; g < g1; ++g) {
-      while (g >= L.wo[r + 1]) {
-        if (part) atomicAdd(&L.n[r], part);
-        part = 0;
-        ++r;
-        maps = A.reals[r].maps;
-      }
-      const uint32_t mw = tile_map_words(L.tn[r]), half = (L.info[r] >> 2) & 1u;
-      const uint32_t w = g - L.wo[r];
-      const uint32_t pop = (uint32_t)__builtin_popcount(((const g_u32*)maps)[half * mw + w]);
-      part += pop;
-      run_total += pop;
-      if (clear_other) ((g_u32*)maps)[(half ^ 1u) * mw + w] = 0u;
+    uint32_t hi = count;
+    while (hi - r0 > 1) {
+      const uint32_t mid = (r0 + hi) >> 1;
+      if (L.wo[mid] <= g0) r0 = mid; else hi = mid;
     }
-    if (part) atomicAdd(&L.n[r], part);
+    while (L.wo[r0 + 1] <= g0) ++r0;  // (realizations without words share their start)
+  }
+  // the words c0 .. c0 + kChunk - 1 of the run (0 past its end), their realizations and
+  // their indices in their maps; r, rbase, rend follow the realization of the next word
+  uint32_t wv[kChunk], wr[kChunk], wl[kChunk];
+  auto load_chunk = [&](uint32_t c0, uint32_t& r, uint32_t& rbase, uint32_t& rend) {
+#pragma unroll
+    for (uint32_t k = 0; k < kChunk; ++k) {
+      const uint32_t g = c0 + k;
+      wv[k] = 0;
+      wr[k] = r;
+      wl[k] = 0;
+      if (g < g1) {
+        while (g >= rend) {
+          ++r;
+          rbase = rend;
+          rend = L.wo[r + 1];
+        }
+        const uint32_t mw = tile_map_words(L.tn[r]), half = (L.info[r] >> 2) & 1u;
+        wr[k] = r;
+        wl[k] = g - rbase;
+        wv[k] = ((const g_u32*)L.maps[r])[half * mw + wl[k]];
+      }
+    }
+  };
+  // 1. listed tiles per realization (and the other halves cleared)
+  uint32_t run_total = 0;
+  const bool one_chunk = g1 - g0 <= kChunk;
+  if (g0 < g1) {
+    uint32_t r = r0, rbase = L.wo[r0], rend = L.wo[r0 + 1];
+    uint32_t cr = r0, part = 0;
+    for (uint32_t c0 = g0; c0 < g1; c0 += kChunk) {
+      load_chunk(c0, r, rbase, rend);
+#pragma unroll
+      for (uint32_t k = 0; k < kChunk; ++k) {
+        if (c0 + k >= g1) break;
+        if (wr[k] != cr) {
+          if (part) atomicAdd(&L.n[cr], part);
+          part = 0;
+          cr = wr[k];
+        }
+        const uint32_t pop = (uint32_t)__builtin_popcount(wv[k]);
+        part += pop;
+        run_total += pop;
+        if (clear_other) {
+          const uint32_t mw = tile_map_words(L.tn[cr]), half = (L.info[cr] >> 2) & 1u;
+          ((g_u32*)L.maps[cr])[(half ^ 1u) * mw + wl[k]] = 0u;
+        }
+      }
+    }
+    if (part) atomicAdd(&L.n[cr], part);
   }
   __syncthreads();
   // 2. workgroups per realization, listed tiles before each mapped realization
@@ -1307,44 +1357,44 @@ __device__ uint32_t plan_shares(const BatchArgs& A, const PlanArrays& L, bool cl
       if (busy) atomicAdd(&L.sum[1], busy);
     }
   }
-  lds_exclusive_scan(L.np, count);
+  __syncthreads();
   const uint32_t total = L.sum[0];
   const uint64_t avail = (uint64_t)G - L.sum[1];
   for (uint32_t r = tid; r < count; r += blockDim.x) {
     const uint32_t nr = (L.info[r] & 1u) ? L.n[r] : 0u;
     L.wg[r] = nr ? max(1u, floor_div53(avail * nr, total)) : 0u;
   }
-  const uint32_t nwg = lds_exclusive_scan(L.wg, count);
+  lds_exclusive_scan2(L.np, L.wg, count);
+  const uint32_t nwg = L.wg[count];
   // 3. the first tile of every share of a mapped realization, from the words' side: the
   // word holding listed tiles [pre, pre + pop) of r holds the first one of exactly the
   // shares k in [ceil(pre G_r / n_r), ceil((pre + pop) G_r / n_r))
-  const uint32_t before = wave_incl_sum(run_total) - run_total;
   __shared__ uint32_t s_wave_tot[1024 / kWave];
+  const uint32_t before = wave_incl_sum(run_total) - run_total;
   if (lane_id() == kWave - 1) s_wave_tot[tid / kWave] = before + run_total;
   __syncthreads();
   uint32_t gp = before;  // listed tiles of mapped realizations before this thread's run
   for (uint32_t v = 0; v < tid / kWave; ++v) gp += s_wave_tot[v];
   if (g0 < g1) {
-    uint32_t r = realization_of(g0);
-    const uint32_t* maps = A.reals[r].maps;
-    for (uint32_t g = g0; g < g1; ++g) {
-      while (g >= L.wo[r + 1]) {
-        ++r;
-        maps = A.reals[r].maps;
+    uint32_t r = r0, rbase = L.wo[r0], rend = L.wo[r0 + 1];
+    for (uint32_t c0 = g0; c0 < g1; c0 += kChunk) {
+      if (!one_chunk) load_chunk(c0, r, rbase, rend);  // (a run of one chunk is still held)
+#pragma unroll
+      for (uint32_t k = 0; k < kChunk; ++k) {
+        if (c0 + k >= g1) break;
+        const uint32_t rr = wr[k], word = wv[k];
+        const uint32_t pop = (uint32_t)__builtin_popcount(word);
+        const uint32_t nr = L.n[rr], w0 = L.wg[rr], Gr = L.wg[rr + 1] - w0;
+        if (pop && Gr) {
+          const uint32_t pre = gp - L.np[rr];
+          const uint32_t k0 = floor_div53((uint64_t)pre * Gr + nr - 1u, nr);
+          const uint32_t k1 = min(Gr, floor_div53((uint64_t)(pre + pop) * Gr + nr - 1u, nr));
+          for (uint32_t ks = k0; ks < k1; ++ks)
+            L.ulo[w0 + ks] =
+                32u * wl[k] + select_bit(word, floor_div53((uint64_t)nr * ks, Gr) - pre);
+        }
+        gp += pop;
       }
-      const uint32_t mw = tile_map_words(L.tn[r]), half = (L.info[r] >> 2) & 1u;
-      const uint32_t w = g - L.wo[r];
-      const uint32_t word = ((const g_u32*)maps)[half * mw + w];
-      const uint32_t pop = (uint32_t)__builtin_popcount(word);
-      const uint32_t nr = L.n[r], w0 = L.wg[r], Gr = L.wg[r + 1] - w0;
-      if (pop && Gr) {
-        const uint32_t pre = gp - L.np[r];
-        const uint32_t k0 = floor_div53((uint64_t)pre * Gr + nr - 1u, nr);
-        const uint32_t k1 = min(Gr, floor_div53((uint64_t)(pre + pop) * Gr + nr - 1u, nr));
-        for (uint32_t k = k0; k < k1; ++k)
-          L.ulo[w0 + k] = 32u * w + select_bit(word, floor_div53((uint64_t)nr * k, Gr) - pre);
-      }
-      gp += pop;
     }
   }
   __syncthreads();
@@ -1374,11 +1424,12 @@ __device__ uint32_t plan_shares(const BatchArgs& A, const PlanArrays& L, bool cl
 // its seeds, in half 0), and the shares of the next pass over every realization with a
 // pending one.  One workgroup.
 __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
-  __shared__ uint32_t s_info[kMaxBatch], s_tn[kMaxBatch], s_n[kMaxBatch];
+  __shared__ uint8_t s_info[kMaxBatch];
+  __shared__ uint32_t s_tn[kMaxBatch], s_n[kMaxBatch];
+  __shared__ uint32_t* s_maps[kMaxBatch];
   __shared__ uint32_t s_wo[kMaxBatch + 1], s_np[kMaxBatch + 1], s_wg[kMaxBatch + 1];
   __shared__ uint32_t s_ulo[kMaxSweepGrid], s_sum[4];
   if (threadIdx.x == 0) {
-    A.bctl->blocks_done = 0;
     A.bctl->running = 0;
   }
   __syncthreads();
@@ -1409,11 +1460,13 @@ __global__ __launch_bounds__(1024) void k_sweep_prepare(BatchArgs A) {
     }
     const bool tiles = sweep_active(R);
     if (tiles || field_active(R)) atomicAdd(&A.bctl->running, 1u);
-    s_info[r] = (tiles ? 1u : 0u) | (R.form == kFormAllTiles ? 2u : 0u) | (R.ctl.cur & 1u) << 2;
+    s_info[r] = (uint8_t)((tiles ? 1u : 0u) | (R.form == kFormAllTiles ? 2u : 0u) |
+                          (R.ctl.cur & 1u) << 2);
     s_tn[r] = R.tl.n;
+    s_maps[r] = R.maps;
   }
   __syncthreads();
-  const PlanArrays L{s_info, s_tn, s_n, s_wo, s_np, s_wg, s_ulo, s_sum};
+  const PlanArrays L{s_info, s_tn, s_maps, s_n, s_wo, s_np, s_wg, s_ulo, s_sum};
   const uint32_t nwg = plan_shares(A, L, false);
   if (threadIdx.x == 0) A.bctl->nwg = nwg;
 }
@@ -1428,6 +1481,7 @@ struct EndIn {
   int32_t step, max_steps;
   uint64_t cnt, s_star, t_ref[3];
   uint64_t* log;
+  uint32_t* maps;
 };
 
 __device__ __forceinline__ EndIn end_load(const BatchArgs& A, uint32_t r) {
@@ -1447,6 +1501,7 @@ __device__ __forceinline__ EndIn end_load(const BatchArgs& A, uint32_t r) {
   in.s_star = c.s_star;
   for (int k = 0; k < 3; ++k) in.t_ref[k] = c.t_ref[k];
   in.log = R.log;
+  in.maps = R.maps;
   return in;
 }
 
@@ -2067,7 +2122,9 @@ template __global__ void k_sweep<true, true>(BatchArgs A);
 // together at the start.
 __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
   constexpr uint32_t kRecPerThread = kMaxSweepGrid / 1024;
-  __shared__ uint32_t s_info[kMaxBatch], s_tn[kMaxBatch], s_sum[4];
+  __shared__ uint8_t s_info[kMaxBatch];
+  __shared__ uint32_t s_tn[kMaxBatch], s_sum[4];
+  __shared__ uint32_t* s_maps[kMaxBatch];
   // the per-realization sums, then plan_shares' arrays
   constexpr size_t kSumBytes = (2 * sizeof(uint32_t) + 2 * sizeof(unsigned long long)) * kMaxBatch;
   constexpr size_t kPlanBytes = sizeof(uint32_t) * (kMaxBatch + 3 * (kMaxBatch + 1) + kMaxSweepGrid);
@@ -2137,14 +2194,15 @@ __global__ __launch_bounds__(1024) void k_sweep_end(BatchArgs A) {
     const bool pending = in.active && pass_end(A, r, in, acc_kept[r], acc_grown[r],
                                                 acc_draws[r], acc_blocks[r]);
     pending_n += pending ? 1u : 0u;
-    s_info[r] = (pending ? 1u : 0u) | (in.all ? 2u : 0u) | ((in.cur ^ 1u) & 1u) << 2;
+    s_info[r] = (uint8_t)((pending ? 1u : 0u) | (in.all ? 2u : 0u) | ((in.cur ^ 1u) & 1u) << 2);
     s_tn[r] = in.tn;
+    s_maps[r] = in.maps;
   }
   pending_n = wave_sum(pending_n);
   if (lane == 0 && pending_n) atomicAdd(&s_sum[0], pending_n);
   __syncthreads();
   const uint32_t running = s_sum[0];
-  const PlanArrays L{s_info, s_tn, p_n, p_wo, p_np, p_wg, p_ulo, s_sum};
+  const PlanArrays L{s_info, s_tn, s_maps, p_n, p_wo, p_np, p_wg, p_ulo, s_sum};
   const uint32_t nwg_next = plan_shares(A, L, true);
   if (tid == 0) {
     A.bctl->nwg = nwg_next;
