@@ -1263,7 +1263,8 @@ struct PlanArrays {
 // of each pending realization (the previous pass's list) is cleared for the pass after.
 // Writes every logical workgroup's WgDesc and each pending realization's n_list; returns
 // the number of workgroups with a share.  Each thread reads a contiguous run of the map
-// words, kChunk at a time with the loads issued together.
+// words, kChunk at a time with the loads issued together (held from the first reading to
+// the second when the run is one chunk).
 __device__ uint32_t plan_shares(const BatchArgs& A, const PlanArrays& L, bool clear_other) {
   constexpr uint32_t kChunk = 8;
   const uint32_t tid = threadIdx.x, count = A.count, G = A.sweep_grid;
@@ -1377,6 +1378,8 @@ __device__ uint32_t plan_shares(const BatchArgs& A, const PlanArrays& L, bool cl
   for (uint32_t v = 0; v < tid / kWave; ++v) gp += s_wave_tot[v];
   if (g0 < g1) {
     uint32_t r = r0, rbase = L.wo[r0], rend = L.wo[r0 + 1];
+    // the realization of the words in hand and the first share not yet placed
+    uint32_t cr = kNoReal, nr = 0, w0 = 0, Gr = 0, npr = 0, knext = 0;
     for (uint32_t c0 = g0; c0 < g1; c0 += kChunk) {
       if (!one_chunk) load_chunk(c0, r, rbase, rend);  // (a run of one chunk is still held)
 #pragma unroll
@@ -1384,14 +1387,21 @@ __device__ uint32_t plan_shares(const BatchArgs& A, const PlanArrays& L, bool cl
         if (c0 + k >= g1) break;
         const uint32_t rr = wr[k], word = wv[k];
         const uint32_t pop = (uint32_t)__builtin_popcount(word);
-        const uint32_t nr = L.n[rr], w0 = L.wg[rr], Gr = L.wg[rr + 1] - w0;
+        if (rr != cr) {
+          cr = rr;
+          nr = L.n[rr];
+          w0 = L.wg[rr];
+          Gr = L.wg[rr + 1] - w0;
+          npr = L.np[rr];
+          knext = Gr ? floor_div53((uint64_t)(gp - npr) * Gr + nr - 1u, nr) : 0u;
+        }
         if (pop && Gr) {
-          const uint32_t pre = gp - L.np[rr];
-          const uint32_t k0 = floor_div53((uint64_t)pre * Gr + nr - 1u, nr);
+          const uint32_t pre = gp - npr;
           const uint32_t k1 = min(Gr, floor_div53((uint64_t)(pre + pop) * Gr + nr - 1u, nr));
-          for (uint32_t ks = k0; ks < k1; ++ks)
+          for (uint32_t ks = knext; ks < k1; ++ks)
             L.ulo[w0 + ks] =
                 32u * wl[k] + select_bit(word, floor_div53((uint64_t)nr * ks, Gr) - pre);
+          knext = k1;
         }
         gp += pop;
       }
