@@ -1727,9 +1727,16 @@ struct TileImage {
 };
 
 static_assert(kCandCap <= kTileVoxels / 2, "the candidate list lives in the row bytes");
+
+// Words of a workgroup's LDS copy of the next map (the tiles of kMarkWords * 32 indices).
+constexpr uint32_t kMarkWords = 64;
+
 // Four images (one workgroup of 256 threads) plus the workgroup's own LDS must stay
-// within a fifth of the compute unit's 160 KiB, so that five workgroups fit.
-static_assert(4 * sizeof(TileImage) + 1024 <= 160 * 1024 / 5, "tile image too large");
+// within a fifth of the compute unit's 160 KiB, so that five workgroups fit.  LDS is
+// granted in granules of 1280 bytes: a fifth holds 25 of them, 32000 bytes, of which the
+// images take 30912 and the static arrays (tile block, directions, counters, marks) the
+// rest.
+static_assert(4 * sizeof(TileImage) + 544 + 4 * kMarkWords <= 32000, "tile image too large");
 
 // The 26-bit void mask (direction order) of front voxel (xl, jy, jz) of the image: the
 // three bits x - 1, x, x + 1 of each of the nine neighbouring rows are bits xl..xl + 2
@@ -1781,6 +1788,7 @@ void k_sweep(BatchArgs A) {
   __shared__ uint32_t s_dhi[32];  // 26..31: 0, read for the empty slots of a block
   __shared__ uint32_t s_key[2];
   __shared__ uint32_t s_kept, s_grown, s_draws, s_blocks, s_next, s_nb;
+  __shared__ uint32_t s_marks[kMarkWords];
   const uint32_t G = gridDim.x;
   // logical workgroup index: XCD x (workgroups b with b % 8 == x) holds [x G/8, (x+1) G/8)
   const uint32_t beta = (blockIdx.x % kNumXcd) * (G / kNumXcd) + blockIdx.x / kNumXcd;
@@ -1793,7 +1801,13 @@ void k_sweep(BatchArgs A) {
     s_draws = 0;
     s_blocks = 0;
   }
+  for (uint32_t w = threadIdx.x; w < kMarkWords; w += blockDim.x) s_marks[w] = 0;
   const uint32_t r = uniform(D.r);
+  // the next map's words [mark_lo / 32, mark_lo / 32 + kMarkWords) are set in LDS when
+  // they hold every tile this workgroup can list, then or-ed into the map at the end
+  uint32_t mark_lo = 0;
+  bool lds_marks = false;
+  uint32_t* map_flush = nullptr;
   if (r != kNoReal) {
     Real& R = A.reals[r];
     Ctl& c = R.ctl;
@@ -1849,6 +1863,12 @@ void k_sweep(BatchArgs A) {
     uint32_t* const maps = (uint32_t*)uniform64((uint64_t)R.maps);
     const g_u32* __restrict__ map_in = (const g_u32*)(maps + (uniform(c.cur) ? mw : 0u));
     uint32_t* __restrict__ map_out = maps + (uniform(c.cur) ? 0u : mw);
+    {
+      const uint32_t reach = ntx * tl.nty + ntx + 1u;  // index distance of a neighbour tile
+      mark_lo = (u_lo > reach ? u_lo - reach : 0u) & ~31u;
+      lds_marks = !full && (uint64_t)u_hi + reach - mark_lo <= 32ull * kMarkWords;
+      map_flush = map_out + (mark_lo >> 5);
+    }
     uint32_t kept_w = 0, grown_w = 0, draws_l = 0, blocks_l = 0;
     uint32_t taken = 0;  // listed tiles of the share in the blocks before this one
     for (uint32_t ub = u_lo; ub < u_hi; ub += kWave) {
@@ -2100,7 +2120,10 @@ void k_sweep(BatchArgs A) {
           const int ox = (int)lane % 3 - 1, oy = (int)(lane / 3) % 3 - 1, oz = (int)lane / 9 - 1;
           const uint32_t un =
               (uint32_t)((int32_t)u + ox + (int32_t)tl.ntx * (oy + (int32_t)tl.nty * oz));
-          global_or_nr(map_out + (un >> 5), 1u << (un & 31u));
+          if (lds_marks)
+            atomicOr(&s_marks[(un - mark_lo) >> 5], 1u << (un & 31u));
+          else
+            global_or_nr(map_out + (un >> 5), 1u << (un & 31u));
         }
       }
       taken += nb;
@@ -2114,6 +2137,12 @@ void k_sweep(BatchArgs A) {
     }
   }
   __syncthreads();
+  if (lds_marks) {  // (uniform)
+    for (uint32_t w = threadIdx.x; w < kMarkWords; w += blockDim.x) {
+      const uint32_t v = s_marks[w];
+      if (v) global_or_nr(map_flush + w, v);
+    }
+  }
   if (r != kNoReal && threadIdx.x == 0)
     A.rec[beta] = WgRec{r, s_kept, s_grown, s_draws, s_blocks, {0u, 0u, 0u}};
 }
