@@ -88,7 +88,7 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
   if (ws_bytes < G.total)
     return fail(QSGS_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", G.total, ws_bytes);
   Engine E;
-  E.bind(ws, G.P, (size_t)count, s);
+  E.bind(ws, G.P, (size_t)count, s, walls);
   E.no_events = no_alloc || async;
   E.async = async;
   E.stage = (no_alloc || async) ? nullptr

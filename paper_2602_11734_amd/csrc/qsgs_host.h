@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -315,32 +316,66 @@ struct Tuning {
   bool graphs = true;          // passes as launches of captured chunk graphs
 };
 
-// Workgroups of k_sweep (block threads each) that the current device holds at once:
-// one round of them takes every list share at the same time, and no share waits for a
-// slot.  2048 when the runtime cannot say.
-// Computed once per device and block size (the later calls may be under graph capture).
-inline uint32_t resident_sweep_grid(uint32_t block) {
+// LDS is granted to a workgroup in whole granules of this many bytes (gfx950: 128 of them
+// per compute unit).  The runtime's occupancy query divides the bytes exactly and so can
+// promise one workgroup per compute unit more than the granules allow: measured, 26 880
+// bytes (21 granules) fit six workgroups and 26 881 five, though the query says six up to
+// 27 306; 32 000 bytes fit five and 32 001 four.
+constexpr size_t kLdsGranule = 1280;
+
+// Workgroups of one k_sweep variant (block threads each) that a compute unit of device
+// dev holds at once: the runtime's occupancy (registers, waves) capped by the LDS
+// granules; 0 when the runtime cannot say.
+template <bool kWalls, bool kLiteral>
+int sweep_per_cu(int dev, uint32_t block) {
+  int per_cu = 0, lds_cu = 0;
+  hipFuncAttributes fa{};
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<kWalls, kLiteral>,
+                                                   (int)block,
+                                                   sweep_lds_bytes(block)) != hipSuccess ||
+      hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_sweep<kWalls, kLiteral>)) !=
+          hipSuccess ||
+      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+          hipSuccess ||
+      per_cu <= 0 || lds_cu <= 0) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const size_t wg = (fa.sharedSizeBytes + sweep_lds_bytes(block) + kLdsGranule - 1) /
+                    kLdsGranule * kLdsGranule;
+  return std::min<int>(per_cu, (int)((size_t)lds_cu / wg));
+}
+
+// Workgroups of k_sweep (block threads each; the variants for grids with other phases'
+// cells when walls) that the current device holds at once: one round of them takes every
+// list share at the same time, and no share waits for a slot.  2048 when the runtime
+// cannot say.
+// Computed once per device, block size and variant pair (the later calls may be under
+// graph capture).
+inline uint32_t resident_sweep_grid(uint32_t block, bool walls) {
   static std::mutex mu;
-  static std::map<std::pair<int, uint32_t>, uint32_t> known;
-  int dev = 0, cus = 0, per_cu = 0;
+  static std::map<std::tuple<int, uint32_t, bool>, uint32_t> known;
+  int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     (void)hipGetLastError();
     return 2048;
   }
   std::lock_guard<std::mutex> lk(mu);
-  const auto it = known.find({dev, block});
+  const auto it = known.find({dev, block, walls});
   if (it != known.end()) return it->second;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep<false, false>,
-                                                   (int)block,
-                                                   sweep_lds_bytes(block)) != hipSuccess ||
-      cus <= 0 || per_cu <= 0) {
+      cus <= 0) {
     (void)hipGetLastError();
     return 2048;
   }
+  const int per_cu = walls ? std::min(sweep_per_cu<true, false>(dev, block),
+                                      sweep_per_cu<true, true>(dev, block))
+                           : std::min(sweep_per_cu<false, false>(dev, block),
+                                      sweep_per_cu<false, true>(dev, block));
+  if (per_cu <= 0) return 2048;
   const uint32_t n = (uint32_t)cus * (uint32_t)per_cu;
   const uint32_t g = std::max<uint32_t>(kNumXcd, n / kNumXcd * kNumXcd);
-  known[{dev, block}] = g;
+  known[{dev, block, walls}] = g;
   return g;
 }
 
@@ -453,7 +488,9 @@ struct Engine {
   char* st_dn_live() { return st_dn_reals() + align_up(sizeof(Real) * reals.size()); }
 
   // Binds the engine to a persistent region of `count` records at `base`.
-  void bind(void* base, const PersistLayout& L, size_t count, hipStream_t stream) {
+  // walls: the records' grids may hold other phases' cells (the sweep variants for them).
+  void bind(void* base, const PersistLayout& L, size_t count, hipStream_t stream,
+            bool walls = false) {
     ws = base;
     P = L;
     s = stream;
@@ -467,7 +504,8 @@ struct Engine {
     args.live = at<uint32_t>(base, L.live);
     args.rec = at<WgRec>(base, L.rec);
     args.desc = at<WgDesc>(base, L.desc);
-    const uint32_t g = tune.grow_grid ? tune.grow_grid : resident_sweep_grid(tune.grow_block);
+    const uint32_t g =
+        tune.grow_grid ? tune.grow_grid : resident_sweep_grid(tune.grow_block, walls);
     const uint32_t want = std::max<uint32_t>(g, 2 * (uint32_t)count);
     sweep_grid = std::min<uint32_t>(kMaxSweepGrid, (want + kNumXcd - 1) / kNumXcd * kNumXcd);
     args.sweep_grid = sweep_grid;

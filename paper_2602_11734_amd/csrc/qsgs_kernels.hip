@@ -1702,6 +1702,8 @@ __device__ __forceinline__ uint32_t min_half(const U4& H) {
 
 // Capacity of a wavefront's list of candidate blocks (drained when a round could overflow it).
 constexpr uint32_t kCandCap = 256;
+// Front voxels of a tile queued at once (a tile with more takes them in chunks).
+constexpr uint32_t kQueueCap = 512;
 
 // LDS image of one tile at the step's start.  Halo row h = hy + 6 hz (hy, hz in 0..5)
 // covers y = y0 - 1 + hy, z = z0 - 1 + hz; interior row i = jy + 4 jz is halo row
@@ -1716,27 +1718,27 @@ struct TileImage {
     uint64_t S[kTileRows];   // solid (interior rows), until the front rows are found
     uint32_t hist[32];       // then: void-count histogram, then bucket cursors
   };
-  uint32_t W[kTileVoxels];   // per queued front voxel: void mask (direction order) | x << 26
-  uint16_t qo[kTileVoxels];  // the queue (interior row << 6 | x - x0), then its order by
+  uint32_t W[kQueueCap];     // per queued front voxel: void mask (direction order) | x << 26
+  uint16_t qo[kQueueCap];    // the queue (interior row << 6 | x - x0), then its order by
                              // void count, heaviest first (queue slot | interior row << 10)
   union {
-    uint8_t row[kTileVoxels];  // interior row of each queued voxel (until the order is made)
+    uint8_t row[kQueueCap];    // interior row of each queued voxel (until the order is made)
     uint16_t cand[kCandCap];   // then: blocks that may hold a passing rank
                                // (queue slot << 2 | block | interior row << 12)
   };
 };
 
-static_assert(kCandCap <= kTileVoxels / 2, "the candidate list lives in the row bytes");
+static_assert(kCandCap <= kQueueCap / 2, "the candidate list lives in the row bytes");
+static_assert(kQueueCap <= 1024 && kQueueCap % kWave == 0, "queue slots are 10-bit fields");
 
 // Words of a workgroup's LDS copy of the next map (the tiles of kMarkWords * 32 indices).
 constexpr uint32_t kMarkWords = 64;
 
 // Four images (one workgroup of 256 threads) plus the workgroup's own LDS must stay
-// within a fifth of the compute unit's 160 KiB, so that five workgroups fit.  LDS is
-// granted in granules of 1280 bytes: a fifth holds 25 of them, 32000 bytes, of which the
-// images take 30912 and the static arrays (tile block, directions, counters, marks) the
-// rest.
-static_assert(4 * sizeof(TileImage) + 544 + 4 * kMarkWords <= 32000, "tile image too large");
+// within a sixth of the compute unit's 160 KiB, so that six workgroups fit.  LDS is
+// granted in granules of 1280 bytes: a sixth holds 21 of them, 26880 bytes, for the
+// images and the static arrays (tile block, directions, counters, marks).
+static_assert(4 * sizeof(TileImage) + 544 + 4 * kMarkWords <= 26880, "tile image too large");
 
 // The 26-bit void mask (direction order) of front voxel (xl, jy, jz) of the image: the
 // three bits x - 1, x, x + 1 of each of the nine neighbouring rows are bits xl..xl + 2
@@ -1777,10 +1779,11 @@ size_t sweep_lds_bytes(uint32_t block) { return sizeof(TileImage) * (block / kWa
 // neither void nor sources.  kLiteral: a realization with the literal front rule takes
 // as sources, from its second step on, only the voxels grown in the previous step
 // (its marks that its tile's fold has not yet moved into S).
-// At most 96 VGPRs: five waves per SIMD, the occupancy the per-wave LDS images
-// (< 8 KB each) allow at the default 256-thread workgroup.
+// At most 80 VGPRs: six waves per SIMD, which the per-wave LDS images (4.1 KB each)
+// allow at the default 256-thread workgroup; the variants for other phases' cells need
+// more registers and run five waves per SIMD (96 VGPRs).
 template <bool kWalls, bool kLiteral>
-__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(kWalls ? 5 : 6)))
 void k_sweep(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char sweep_lds[];
   __shared__ uint32_t s_tiles[kWave];
@@ -2004,112 +2007,123 @@ void k_sweep(BatchArgs A) {
         const uint32_t nq = uniform(nq_l);
         kept_w += nq;
         if (!run || nq == 0) continue;
-        for (uint32_t c = piece; c; c &= c - 1u)
-          T.qo[pos++] = (uint16_t)((lane >> 2) << 6 | (lane & 3u) * 16u | (uint32_t)__builtin_ctz(c));
-        wave_sync();
-        // 4. void masks of the queue, then a counting sort of the queue by void count
-        // so that the lanes of one round draw similar numbers of blocks and slots
-        if (lane < 32u) T.hist[lane] = 0;
-        wave_sync();
-        for (uint32_t qi = lane; qi < nq; qi += kWave) {
-          const uint32_t ent = T.qo[qi];
-          const int i = (int)(ent >> 6), xl = (int)(ent & 63u);
-          const uint32_t vm = tile_void_mask(T, xl, i % kTileY, i / kTileY);
-          T.W[qi] = vm | (uint32_t)xl << 26;
-          T.row[qi] = (uint8_t)i;
-          atomicAdd(&T.hist[__builtin_popcount(vm)], 1u);
-        }
-        wave_sync();
-        {
-          const uint32_t hc = lane < 32u ? T.hist[lane] : 0u;
-          const uint32_t hin = wave_incl_sum(hc);
-          if (lane < 32u) T.hist[lane] = hin - hc;
-        }
-        wave_sync();
-        // (the queue has been read: its slots now take the order, heaviest first, so that
-        // a tile's last, partial round holds the lightest voxels)
-        for (uint32_t qi = lane; qi < nq; qi += kWave)
-          T.qo[nq - 1u - atomicAdd(&T.hist[__builtin_popcount(T.W[qi] & 0x3FFFFFFu)], 1u)] =
-              (uint16_t)(qi | (uint32_t)T.row[qi] << 10);
-        wave_sync();
-        // 5. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1)), in two
-        // phases.  A: every block of high halves is drawn and kept only if one of its
-        // half-words is at or below the largest high-half threshold (no rank of it can
-        // pass otherwise); kept blocks go to the LDS list.  B: each listed block is drawn
-        // again and its ranks are decided exactly and claimed, 64 blocks per round.
-        uint32_t tm = 0, grown = 0, ncand = 0;
+        uint32_t tm = 0, grown = 0;  // step 5 over the whole queue
         uint32_t hmax = max(th.hi_face, max(th.hi_edge, th.hi_corner));
         if (itab) hmax = max(hmax, max(R.ihi_max[0], max(R.ihi_max[1], R.ihi_max[2])));
-        auto drain = [&]() {
+        // steps 4 and 5 take the queue kQueueCap voxels at a time, in queue order
+        for (uint32_t cb = 0; cb < nq; cb += kQueueCap) {
+          const uint32_t nc = min(nq - cb, kQueueCap);
+          wave_sync();  // the previous chunk's queue, order and candidates are consumed
+          {
+            uint32_t p = pos - cb;  // (modulo 2^32: positions before the chunk wrap)
+            for (uint32_t c = piece; c; c &= c - 1u, ++p)
+              if (p < kQueueCap)
+                T.qo[p] = (uint16_t)((lane >> 2) << 6 | (lane & 3u) * 16u |
+                                     (uint32_t)__builtin_ctz(c));
+          }
           wave_sync();
-          for (uint32_t c0 = 0; c0 < ncand; c0 += kWave) {
-            if (c0 + lane < ncand) {
-              const uint32_t e = T.cand[c0 + lane];
-              const uint32_t qi = (e >> 2) & 1023u, blk = e & 3u;
-              const uint32_t w = T.W[qi];
-              const int i = (int)(e >> 12), xl = (int)(w >> 26);
-              const int jy = i % kTileY, jz = i / kTileY;
-              const uint32_t m = drop_low_ranks(w & 0x3FFFFFFu, 8u * blk);  // earlier blocks'
-              const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
-                                 (uint32_t)(z0 + jz) * g.nxy;
-              uint32_t passed = 0;
-              const uint32_t rb = ((uint32_t)(y0 + jy) + (uint32_t)g.ny * (uint32_t)(z0 + jz)) *
-                                  (2u * ntx);
-              grown += sweep_block<kWalls>(mark32, k0, k1, s_key, s_drow, s_dhi, a, rb,
-                                           (uint32_t)(x0 + xl), t, blk, m, th, &passed, g,
-                                           labels, itab);
-              // passing ranks whose target leaves this tile list the target's tile (this
-              // tile is listed anyway); first claim or not, the target was void
-              const uint32_t leave = (xl == 0 ? kDxNeg : 0u) | (xl == kTileX - 1 ? kDxPos : 0u) |
-                                     (jy == 0 ? kDyNeg : 0u) | (jy == kTileY - 1 ? kDyPos : 0u) |
-                                     (jz == 0 ? kDzNeg : 0u) | (jz == kTileZ - 1 ? kDzPos : 0u);
-              uint32_t out = passed & leave;
-              while (out) {
-                const int d = __builtin_ctz(out);
-                out &= out - 1u;
-                const int xn = xl + dir_field(kDirDX, d) - 1, yn = jy + dir_field(kDirDY, d) - 1,
-                          zn = jz + dir_field(kDirDZ, d) - 1;
-                const int ox = xn < 0 ? 0 : (xn >= kTileX ? 2 : 1);
-                const int oy = yn < 0 ? 0 : (yn >= kTileY ? 2 : 1);
-                const int oz = zn < 0 ? 0 : (zn >= kTileZ ? 2 : 1);
-                tm |= 1u << (ox + 3 * oy + 9 * oz);
+          // 4. void masks of the queue, then a counting sort of the queue by void count
+          // so that the lanes of one round draw similar numbers of blocks and slots
+          if (lane < 32u) T.hist[lane] = 0;
+          wave_sync();
+          for (uint32_t qi = lane; qi < nc; qi += kWave) {
+            const uint32_t ent = T.qo[qi];
+            const int i = (int)(ent >> 6), xl = (int)(ent & 63u);
+            const uint32_t vm = tile_void_mask(T, xl, i % kTileY, i / kTileY);
+            T.W[qi] = vm | (uint32_t)xl << 26;
+            T.row[qi] = (uint8_t)i;
+            atomicAdd(&T.hist[__builtin_popcount(vm)], 1u);
+          }
+          wave_sync();
+          {
+            const uint32_t hc = lane < 32u ? T.hist[lane] : 0u;
+            const uint32_t hin = wave_incl_sum(hc);
+            if (lane < 32u) T.hist[lane] = hin - hc;
+          }
+          wave_sync();
+          // (the queue has been read: its slots now take the order, heaviest first, so that
+          // a tile's last, partial round holds the lightest voxels)
+          for (uint32_t qi = lane; qi < nc; qi += kWave)
+            T.qo[nc - 1u - atomicAdd(&T.hist[__builtin_popcount(T.W[qi] & 0x3FFFFFFu)], 1u)] =
+                (uint16_t)(qi | (uint32_t)T.row[qi] << 10);
+          wave_sync();
+          // 5. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1)), in two
+          // phases.  A: every block of high halves is drawn and kept only if one of its
+          // half-words is at or below the largest high-half threshold (no rank of it can
+          // pass otherwise); kept blocks go to the LDS list.  B: each listed block is drawn
+          // again and its ranks are decided exactly and claimed, 64 blocks per round.
+          uint32_t ncand = 0;
+          auto drain = [&]() {
+            wave_sync();
+            for (uint32_t c0 = 0; c0 < ncand; c0 += kWave) {
+              if (c0 + lane < ncand) {
+                const uint32_t e = T.cand[c0 + lane];
+                const uint32_t qi = (e >> 2) & 1023u, blk = e & 3u;
+                const uint32_t w = T.W[qi];
+                const int i = (int)(e >> 12), xl = (int)(w >> 26);
+                const int jy = i % kTileY, jz = i / kTileY;
+                const uint32_t m = drop_low_ranks(w & 0x3FFFFFFu, 8u * blk);  // earlier blocks'
+                const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
+                                   (uint32_t)(z0 + jz) * g.nxy;
+                uint32_t passed = 0;
+                const uint32_t rb = ((uint32_t)(y0 + jy) + (uint32_t)g.ny * (uint32_t)(z0 + jz)) *
+                                    (2u * ntx);
+                grown += sweep_block<kWalls>(mark32, k0, k1, s_key, s_drow, s_dhi, a, rb,
+                                             (uint32_t)(x0 + xl), t, blk, m, th, &passed, g,
+                                             labels, itab);
+                // passing ranks whose target leaves this tile list the target's tile (this
+                // tile is listed anyway); first claim or not, the target was void
+                const uint32_t leave = (xl == 0 ? kDxNeg : 0u) | (xl == kTileX - 1 ? kDxPos : 0u) |
+                                       (jy == 0 ? kDyNeg : 0u) | (jy == kTileY - 1 ? kDyPos : 0u) |
+                                       (jz == 0 ? kDzNeg : 0u) | (jz == kTileZ - 1 ? kDzPos : 0u);
+                uint32_t out = passed & leave;
+                while (out) {
+                  const int d = __builtin_ctz(out);
+                  out &= out - 1u;
+                  const int xn = xl + dir_field(kDirDX, d) - 1, yn = jy + dir_field(kDirDY, d) - 1,
+                            zn = jz + dir_field(kDirDZ, d) - 1;
+                  const int ox = xn < 0 ? 0 : (xn >= kTileX ? 2 : 1);
+                  const int oy = yn < 0 ? 0 : (yn >= kTileY ? 2 : 1);
+                  const int oz = zn < 0 ? 0 : (zn >= kTileZ ? 2 : 1);
+                  tm |= 1u << (ox + 3 * oy + 9 * oz);
+                }
+              }
+            }
+            ncand = 0;
+            wave_sync();
+          };
+          for (uint32_t kb = 0; kb < nc; kb += kWave) {
+            const uint32_t k = kb + lane;
+            uint32_t qe = 0, nb = 0, a = 0;
+            if (k < nc) {
+              qe = T.qo[k];
+              const uint32_t w = T.W[qe & 1023u];
+              const int i = (int)(qe >> 10), xl = (int)(w >> 26);
+              const uint32_t nv = (uint32_t)__builtin_popcount(w & 0x3FFFFFFu);
+              nb = (nv + 7u) >> 3;
+              draws_l += nv;
+              blocks_l += nb;
+              a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + i % kTileY) * (uint32_t)g.nx +
+                  (uint32_t)(z0 + i / kTileY) * g.nxy;
+            }
+            // the queue runs heaviest first, so the round's first lane has the most blocks
+            const uint32_t nbmax = uniform((uint32_t)__builtin_amdgcn_readfirstlane(nb));
+            for (uint32_t blk = 0; blk < nbmax; ++blk) {
+              bool keep = false;
+              if (blk < nb) keep = min_half(philox10(a, t, blk, kTagGrowHi, k0, k1)) <= hmax;
+              const uint64_t kept = __ballot(keep);
+              if (kept) {
+                if (keep)
+                  T.cand[ncand + __builtin_amdgcn_mbcnt_hi((uint32_t)(kept >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u))] =
+                      (uint16_t)((qe & 1023u) << 2 | blk | (qe >> 10) << 12);
+                ncand += (uint32_t)__popcll(kept);
+                if (ncand > kCandCap - kWave) drain();
               }
             }
           }
-          ncand = 0;
-          wave_sync();
-        };
-        for (uint32_t kb = 0; kb < nq; kb += kWave) {
-          const uint32_t k = kb + lane;
-          uint32_t qe = 0, nb = 0, a = 0;
-          if (k < nq) {
-            qe = T.qo[k];
-            const uint32_t w = T.W[qe & 1023u];
-            const int i = (int)(qe >> 10), xl = (int)(w >> 26);
-            const uint32_t nv = (uint32_t)__builtin_popcount(w & 0x3FFFFFFu);
-            nb = (nv + 7u) >> 3;
-            draws_l += nv;
-            blocks_l += nb;
-            a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + i % kTileY) * (uint32_t)g.nx +
-                (uint32_t)(z0 + i / kTileY) * g.nxy;
-          }
-          // the queue runs heaviest first, so the round's first lane has the most blocks
-          const uint32_t nbmax = uniform((uint32_t)__builtin_amdgcn_readfirstlane(nb));
-          for (uint32_t blk = 0; blk < nbmax; ++blk) {
-            bool keep = false;
-            if (blk < nb) keep = min_half(philox10(a, t, blk, kTagGrowHi, k0, k1)) <= hmax;
-            const uint64_t kept = __ballot(keep);
-            if (kept) {
-              if (keep)
-                T.cand[ncand + __builtin_amdgcn_mbcnt_hi((uint32_t)(kept >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u))] =
-                    (uint16_t)((qe & 1023u) << 2 | blk | (qe >> 10) << 12);
-              ncand += (uint32_t)__popcll(kept);
-              if (ncand > kCandCap - kWave) drain();
-            }
-          }
+          if (ncand) drain();
         }
-        if (ncand) drain();
         grown_w += wave_sum(grown);
         if (full) continue;  // the all-tiles form lists every tile anyway
         // 6. list the tiles that may hold F_{t+1} for the next pass: this tile (it has
