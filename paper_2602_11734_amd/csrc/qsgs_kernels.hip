@@ -1700,10 +1700,18 @@ __device__ __forceinline__ uint32_t min_half(const U4& H) {
   return min((uint32_t)c.x, (uint32_t)c.y);
 }
 
-// Capacity of a wavefront's list of candidate blocks (drained when a round could overflow it).
-constexpr uint32_t kCandCap = 256;
 // Front voxels of a tile queued at once (a tile with more takes them in chunks).
 constexpr uint32_t kQueueCap = 512;
+// Entries of a wavefront's ring of kept blocks: fewer than 64 wait between rounds, and one
+// reject iteration adds at most 64.
+constexpr uint32_t kRing = 2 * kWave;
+
+// A kept block, self-contained so that it can wait across tiles: the voxel, its void mask
+// (direction order) and the block index.
+struct RingEntry {
+  uint32_t x, y, z;
+  uint32_t mb;  // void mask | block << 26
+};
 
 // LDS image of one tile at the step's start.  Halo row h = hy + 6 hz (hy, hz in 0..5)
 // covers y = y0 - 1 + hy, z = z0 - 1 + hz; interior row i = jy + 4 jz is halo row
@@ -1721,14 +1729,11 @@ struct TileImage {
   uint32_t W[kQueueCap];     // per queued front voxel: void mask (direction order) | x << 26
   uint16_t qo[kQueueCap];    // the queue (interior row << 6 | x - x0), then its order by
                              // void count, heaviest first (queue slot | interior row << 10)
-  union {
-    uint8_t row[kQueueCap];    // interior row of each queued voxel (until the order is made)
-    uint16_t cand[kCandCap];   // then: blocks that may hold a passing rank
-                               // (queue slot << 2 | block | interior row << 12)
-  };
+  uint8_t row[kQueueCap];    // interior row of each queued voxel (until the order is made)
+  // the wavefront's kept blocks (phase B's list; it outlives the tile)
+  RingEntry ring[kRing] __attribute__((aligned(16)));
 };
 
-static_assert(kCandCap <= kQueueCap / 2, "the candidate list lives in the row bytes");
 static_assert(kQueueCap <= 1024 && kQueueCap % kWave == 0, "queue slots are 10-bit fields");
 
 // Words of a workgroup's LDS copy of the next map (the tiles of kMarkWords * 32 indices).
@@ -1872,8 +1877,53 @@ void k_sweep(BatchArgs A) {
       lds_marks = !full && (uint64_t)u_hi + reach - mark_lo <= 32ull * kMarkWords;
       map_flush = map_out + (mark_lo >> 5);
     }
-    uint32_t kept_w = 0, grown_w = 0, draws_l = 0, blocks_l = 0;
+    uint32_t kept_w = 0, draws_l = 0, blocks_l = 0;
+    uint32_t grown = 0;  // voxels grown by this lane's claims
     uint32_t taken = 0;  // listed tiles of the share in the blocks before this one
+    // the next map's bit of tile un
+    auto mark_tile = [&](uint32_t un) {
+      if (lds_marks)
+        atomicOr(&s_marks[(un - mark_lo) >> 5], 1u << (un & 31u));
+      else
+        global_or_nr(map_out + (un >> 5), 1u << (un & 31u));
+    };
+    // Phase B of step 5 (below): the wavefront's kept blocks wait in a ring across tiles,
+    // entries [head, tail), and are decided 64 at a time, so that every round but the
+    // share's last is full.  Each entry is drawn again, its ranks decided exactly and
+    // claimed; a passing rank whose target leaves the entry's tile lists the target's tile
+    // (first claim or not: the target was void).
+    uint32_t head = 0, tail = 0;  // (uniform)
+    auto decide_round = [&](uint32_t n) {  // the n <= 64 entries from head
+      wave_sync();
+      if (lane < n) {
+        const RingEntry e = T.ring[(head + lane) & (kRing - 1u)];
+        const uint32_t blk = e.mb >> 26;
+        const uint32_t m = drop_low_ranks(e.mb & 0x3FFFFFFu, 8u * blk);  // earlier blocks'
+        const uint32_t a = e.x + e.y * (uint32_t)g.nx + e.z * g.nxy;
+        const uint32_t rb = (e.y + (uint32_t)g.ny * e.z) * (2u * ntx);
+        uint32_t passed = 0;
+        grown += sweep_block<kWalls>(mark32, k0, k1, s_key, s_drow, s_dhi, a, rb, e.x, t, blk,
+                                     m, th, &passed, g, labels, itab);
+        if (!full) {  // (the all-tiles form lists every tile anyway)
+          const uint32_t xl = e.x % kTileX, jy = e.y % kTileY, jz = e.z % kTileZ;
+          const uint32_t leave = (xl == 0 ? kDxNeg : 0u) | (xl == kTileX - 1 ? kDxPos : 0u) |
+                                 (jy == 0 ? kDyNeg : 0u) | (jy == kTileY - 1 ? kDyPos : 0u) |
+                                 (jz == 0 ? kDzNeg : 0u) | (jz == kTileZ - 1 ? kDzPos : 0u);
+          uint32_t out = passed & leave;
+          while (out) {
+            const int d = __builtin_ctz(out);
+            out &= out - 1u;
+            // the target (in the domain: its claim was issued)
+            const uint32_t xn = e.x + (uint32_t)dir_field(kDirDX, d) - 1u,
+                           yn = e.y + (uint32_t)dir_field(kDirDY, d) - 1u,
+                           zn = e.z + (uint32_t)dir_field(kDirDZ, d) - 1u;
+            mark_tile(xn / kTileX + ntx * (yn / kTileY + tl.nty * (zn / kTileZ)));
+          }
+        }
+      }
+      head += n;
+      wave_sync();
+    };
     for (uint32_t ub = u_lo; ub < u_hi; ub += kWave) {
       __syncthreads();  // the previous block of tiles is consumed
       if (threadIdx.x < (uint32_t)kWave) {
@@ -2007,7 +2057,6 @@ void k_sweep(BatchArgs A) {
         const uint32_t nq = uniform(nq_l);
         kept_w += nq;
         if (!run || nq == 0) continue;
-        uint32_t tm = 0, grown = 0;  // step 5 over the whole queue
         uint32_t hmax = max(th.hi_face, max(th.hi_edge, th.hi_corner));
         if (itab) hmax = max(hmax, max(R.ihi_max[0], max(R.ihi_max[1], R.ihi_max[2])));
         // steps 4 and 5 take the queue kQueueCap voxels at a time, in queue order
@@ -2050,61 +2099,24 @@ void k_sweep(BatchArgs A) {
           // 5. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1)), in two
           // phases.  A: every block of high halves is drawn and kept only if one of its
           // half-words is at or below the largest high-half threshold (no rank of it can
-          // pass otherwise); kept blocks go to the LDS list.  B: each listed block is drawn
-          // again and its ranks are decided exactly and claimed, 64 blocks per round.
-          uint32_t ncand = 0;
-          auto drain = [&]() {
-            wave_sync();
-            for (uint32_t c0 = 0; c0 < ncand; c0 += kWave) {
-              if (c0 + lane < ncand) {
-                const uint32_t e = T.cand[c0 + lane];
-                const uint32_t qi = (e >> 2) & 1023u, blk = e & 3u;
-                const uint32_t w = T.W[qi];
-                const int i = (int)(e >> 12), xl = (int)(w >> 26);
-                const int jy = i % kTileY, jz = i / kTileY;
-                const uint32_t m = drop_low_ranks(w & 0x3FFFFFFu, 8u * blk);  // earlier blocks'
-                const uint32_t a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + jy) * (uint32_t)g.nx +
-                                   (uint32_t)(z0 + jz) * g.nxy;
-                uint32_t passed = 0;
-                const uint32_t rb = ((uint32_t)(y0 + jy) + (uint32_t)g.ny * (uint32_t)(z0 + jz)) *
-                                    (2u * ntx);
-                grown += sweep_block<kWalls>(mark32, k0, k1, s_key, s_drow, s_dhi, a, rb,
-                                             (uint32_t)(x0 + xl), t, blk, m, th, &passed, g,
-                                             labels, itab);
-                // passing ranks whose target leaves this tile list the target's tile (this
-                // tile is listed anyway); first claim or not, the target was void
-                const uint32_t leave = (xl == 0 ? kDxNeg : 0u) | (xl == kTileX - 1 ? kDxPos : 0u) |
-                                       (jy == 0 ? kDyNeg : 0u) | (jy == kTileY - 1 ? kDyPos : 0u) |
-                                       (jz == 0 ? kDzNeg : 0u) | (jz == kTileZ - 1 ? kDzPos : 0u);
-                uint32_t out = passed & leave;
-                while (out) {
-                  const int d = __builtin_ctz(out);
-                  out &= out - 1u;
-                  const int xn = xl + dir_field(kDirDX, d) - 1, yn = jy + dir_field(kDirDY, d) - 1,
-                            zn = jz + dir_field(kDirDZ, d) - 1;
-                  const int ox = xn < 0 ? 0 : (xn >= kTileX ? 2 : 1);
-                  const int oy = yn < 0 ? 0 : (yn >= kTileY ? 2 : 1);
-                  const int oz = zn < 0 ? 0 : (zn >= kTileZ ? 2 : 1);
-                  tm |= 1u << (ox + 3 * oy + 9 * oz);
-                }
-              }
-            }
-            ncand = 0;
-            wave_sync();
-          };
+          // pass otherwise); kept blocks go to the wavefront's ring.  B (decide_round above):
+          // 64 kept blocks at a time are drawn again, decided exactly and claimed.
           for (uint32_t kb = 0; kb < nc; kb += kWave) {
             const uint32_t k = kb + lane;
-            uint32_t qe = 0, nb = 0, a = 0;
+            uint32_t nb = 0, a = 0, vx = 0, vy = 0, vz = 0, vm = 0;
             if (k < nc) {
-              qe = T.qo[k];
+              const uint32_t qe = T.qo[k];
               const uint32_t w = T.W[qe & 1023u];
-              const int i = (int)(qe >> 10), xl = (int)(w >> 26);
-              const uint32_t nv = (uint32_t)__builtin_popcount(w & 0x3FFFFFFu);
+              const uint32_t i = qe >> 10;
+              vm = w & 0x3FFFFFFu;
+              const uint32_t nv = (uint32_t)__builtin_popcount(vm);
               nb = (nv + 7u) >> 3;
               draws_l += nv;
               blocks_l += nb;
-              a = (uint32_t)(x0 + xl) + (uint32_t)(y0 + i % kTileY) * (uint32_t)g.nx +
-                  (uint32_t)(z0 + i / kTileY) * g.nxy;
+              vx = (uint32_t)x0 + (w >> 26);
+              vy = (uint32_t)y0 + i % kTileY;
+              vz = (uint32_t)z0 + i / kTileY;
+              a = vx + vy * (uint32_t)g.nx + vz * g.nxy;
             }
             // the queue runs heaviest first, so the round's first lane has the most blocks
             const uint32_t nbmax = uniform((uint32_t)__builtin_amdgcn_readfirstlane(nb));
@@ -2114,34 +2126,25 @@ void k_sweep(BatchArgs A) {
               const uint64_t kept = __ballot(keep);
               if (kept) {
                 if (keep)
-                  T.cand[ncand + __builtin_amdgcn_mbcnt_hi((uint32_t)(kept >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u))] =
-                      (uint16_t)((qe & 1023u) << 2 | blk | (qe >> 10) << 12);
-                ncand += (uint32_t)__popcll(kept);
-                if (ncand > kCandCap - kWave) drain();
+                  T.ring[(tail + __builtin_amdgcn_mbcnt_hi(
+                                     (uint32_t)(kept >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u))) &
+                         (kRing - 1u)] = RingEntry{vx, vy, vz, vm | blk << 26};
+                tail += (uint32_t)__popcll(kept);
+                if (tail - head >= (uint32_t)kWave) decide_round(kWave);
               }
             }
           }
-          if (ncand) drain();
         }
-        grown_w += wave_sum(grown);
-        if (full) continue;  // the all-tiles form lists every tile anyway
-        // 6. list the tiles that may hold F_{t+1} for the next pass: this tile (it has
-        // front voxels) and every tile that received a claim, by setting their bits in
-        // the next map (an atomic whose old value is not needed: nothing waits for it)
-        const uint32_t tmask = wave_or(tm) | 1u << 13;
-        if (lane < 27u && ((tmask >> lane) & 1u)) {
-          const int ox = (int)lane % 3 - 1, oy = (int)(lane / 3) % 3 - 1, oz = (int)lane / 9 - 1;
-          const uint32_t un =
-              (uint32_t)((int32_t)u + ox + (int32_t)tl.ntx * (oy + (int32_t)tl.nty * oz));
-          if (lds_marks)
-            atomicOr(&s_marks[(un - mark_lo) >> 5], 1u << (un & 31u));
-          else
-            global_or_nr(map_out + (un >> 5), 1u << (un & 31u));
-        }
+        // 6. list the tiles that may hold F_{t+1} for the next pass, by setting their bits
+        // in the next map (an atomic whose old value is not needed: nothing waits for it):
+        // this tile (it has front voxels) here, the tiles its claims reach in decide_round
+        if (!full && lane == 0) mark_tile(u);
       }
       taken += nb;
     }
+    if (tail != head) decide_round(tail - head);  // the share's last, partial round
+    const uint32_t grown_w = wave_sum(grown);
     const uint32_t draws_w = wave_sum(draws_l), blocks_w = wave_sum(blocks_l);
     if (lane == 0) {
       if (kept_w) atomicAdd(&s_kept, kept_w);
