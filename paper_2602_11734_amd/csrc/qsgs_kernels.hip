@@ -1722,16 +1722,12 @@ struct TileImage {
   // phases) in three words: bit i of the window (word i / 32, bit i % 32) is voxel
   // x0 - 1 + i, i < 66.
   uint32_t win[kHaloRows][3];
-  union {
-    uint64_t S[kTileRows];   // solid (interior rows), until the front rows are found
-    uint32_t hist[32];       // then: void-count histogram, then bucket cursors
-  };
-  uint32_t W[kQueueCap];     // per queued front voxel: void mask (direction order) | x << 26
-  uint16_t qo[kQueueCap];    // the queue (interior row << 6 | x - x0), then its order by
-                             // void count, heaviest first (queue slot | interior row << 10)
-  uint8_t row[kQueueCap];    // interior row of each queued voxel (until the order is made)
-  // the wavefront's kept blocks (phase B's list; it outlives the tile)
-  RingEntry ring[kRing] __attribute__((aligned(16)));
+  uint64_t S[kTileRows];     // solid (interior rows)
+  uint16_t qo[kQueueCap];    // the queue of front voxels (interior row << 6 | x - x0)
+  // the wavefront's blocks to draw (phase A) and its kept blocks (phase B); both outlive
+  // the tile
+  RingEntry bring[kRing] __attribute__((aligned(16)));
+  RingEntry kring[kRing] __attribute__((aligned(16)));
 };
 
 static_assert(kQueueCap <= 1024 && kQueueCap % kWave == 0, "queue slots are 10-bit fields");
@@ -1881,7 +1877,7 @@ void k_sweep(BatchArgs A) {
     uint32_t grown = 0;  // voxels grown by this lane's claims
     uint32_t taken = 0;  // listed tiles of the share in the blocks before this one
     // the next map's bit of tile un
-    auto mark_tile = [&](uint32_t un) {
+    auto mark_tile = [&](uint32_t un) __attribute__((always_inline)) {
       if (lds_marks)
         atomicOr(&s_marks[(un - mark_lo) >> 5], 1u << (un & 31u));
       else
@@ -1893,10 +1889,10 @@ void k_sweep(BatchArgs A) {
     // claimed; a passing rank whose target leaves the entry's tile lists the target's tile
     // (first claim or not: the target was void).
     uint32_t head = 0, tail = 0;  // (uniform)
-    auto decide_round = [&](uint32_t n) {  // the n <= 64 entries from head
+    auto decide_round = [&](uint32_t n) __attribute__((always_inline)) {  // the n <= 64 entries from head
       wave_sync();
       if (lane < n) {
-        const RingEntry e = T.ring[(head + lane) & (kRing - 1u)];
+        const RingEntry e = T.kring[(head + lane) & (kRing - 1u)];
         const uint32_t blk = e.mb >> 26;
         const uint32_t m = drop_low_ranks(e.mb & 0x3FFFFFFu, 8u * blk);  // earlier blocks'
         const uint32_t a = e.x + e.y * (uint32_t)g.nx + e.z * g.nxy;
@@ -1922,6 +1918,35 @@ void k_sweep(BatchArgs A) {
         }
       }
       head += n;
+      wave_sync();
+    };
+    // Phase A: the wavefront's blocks to draw wait in a ring across tiles too, entries
+    // [bhead, btail), and are drawn 64 at a time.  A block is kept (goes to the ring of
+    // phase B) only if one of its high half-words is at or below the largest high-half
+    // threshold: no rank of any other block can pass.
+    uint32_t hmax = max(th.hi_face, max(th.hi_edge, th.hi_corner));
+    if (itab) hmax = max(hmax, max(R.ihi_max[0], max(R.ihi_max[1], R.ihi_max[2])));
+    uint32_t bhead = 0, btail = 0;  // (uniform)
+    auto reject_round = [&](uint32_t n) __attribute__((always_inline)) {  // the n <= 64 entries from bhead
+      wave_sync();
+      RingEntry e{0u, 0u, 0u, 0u};
+      bool keep = false;
+      if (lane < n) {
+        e = T.bring[(bhead + lane) & (kRing - 1u)];
+        const uint32_t a = e.x + e.y * (uint32_t)g.nx + e.z * g.nxy;
+        keep = min_half(philox10(a, t, e.mb >> 26, kTagGrowHi, k0, k1)) <= hmax;
+      }
+      bhead += n;
+      const uint64_t kept = __ballot(keep);
+      if (kept) {
+        if (keep)
+          T.kring[(tail + __builtin_amdgcn_mbcnt_hi(
+                              (uint32_t)(kept >> 32),
+                              __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u))) &
+                  (kRing - 1u)] = e;
+        tail += (uint32_t)__popcll(kept);
+        if (tail - head >= (uint32_t)kWave) decide_round(kWave);
+      }
       wave_sync();
     };
     for (uint32_t ub = u_lo; ub < u_hi; ub += kWave) {
@@ -2057,12 +2082,10 @@ void k_sweep(BatchArgs A) {
         const uint32_t nq = uniform(nq_l);
         kept_w += nq;
         if (!run || nq == 0) continue;
-        uint32_t hmax = max(th.hi_face, max(th.hi_edge, th.hi_corner));
-        if (itab) hmax = max(hmax, max(R.ihi_max[0], max(R.ihi_max[1], R.ihi_max[2])));
         // steps 4 and 5 take the queue kQueueCap voxels at a time, in queue order
         for (uint32_t cb = 0; cb < nq; cb += kQueueCap) {
           const uint32_t nc = min(nq - cb, kQueueCap);
-          wave_sync();  // the previous chunk's queue, order and candidates are consumed
+          wave_sync();  // the previous chunk's queue is consumed
           {
             uint32_t p = pos - cb;  // (modulo 2^32: positions before the chunk wrap)
             for (uint32_t c = piece; c; c &= c - 1u, ++p)
@@ -2071,68 +2094,36 @@ void k_sweep(BatchArgs A) {
                                      (uint32_t)__builtin_ctz(c));
           }
           wave_sync();
-          // 4. void masks of the queue, then a counting sort of the queue by void count
-          // so that the lanes of one round draw similar numbers of blocks and slots
-          if (lane < 32u) T.hist[lane] = 0;
-          wave_sync();
-          for (uint32_t qi = lane; qi < nc; qi += kWave) {
-            const uint32_t ent = T.qo[qi];
-            const int i = (int)(ent >> 6), xl = (int)(ent & 63u);
-            const uint32_t vm = tile_void_mask(T, xl, i % kTileY, i / kTileY);
-            T.W[qi] = vm | (uint32_t)xl << 26;
-            T.row[qi] = (uint8_t)i;
-            atomicAdd(&T.hist[__builtin_popcount(vm)], 1u);
-          }
-          wave_sync();
-          {
-            const uint32_t hc = lane < 32u ? T.hist[lane] : 0u;
-            const uint32_t hin = wave_incl_sum(hc);
-            if (lane < 32u) T.hist[lane] = hin - hc;
-          }
-          wave_sync();
-          // (the queue has been read: its slots now take the order, heaviest first, so that
-          // a tile's last, partial round holds the lightest voxels)
-          for (uint32_t qi = lane; qi < nc; qi += kWave)
-            T.qo[nc - 1u - atomicAdd(&T.hist[__builtin_popcount(T.W[qi] & 0x3FFFFFFu)], 1u)] =
-                (uint16_t)(qi | (uint32_t)T.row[qi] << 10);
-          wave_sync();
-          // 5. draws and claims of every front voxel (Sec. 2.3 step 3, Eq. (1)), in two
-          // phases.  A: every block of high halves is drawn and kept only if one of its
-          // half-words is at or below the largest high-half threshold (no rank of it can
-          // pass otherwise); kept blocks go to the wavefront's ring.  B (decide_round above):
-          // 64 kept blocks at a time are drawn again, decided exactly and claimed.
+          // 4. each front voxel's void mask and its blocks of ranks (eight ranks a block);
+          // the blocks enter the wavefront's ring of phase A, block by block
           for (uint32_t kb = 0; kb < nc; kb += kWave) {
             const uint32_t k = kb + lane;
-            uint32_t nb = 0, a = 0, vx = 0, vy = 0, vz = 0, vm = 0;
+            uint32_t nb = 0, vx = 0, vy = 0, vz = 0, vm = 0;
             if (k < nc) {
-              const uint32_t qe = T.qo[k];
-              const uint32_t w = T.W[qe & 1023u];
-              const uint32_t i = qe >> 10;
-              vm = w & 0x3FFFFFFu;
+              const uint32_t ent = T.qo[k];
+              const uint32_t i = ent >> 6, xl = ent & 63u;
+              vm = tile_void_mask(T, (int)xl, (int)(i % kTileY), (int)(i / kTileY));
               const uint32_t nv = (uint32_t)__builtin_popcount(vm);
               nb = (nv + 7u) >> 3;
               draws_l += nv;
               blocks_l += nb;
-              vx = (uint32_t)x0 + (w >> 26);
+              vx = (uint32_t)x0 + xl;
               vy = (uint32_t)y0 + i % kTileY;
               vz = (uint32_t)z0 + i / kTileY;
-              a = vx + vy * (uint32_t)g.nx + vz * g.nxy;
             }
-            // the queue runs heaviest first, so the round's first lane has the most blocks
-            const uint32_t nbmax = uniform((uint32_t)__builtin_amdgcn_readfirstlane(nb));
-            for (uint32_t blk = 0; blk < nbmax; ++blk) {
-              bool keep = false;
-              if (blk < nb) keep = min_half(philox10(a, t, blk, kTagGrowHi, k0, k1)) <= hmax;
-              const uint64_t kept = __ballot(keep);
-              if (kept) {
-                if (keep)
-                  T.ring[(tail + __builtin_amdgcn_mbcnt_hi(
-                                     (uint32_t)(kept >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u))) &
-                         (kRing - 1u)] = RingEntry{vx, vy, vz, vm | blk << 26};
-                tail += (uint32_t)__popcll(kept);
-                if (tail - head >= (uint32_t)kWave) decide_round(kWave);
-              }
+            for (uint32_t blk = 0;; ++blk) {
+              const bool has = blk < nb;
+              const uint64_t bal = __ballot(has);
+              if (!bal) break;
+              if (has)
+                T.bring[(btail + __builtin_amdgcn_mbcnt_hi(
+                                     (uint32_t)(bal >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))) &
+                        (kRing - 1u)] = RingEntry{vx, vy, vz, vm | blk << 26};
+              btail += (uint32_t)__popcll(bal);
+              // 5. draws and claims (Sec. 2.3 step 3, Eq. (1)): phase A as soon as 64
+              // blocks wait, phase B as soon as 64 kept blocks wait
+              if (btail - bhead >= (uint32_t)kWave) reject_round(kWave);
             }
           }
         }
@@ -2143,7 +2134,9 @@ void k_sweep(BatchArgs A) {
       }
       taken += nb;
     }
-    if (tail != head) decide_round(tail - head);  // the share's last, partial round
+    // the share's last, partial rounds
+    if (btail != bhead) reject_round(btail - bhead);
+    if (tail != head) decide_round(tail - head);
     const uint32_t grown_w = wave_sum(grown);
     const uint32_t draws_w = wave_sum(draws_l), blocks_w = wave_sum(blocks_l);
     if (lane == 0) {
