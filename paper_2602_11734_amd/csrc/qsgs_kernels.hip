@@ -1702,6 +1702,13 @@ __device__ __forceinline__ uint32_t min_half(const U4& H) {
 
 // Front voxels of a tile queued at once (a tile with more takes them in chunks).
 constexpr uint32_t kQueueCap = 512;
+// The front compaction's pieces: kPiecesPerRow lanes per interior row, kPieceBits each.
+constexpr uint32_t kPieceBits = kTileRows * kTileX / kWave;
+constexpr uint32_t kPiecesPerRow = kTileX / kPieceBits;
+constexpr uint64_t kPieceMask = kPieceBits == 64 ? ~0ull : (1ull << (kPieceBits % 64)) - 1ull;
+static_assert(kTileX == 64 && kHaloRows <= kWave && kWave % kTileRows == 0 && kPieceBits <= 32,
+              "a tile row is one 64-bit word; a lane stages one halo row and compacts one piece");
+static_assert(kTileRows <= 32, "interior rows are 5-bit fields of the queue entries");
 // Entries of a wavefront's ring of kept blocks: fewer than 64 wait between rounds, and one
 // reject iteration adds at most 64.
 constexpr uint32_t kRing = 2 * kWave;
@@ -1713,9 +1720,9 @@ struct RingEntry {
   uint32_t mb;  // void mask | block << 26
 };
 
-// LDS image of one tile at the step's start.  Halo row h = hy + 6 hz (hy, hz in 0..5)
-// covers y = y0 - 1 + hy, z = z0 - 1 + hz; interior row i = jy + 4 jz is halo row
-// (jy + 1) + 6 (jz + 1).  Bit i of a row mask is voxel x0 + i.
+// LDS image of one tile at the step's start.  Halo row h = hy + (kTileY + 2) hz covers
+// y = y0 - 1 + hy, z = z0 - 1 + hz; interior row i = jy + kTileY jz is halo row
+// (jy + 1) + (kTileY + 2) (jz + 1).  Bit i of a row mask is voxel x0 + i.
 struct TileImage {
   // Halo row h as a 66-bit window of "in-domain candidate at the step's start" (in none
   // of S, the previous step's marks and the walls, except convertible cells of other
@@ -1987,11 +1994,11 @@ void k_sweep(BatchArgs A) {
         const int32_t y0 = (int32_t)(q1 - iz * tl.nty) * kTileY;
         const int32_t z0 = (int32_t)iz * kTileZ;
         wave_sync();  // the previous tile's image is no longer read
-        // 1. stage the tile and its one-voxel halo from the planes: lane h < 36 takes halo
-        // row h (y = y0 - 1 + h % 6, z = z0 - 1 + h / 6) and loads the row's words ix - 1,
-        // ix and ix + 1 of S, of the previous step's marks and of the walls; bit 63 of
-        // word ix - 1 is voxel x0 - 1 and bit 0 of word ix + 1 voxel x0 + 64.  A row outside
-        // the domain loads a clamped row and is masked.
+        // 1. stage the tile and its one-voxel halo from the planes: lane h < kHaloRows takes
+        // halo row h (y = y0 - 1 + h % (kTileY + 2), z = z0 - 1 + h / (kTileY + 2)) and loads
+        // the row's words ix - 1, ix and ix + 1 of S, of the previous step's marks and of the
+        // walls; bit 63 of word ix - 1 is voxel x0 - 1 and bit 0 of word ix + 1 voxel
+        // x0 + 64.  A row outside the domain loads a clamped row and is masked.
         const uint32_t ix = (uint32_t)x0 / (uint32_t)kTileX;
         const bool has_l = ix > 0, has_r = ix + 1u < ntx;  // (uniform)
         // voxels of word ix inside the domain in x (uniform)
@@ -2032,10 +2039,11 @@ void k_sweep(BatchArgs A) {
             T.win[lane][2] = (uint32_t)(vm >> 63) | vr << 1;
           }
         }
-        // interior row i < 16 is halo row (i % 4 + 1) + 6 (i / 4 + 1): its words come from
-        // that lane.  Solid = S | previous marks (literal rule: the previous marks not yet
-        // in S); the tile's owner folds the previous marks of its rows into S (a plain
-        // store: S only gains bits the readers already count as solid through the marks).
+        // interior row i < kTileRows is halo row (i % kTileY + 1) + (kTileY + 2) (i / kTileY
+        // + 1): its words come from that lane.  Solid = S | previous marks (literal rule:
+        // the previous marks not yet in S); the tile's owner folds the previous marks of its
+        // rows into S (a plain store: S only gains bits the readers already count as solid
+        // through the marks).
         {
           const uint32_t hi = (lane % kTileY + 1u) + (kTileY + 2u) * (lane / kTileY + 1u);
           const uint32_t src = lane < (uint32_t)kTileRows ? hi : lane;
@@ -2071,12 +2079,16 @@ void k_sweep(BatchArgs A) {
             }
           F = T.S[lane] & D;
         }
-        // 3. compact the front voxels into the queue: lane L takes the 16 bits
-        // 16 (L % 4) .. 16 (L % 4) + 15 of interior row L / 4 (in row-major order the
-        // lanes' pieces follow each other), so one wave prefix places every piece
-        const uint32_t frl = (uint32_t)__shfl((int)(uint32_t)F, (int)(lane >> 2), kWave);
-        const uint32_t frh = (uint32_t)__shfl((int)(uint32_t)(F >> 32), (int)(lane >> 2), kWave);
-        const uint32_t piece = (((lane & 2u) ? frh : frl) >> ((lane & 1u) * 16u)) & 0xFFFFu;
+        // 3. compact the front voxels into the queue: the 64 lanes split the tile's
+        // kTileRows x 64 front bits into pieces of kPieceBits, lane L taking bits
+        // kPieceBits (L % kPiecesPerRow) onwards of interior row L / kPiecesPerRow (in
+        // row-major order the lanes' pieces follow each other), so one wave prefix places
+        // every piece
+        const uint32_t prow = lane / kPiecesPerRow, poff = (lane % kPiecesPerRow) * kPieceBits;
+        const uint64_t Fr =
+            (uint64_t)(uint32_t)__shfl((int)(uint32_t)(F >> 32), (int)prow, kWave) << 32 |
+            (uint32_t)__shfl((int)(uint32_t)F, (int)prow, kWave);
+        const uint32_t piece = (uint32_t)((Fr >> poff) & kPieceMask);
         uint32_t nq_l;
         uint32_t pos = wave_prefix((uint32_t)__builtin_popcount(piece), &nq_l);
         const uint32_t nq = uniform(nq_l);
@@ -2090,8 +2102,7 @@ void k_sweep(BatchArgs A) {
             uint32_t p = pos - cb;  // (modulo 2^32: positions before the chunk wrap)
             for (uint32_t c = piece; c; c &= c - 1u, ++p)
               if (p < kQueueCap)
-                T.qo[p] = (uint16_t)((lane >> 2) << 6 | (lane & 3u) * 16u |
-                                     (uint32_t)__builtin_ctz(c));
+                T.qo[p] = (uint16_t)(prow << 6 | (poff + (uint32_t)__builtin_ctz(c)));
           }
           wave_sync();
           // 4. each front voxel's void mask and its blocks of ranks (eight ranks a block);
