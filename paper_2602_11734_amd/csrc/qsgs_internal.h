@@ -45,7 +45,7 @@ struct Buckets {
 
 // Tiles of the fused sweep: 64 x 4 x 4 voxels (one wavefront spans a tile row).
 // Tile (ix, iy, iz) has id ix + ntx (iy + nty iz).
-constexpr int kTileX = 64, kTileY = 4, kTileZ = 8;
+constexpr int kTileX = 64, kTileY = 8, kTileZ = 4;
 constexpr int kTileRows = kTileY * kTileZ;                // 16 interior rows
 constexpr int kHaloRows = (kTileY + 2) * (kTileZ + 2);    // 36 rows with the halo
 constexpr int kTileVoxels = kTileX * kTileRows;           // 1024
