@@ -43,12 +43,11 @@ struct Buckets {
   int32_t radius;
 };
 
-// Tiles of the fused sweep: 64 x 4 x 4 voxels (one wavefront spans a tile row).
-// Tile (ix, iy, iz) has id ix + ntx (iy + nty iz).
+// Tiles of the fused sweep: 64 x 8 x 4 voxels (x, y, z; a tile row is one 64-bit plane
+// word).  Tile (ix, iy, iz) has id ix + ntx (iy + nty iz).
 constexpr int kTileX = 64, kTileY = 8, kTileZ = 4;
-constexpr int kTileRows = kTileY * kTileZ;                // 16 interior rows
-constexpr int kHaloRows = (kTileY + 2) * (kTileZ + 2);    // 36 rows with the halo
-constexpr int kTileVoxels = kTileX * kTileRows;           // 1024
+constexpr int kTileRows = kTileY * kTileZ;                // 32 interior rows
+constexpr int kHaloRows = (kTileY + 2) * (kTileZ + 2);    // 60 rows with the halo
 
 struct Tiles {
   uint32_t ntx, nty, ntz, n;

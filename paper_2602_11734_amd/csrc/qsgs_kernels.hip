@@ -976,28 +976,24 @@ __global__ __launch_bounds__(kBlock) void k_rollback(uint8_t* grid, uint32_t n) 
 // with an in-domain void neighbour): a voxel of F_{t-1} keeps a void neighbour only
 // if it had one, since the void set only shrinks, and a voxel grown in step t-1
 // joins F_t iff it has one.  The list carried from step to step therefore names
-// 64 x 4 x 4 tiles rather than voxels: the list of step t holds every tile that
-// contains a voxel of F_t (a superset is harmless).  A pass stages each listed tile
-// with its one-voxel halo by coalesced row loads, finds F_t in the tile with 64-bit
-// row masks, compacts those voxels into an LDS queue (wavefront ballot + prefix),
-// and every queue entry draws for its void neighbours (Sec. 2.3 step 3, Eq. (1)) and
-// claims winners with a 32-bit atomicOr of the step's mark 2 + (t & 1).  A voxel of
-// F_{t+1} either was in F_t or was grown in step t, so the next list holds the tiles
-// that had a front voxel and the tiles that received a claim, each once: a tile's
-// stamp (1 + the pass whose list holds it) is raised with atomicMax and the first
-// raiser appends it.  Voxels grown in step t-1 still carry the previous mark; the
-// pass that owns their tile (listed, because a claim lists its tile) folds them to 1
-// with an atomicXor, so a byte equal to the current mark always means "grown in this
-// step", i.e. void at the step's start, and stale reads never change a decision.
+// 64 x 8 x 4 tiles rather than voxels: the list of step t, a bitmap over the tiles,
+// holds every tile that contains a voxel of F_t (a superset is harmless).  A pass
+// stages each listed tile with its one-voxel halo from the occupancy planes (S, the
+// marks of the previous step, the walls) by coalesced row loads, finds F_t in the tile
+// with 64-bit row masks, compacts those voxels into an LDS queue (wavefront prefix),
+// and every queued voxel draws for its void neighbours (Sec. 2.3 step 3, Eq. (1)),
+// claiming winners with a 32-bit atomicOr on the step's mark plane.  A voxel of
+// F_{t+1} either was in F_t or was grown in step t, so the next bitmap gets the tiles
+// that had a front voxel and the tiles that received a claim (an atomicOr each).  The
+// previous step's marks are folded into S by the wavefront that stages their tile
+// (listed, because a claim lists its tile); until then every reader counts them as
+// solid, so stale reads never change a decision.
 //
-// Output without contended atomics: every active realization r gets G_r workgroups;
-// workgroup k takes the k-th equal share of r's list entries (through the segment
-// table of the input plan) and appends the tiles it activates to the k-th part of
-// r's other list buffer with an LDS counter.  Its part's fill, its front count and
-// its growth count go to per-workgroup slots; a part that fills up spills into the
-// second half of the buffer through r's tail counter.  k_sweep_end then ends the step
-// for every realization (a6: log, count, status, Eq. (1) thresholds of the next step)
-// and builds the next plan.
+// Every realization with a pending pass gets G_r workgroups; workgroup k takes the k-th
+// equal share of r's listed tiles, in index order, from a descriptor written by the
+// previous step end.  Its front count, growth count, draws and blocks go to a
+// per-workgroup record; k_sweep_end then ends the step for every realization (log,
+// count, status, Eq. (1) thresholds of the next step) and writes the next shares.
 // ---------------------------------------------------------------------------
 
 // Bitwise or / sum of a value over the 64 lanes of the wavefront (every lane gets it;
@@ -1787,7 +1783,7 @@ size_t sweep_lds_bytes(uint32_t block) { return sizeof(TileImage) * (block / kWa
 // neither void nor sources.  kLiteral: a realization with the literal front rule takes
 // as sources, from its second step on, only the voxels grown in the previous step
 // (its marks that its tile's fold has not yet moved into S).
-// At most 80 VGPRs: six waves per SIMD, which the per-wave LDS images (4.1 KB each)
+// At most 80 VGPRs: six waves per SIMD, which the per-wave LDS images (6.1 KB each)
 // allow at the default 256-thread workgroup; the variants for other phases' cells need
 // more registers and run five waves per SIMD (96 VGPRs).
 template <bool kWalls, bool kLiteral>
