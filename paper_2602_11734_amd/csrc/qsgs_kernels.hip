@@ -1026,6 +1026,27 @@ __device__ __forceinline__ bool field_active(const Real& R) {
 
 // After seeding: S = the seeds (byte 1), M0 = M1 = 0, W = cells of other phases (bytes
 // above 1, multi-phase generation only).
+// Flags of the four bytes of v (bit k: byte k) equal to 1, resp. above 1: a byte test
+// without carries between bytes (each byte's low seven bits plus 0x7F stay below 0x100),
+// then the four flag bits (7, 15, 23, 31) gathered by one multiply whose partial
+// products land on distinct bits.
+__device__ __forceinline__ uint32_t bytes_eq1(uint32_t v) {
+  const uint32_t t = v ^ 0x01010101u;  // zero where the byte is 1
+  const uint32_t z = ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t | 0x7F7F7F7Fu);
+  return ((z >> 7) * 0x00204081u) >> 21 & 0xFu;
+}
+__device__ __forceinline__ uint32_t bytes_gt1(uint32_t v) {
+  const uint32_t u = v & 0xFEFEFEFEu;  // non-zero where the byte is above 1
+  const uint32_t nz = (((u & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | u) & 0x80808080u;
+  return ((nz >> 7) * 0x00204081u) >> 21 & 0xFu;
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// The four low bits of n as bytes 0 / 1 (the inverse of bytes_eq1 on 0 / 1 bytes).
+__device__ __forceinline__ uint32_t bits_to_bytes(uint32_t n) {
+  return (n * 0x00204081u) & 0x01010101u;
+}
+
 __global__ __launch_bounds__(kMaxBlock) void k_pack_planes(BatchArgs A) {
   const uint32_t lane = lane_id();
   for_each_chunk(A, kItemsPack, [&](uint32_t r, uint32_t i) {
@@ -1041,6 +1062,33 @@ __global__ __launch_bounds__(kMaxBlock) void k_pack_planes(BatchArgs A) {
     // the phases an interacting phase may convert (bit b: grid byte b)
     const InteractTable* it = (const InteractTable*)uniform64((uint64_t)R.itab);
     uint64_t s_mine = 0, w_mine = 0, x_mine = 0;
+    if ((nx & 15u) == 0u && ((uintptr_t)grid & 15u) == 0u && !it) {
+      // (uniform) rows of aligned 16-byte chunks: each lane packs its own word from four
+      // 16-byte loads
+      if (lane < nw) {
+        const uint32_t w = w0 + lane;
+        const uint32_t row = dntx.div(w);
+        const uint32_t x0 = (w - row * ntx) * (uint32_t)kTileX;
+        const uint32_t nc = min((uint32_t)kTileX, nx - x0) >> 4;  // chunks in the domain
+        typedef const __attribute__((address_space(1))) u32x4 g4;
+        g4* p = (g4*)(grid + (size_t)row * nx + x0);
+        u32x4 v[4];
+#pragma unroll
+        for (uint32_t c = 0; c < 4u; ++c) {
+          v[c] = u32x4{0u, 0u, 0u, 0u};
+          if (c < nc) v[c] = p[c];
+        }
+#pragma unroll
+        for (uint32_t c = 0; c < 4u; ++c) {
+          const uint32_t q[4] = {v[c].x, v[c].y, v[c].z, v[c].w};
+#pragma unroll
+          for (uint32_t k = 0; k < 4u; ++k) {
+            s_mine |= (uint64_t)bytes_eq1(q[k]) << (16u * c + 4u * k);
+            w_mine |= (uint64_t)bytes_gt1(q[k]) << (16u * c + 4u * k);
+          }
+        }
+      }
+    } else {
     for (uint32_t j = 0; j < nw; ++j) {
       const uint32_t w = w0 + j;
       const uint32_t row = dntx.div(w);
@@ -1055,6 +1103,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_pack_planes(BatchArgs A) {
         w_mine = wm;
         x_mine = xm;
       }
+    }
     }
     if (lane < nw) {
       uint64_t* P = (uint64_t*)uniform64((uint64_t)R.planes);
@@ -1084,6 +1133,32 @@ __global__ __launch_bounds__(kMaxBlock) void k_export_planes(BatchArgs A) {
         (__attribute__((address_space(1))) uint8_t*)uniform64((uint64_t)R.grid);
     const uint64_t* S = (const uint64_t*)uniform64((uint64_t)R.planes);
     const uint64_t mine = lane < nw ? S[w0 + lane] : 0ull;
+    if ((nx & 15u) == 0u && ((uintptr_t)grid & 15u) == 0u) {
+      // (uniform) rows of aligned 16-byte chunks: each lane writes its own word's bytes
+      // with four 16-byte stores
+      if (lane < nw) {
+        const uint32_t w = w0 + lane;
+        const uint32_t row = dntx.div(w);
+        const uint32_t x0 = (w - row * ntx) * (uint32_t)kTileX;
+        const uint32_t nc = min((uint32_t)kTileX, nx - x0) >> 4;
+        typedef __attribute__((address_space(1))) u32x4 g4;
+        g4* p = (g4*)(grid + (size_t)row * nx + x0);
+        for (uint32_t c = 0; c < nc; ++c) {
+          const uint32_t b16 = (uint32_t)(mine >> (16u * c));
+          u32x4 v = u32x4{bits_to_bytes(b16 & 0xFu), bits_to_bytes((b16 >> 4) & 0xFu),
+                          bits_to_bytes((b16 >> 8) & 0xFu), bits_to_bytes((b16 >> 12) & 0xFu)};
+          if (walls) {  // kSolid where S is set, the byte unchanged elsewhere
+            const u32x4 o = p[c];
+            v.x |= o.x & ~(v.x * 0xFFu);
+            v.y |= o.y & ~(v.y * 0xFFu);
+            v.z |= o.z & ~(v.z * 0xFFu);
+            v.w |= o.w & ~(v.w * 0xFFu);
+          }
+          p[c] = v;
+        }
+      }
+      return;
+    }
     const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
     for (uint32_t j = 0; j < nw; ++j) {
       const uint32_t w = w0 + j;
