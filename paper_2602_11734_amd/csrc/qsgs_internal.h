@@ -56,7 +56,7 @@ struct Tiles {
 
 // Occupancy bit planes of the fused sweep.  A plane holds one bit per voxel in rows of
 // ntx 64-bit words: word ix + ntx (y + ny z), bit b is voxel x = 64 ix + b (bits past
-// nx stay 0), so a 64 x 4 x 4 tile's interior is 16 whole words.
+// nx stay 0), so a 64 x 8 x 4 tile's interior is 32 whole words.
 //   S        solid at the start of the current step (the seeds, then every folded mark);
 //   M0, M1   claims of the steps with t even / odd; the pass of step t claims into
 //            M[t & 1] and folds the tile's bits of M[(t - 1) & 1] into S.  Solid at the

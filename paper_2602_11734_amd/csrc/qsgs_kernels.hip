@@ -1662,11 +1662,11 @@ __device__ __forceinline__ uint32_t sweep_block(uint32_t* __restrict__ mark32, u
                                                 uint32_t k1, const uint32_t* lds_key,
                                                 const int32_t* drow, const uint32_t* dhi,
                                                 uint32_t a, uint32_t rb, uint32_t xa, uint32_t t,
-                                                uint32_t blk, uint32_t m, DrawThresholds th,
-                                                uint32_t* passed, const Geometry& g,
+                                                uint32_t blk, uint32_t m, const U4 H,
+                                                DrawThresholds th, uint32_t* passed,
+                                                const Geometry& g,
                                                 const uint8_t* __restrict__ labels,
                                                 const InteractTable* __restrict__ itab) {
-  const U4 H = philox10(a, t, blk, kTagGrowHi, k0, k1);
   const bool inter = kInteract && itab != nullptr;
   // 1. every rank of the block against dhi of its direction, without branches: with
   // independent phases a high half below it passes and one equal to it ties; with
@@ -1784,10 +1784,10 @@ static_assert(kTileRows <= 32, "interior rows are 5-bit fields of the queue entr
 // reject iteration adds at most 64.
 constexpr uint32_t kRing = 2 * kWave;
 
-// A kept block, self-contained so that it can wait across tiles: the voxel, its void mask
-// (direction order) and the block index.
+// A block of ranks, self-contained so that it can wait across tiles: the voxel (its index
+// in the grid), its void mask (direction order) and the block index.
 struct RingEntry {
-  uint32_t x, y, z;
+  uint32_t a;
   uint32_t mb;  // void mask | block << 26
 };
 
@@ -1802,10 +1802,11 @@ struct TileImage {
   uint32_t win[kHaloRows][3];
   uint64_t S[kTileRows];     // solid (interior rows)
   uint16_t qo[kQueueCap];    // the queue of front voxels (interior row << 6 | x - x0)
-  // the wavefront's blocks to draw (phase A) and its kept blocks (phase B); both outlive
-  // the tile
-  RingEntry bring[kRing] __attribute__((aligned(16)));
-  RingEntry kring[kRing] __attribute__((aligned(16)));
+  // the wavefront's blocks to draw (phase A) and its kept blocks with their high-half
+  // Philox words (phase B); both outlive the tile
+  RingEntry bring[kRing] __attribute__((aligned(8)));
+  RingEntry kring[kRing] __attribute__((aligned(8)));
+  U4 kH[kRing] __attribute__((aligned(16)));
 };
 
 static_assert(kQueueCap <= 1024 && kQueueCap % kWave == 0, "queue slots are 10-bit fields");
@@ -1970,16 +1971,19 @@ void k_sweep(BatchArgs A) {
     auto decide_round = [&](uint32_t n) __attribute__((always_inline)) {  // the n <= 64 entries from head
       wave_sync();
       if (lane < n) {
-        const RingEntry e = T.kring[(head + lane) & (kRing - 1u)];
+        const uint32_t slot = (head + lane) & (kRing - 1u);
+        const RingEntry e = T.kring[slot];
+        const U4 H = T.kH[slot];
         const uint32_t blk = e.mb >> 26;
         const uint32_t m = drop_low_ranks(e.mb & 0x3FFFFFFu, 8u * blk);  // earlier blocks'
-        const uint32_t a = e.x + e.y * (uint32_t)g.nx + e.z * g.nxy;
-        const uint32_t rb = (e.y + (uint32_t)g.ny * e.z) * (2u * ntx);
+        const uint32_t q = g.div_nx.div(e.a);  // row y + ny z of the voxel
+        const uint32_t ex = e.a - q * (uint32_t)g.nx, ez = g.div_ny.div(q);
+        const uint32_t ey = q - ez * (uint32_t)g.ny;
         uint32_t passed = 0;
-        grown += sweep_block<kWalls>(mark32, k0, k1, s_key, s_drow, s_dhi, a, rb, e.x, t, blk,
-                                     m, th, &passed, g, labels, itab);
+        grown += sweep_block<kWalls>(mark32, k0, k1, s_key, s_drow, s_dhi, e.a, q * (2u * ntx),
+                                     ex, t, blk, m, H, th, &passed, g, labels, itab);
         if (!full) {  // (the all-tiles form lists every tile anyway)
-          const uint32_t xl = e.x % kTileX, jy = e.y % kTileY, jz = e.z % kTileZ;
+          const uint32_t xl = ex % kTileX, jy = ey % kTileY, jz = ez % kTileZ;
           const uint32_t leave = (xl == 0 ? kDxNeg : 0u) | (xl == kTileX - 1 ? kDxPos : 0u) |
                                  (jy == 0 ? kDyNeg : 0u) | (jy == kTileY - 1 ? kDyPos : 0u) |
                                  (jz == 0 ? kDzNeg : 0u) | (jz == kTileZ - 1 ? kDzPos : 0u);
@@ -1988,9 +1992,9 @@ void k_sweep(BatchArgs A) {
             const int d = __builtin_ctz(out);
             out &= out - 1u;
             // the target (in the domain: its claim was issued)
-            const uint32_t xn = e.x + (uint32_t)dir_field(kDirDX, d) - 1u,
-                           yn = e.y + (uint32_t)dir_field(kDirDY, d) - 1u,
-                           zn = e.z + (uint32_t)dir_field(kDirDZ, d) - 1u;
+            const uint32_t xn = ex + (uint32_t)dir_field(kDirDX, d) - 1u,
+                           yn = ey + (uint32_t)dir_field(kDirDY, d) - 1u,
+                           zn = ez + (uint32_t)dir_field(kDirDZ, d) - 1u;
             mark_tile(xn / kTileX + ntx * (yn / kTileY + tl.nty * (zn / kTileZ)));
           }
         }
@@ -2007,21 +2011,25 @@ void k_sweep(BatchArgs A) {
     uint32_t bhead = 0, btail = 0;  // (uniform)
     auto reject_round = [&](uint32_t n) __attribute__((always_inline)) {  // the n <= 64 entries from bhead
       wave_sync();
-      RingEntry e{0u, 0u, 0u, 0u};
+      RingEntry e{0u, 0u};
+      U4 H{0u, 0u, 0u, 0u};
       bool keep = false;
       if (lane < n) {
         e = T.bring[(bhead + lane) & (kRing - 1u)];
-        const uint32_t a = e.x + e.y * (uint32_t)g.nx + e.z * g.nxy;
-        keep = min_half(philox10(a, t, e.mb >> 26, kTagGrowHi, k0, k1)) <= hmax;
+        H = philox10(e.a, t, e.mb >> 26, kTagGrowHi, k0, k1);
+        keep = min_half(H) <= hmax;
       }
       bhead += n;
       const uint64_t kept = __ballot(keep);
       if (kept) {
-        if (keep)
-          T.kring[(tail + __builtin_amdgcn_mbcnt_hi(
-                              (uint32_t)(kept >> 32),
-                              __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u))) &
-                  (kRing - 1u)] = e;
+        if (keep) {  // (phase B reads the block's words instead of drawing them again)
+          const uint32_t slot = (tail + __builtin_amdgcn_mbcnt_hi(
+                                            (uint32_t)(kept >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)kept, 0u))) &
+                                (kRing - 1u);
+          T.kring[slot] = e;
+          T.kH[slot] = H;
+        }
         tail += (uint32_t)__popcll(kept);
         if (tail - head >= (uint32_t)kWave) decide_round(kWave);
       }
@@ -2180,7 +2188,7 @@ void k_sweep(BatchArgs A) {
           // the blocks enter the wavefront's ring of phase A, block by block
           for (uint32_t kb = 0; kb < nc; kb += kWave) {
             const uint32_t k = kb + lane;
-            uint32_t nb = 0, vx = 0, vy = 0, vz = 0, vm = 0;
+            uint32_t nb = 0, va = 0, vm = 0;
             if (k < nc) {
               const uint32_t ent = T.qo[k];
               const uint32_t i = ent >> 6, xl = ent & 63u;
@@ -2189,9 +2197,8 @@ void k_sweep(BatchArgs A) {
               nb = (nv + 7u) >> 3;
               draws_l += nv;
               blocks_l += nb;
-              vx = (uint32_t)x0 + xl;
-              vy = (uint32_t)y0 + i % kTileY;
-              vz = (uint32_t)z0 + i / kTileY;
+              va = ((uint32_t)x0 + xl) + ((uint32_t)y0 + i % kTileY) * (uint32_t)g.nx +
+                   ((uint32_t)z0 + i / kTileY) * g.nxy;
             }
             for (uint32_t blk = 0;; ++blk) {
               const bool has = blk < nb;
@@ -2201,7 +2208,7 @@ void k_sweep(BatchArgs A) {
                 T.bring[(btail + __builtin_amdgcn_mbcnt_hi(
                                      (uint32_t)(bal >> 32),
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))) &
-                        (kRing - 1u)] = RingEntry{vx, vy, vz, vm | blk << 26};
+                        (kRing - 1u)] = RingEntry{va, vm | blk << 26};
               btail += (uint32_t)__popcll(bal);
               // 5. draws and claims (Sec. 2.3 step 3, Eq. (1)): phase A as soon as 64
               // blocks wait, phase B as soon as 64 kept blocks wait
