@@ -144,8 +144,10 @@ def many_small_cases(n: int = 80, seed: int = 2602) -> list[Case]:
 
 
 def small_cases() -> list[Case]:
-    """Small and ragged grids (several 256-entry tiles, odd extents) and the method's
-    degenerate cases, for element-by-element parity with the oracle."""
+    """Small and ragged grids (several sweep tiles, odd extents) and the method's
+    degenerate cases, for element-by-element parity with the oracle.  The last one holds
+    fronts of about 1 200 voxels per 64 x 8 x 4 tile for five steps, more than one chunk of the
+    sweep's 512-voxel queue."""
     g = (0.02, 0.005, 0.00125)
     return [
         Case("ragged_37x23x19", (37, 23, 19), 0.65, 0.01, g, 3, 7),
@@ -166,6 +168,7 @@ def small_cases() -> list[Case]:
         Case("single_voxel", (1, 1, 1), 1.0, 1.0, g, 0, 23),
         Case("key_high_bits", (45, 41, 39), 0.7, 0.006, g, 6, 0xFFFF_FFFF_0000_0001),
         Case("two_voxels", (2, 1, 1), 1.0, 0.5, (0.5, 0.5, 0.5), 0, 24),
+        Case("dense_front_64x64x32", (64, 64, 32), 0.97, 0.6, (0.02, 0.01, 0.002), 0, 25),
     ]
 
 
