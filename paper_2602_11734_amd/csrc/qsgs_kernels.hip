@@ -2017,7 +2017,14 @@ void k_sweep(BatchArgs A) {
       if (lane < n) {
         e = T.bring[(bhead + lane) & (kRing - 1u)];
         H = philox10(e.a, t, e.mb >> 26, kTagGrowHi, k0, k1);
-        keep = min_half(H) <= hmax;
+        // only the block's ranks count: slots past the voxel's last void are masked
+        const uint32_t rk = min(8u, (uint32_t)__builtin_popcount(e.mb & 0x3FFFFFFu) - 8u * (e.mb >> 26));
+        U4 Hm = H;
+        Hm.x |= rk >= 2u ? 0u : (rk == 1u ? 0xFFFF0000u : ~0u);
+        Hm.y |= rk >= 4u ? 0u : (rk == 3u ? 0xFFFF0000u : ~0u);
+        Hm.z |= rk >= 6u ? 0u : (rk == 5u ? 0xFFFF0000u : ~0u);
+        Hm.w |= rk >= 8u ? 0u : (rk == 7u ? 0xFFFF0000u : ~0u);
+        keep = min_half(Hm) <= hmax;
       }
       bhead += n;
       const uint64_t kept = __ballot(keep);
