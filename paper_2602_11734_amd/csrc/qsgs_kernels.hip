@@ -1860,8 +1860,8 @@ size_t sweep_lds_bytes(uint32_t block) { return sizeof(TileImage) * (block / kWa
 // as sources, from its second step on, only the voxels grown in the previous step
 // (its marks that its tile's fold has not yet moved into S).
 // At most 80 VGPRs: six waves per SIMD, which the per-wave LDS images (6.1 KB each)
-// allow at the default 256-thread workgroup; the variants for other phases' cells need
-// more registers and run five waves per SIMD (96 VGPRs).
+// allow at the default 256-thread workgroup; the variants for other phases' cells may
+// take up to 96 (five waves per SIMD; the resident grid follows what they need).
 template <bool kWalls, bool kLiteral>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(kWalls ? 5 : 6)))
 void k_sweep(BatchArgs A) {
