@@ -1689,6 +1689,12 @@ __device__ __forceinline__ uint32_t sweep_block(uint32_t* __restrict__ mark32, u
     const uint32_t lf = th.lo_face, le = th.lo_edge, lc = th.lo_corner;
     bool have_lo = false;
     U4 L{0, 0, 0, 0};
+    if (!inter) {  // every slow rank is a tie: the low-half block is needed, drawn once here
+      const uint32_t kl0 = *(const volatile l_u32*)&lds_key[0];
+      const uint32_t kl1 = *(const volatile l_u32*)&lds_key[1];
+      L = philox10(a, t, blk, kTagGrowLo, kl0, kl1);
+      have_lo = true;
+    }
     uint32_t m2 = m;
 #pragma unroll
     for (int sl = 0; sl < 8; ++sl) {
