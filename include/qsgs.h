@@ -337,16 +337,18 @@ void qsgs_server_destroy(qsgs_server* server);
  * issued between two host reads of the loop state (`steps_per_sync`, 0 = adaptive).
  * The shape never changes a result: every output is a function of the inputs only.
  * grow_grid = 0 sizes the growth sweep to one round of the workgroups the device holds
- * at once (1280 of 256 threads on an MI355X: 256 compute units x 5); the step API's
- * growth kernel then takes 2048.  `graphs` = 1 issues the passes of the whole-generation
+ * at once (1536 of 256 threads on an MI355X: 256 compute units x 6; 768 of 512 threads);
+ * the step API's growth kernel then takes 2048.  `graphs` = 1 issues the passes of the
+ * whole-generation
  * calls and of server ticks as HIP graph launches of captured chunks of 16, 8, 4, 2 or 1
  * passes (kernel nodes only; the executable graphs are cached per launch configuration
  * and workspace for the life of the process, at most 64 of them, and reused by later
  * calls with the same configuration); 0 launches every kernel on its own.  Graphs are
  * never used while kernel timing is enabled or by qsgs_generate_noalloc.
  * qsgs_set_tuning applies process-wide to calls that start afterwards (NULL restores the
- * defaults: 256 threads; growth grid 0, 2048 for prune and seeding; adaptive; graphs
- * on); QSGS_ERR_INVALID for a bad shape. */
+ * defaults: 256 threads, and 512 for the growth sweep of a whole-generation call on one
+ * realization; growth grid 0, 2048 for prune and seeding; adaptive; graphs on); a tuning
+ * set here applies as given to every call.  QSGS_ERR_INVALID for a bad shape. */
 typedef struct {
   int32_t grow_block, grow_grid;
   int32_t prune_block, prune_grid;

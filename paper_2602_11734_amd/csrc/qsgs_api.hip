@@ -88,7 +88,7 @@ qsgs_status generate_impl(int32_t count, const qsgs_dims* dims, const qsgs_param
   if (ws_bytes < G.total)
     return fail(QSGS_ERR_WORKSPACE, "workspace needs %zu bytes, got %zu", G.total, ws_bytes);
   Engine E;
-  E.bind(ws, G.P, (size_t)count, s, walls);
+  E.bind(ws, G.P, (size_t)count, s, walls, count == 1 ? 2u * kBlock : 0u);
   E.no_events = no_alloc || async;
   E.async = async;
   E.stage = (no_alloc || async) ? nullptr
@@ -532,6 +532,7 @@ qsgs_status qsgs_set_tuning(const qsgs_tuning* t) {
     if (t->graphs != 0 && t->graphs != 1) return fail(QSGS_ERR_INVALID, "graphs must be 0 or 1");
     n.graphs = t->graphs != 0;
     n.grow_block = blocks[0];
+    n.grow_block_auto = false;
     n.prune_block = blocks[1];
     n.seed_block = blocks[2];
     n.grow_grid = grids[0];

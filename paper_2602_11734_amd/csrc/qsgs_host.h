@@ -310,6 +310,9 @@ inline char* thread_pinned_stage(size_t bytes) {
 // to 512; grid = workgroups, a multiple of 8) and the steps issued between host reads.
 struct Tuning {
   uint32_t grow_block = kBlock, grow_grid = 0;  // 0: one round of resident sweep workgroups
+  // the whole-generation calls on one realization take 512-thread sweep workgroups (eight
+  // waves share a share's tiles; measured faster there, slower for batches of many)
+  bool grow_block_auto = true;
   uint32_t prune_block = kBlock, prune_grid = 2048;
   uint32_t seed_block = kBlock, seed_grid = 2048;
   int32_t steps_per_sync = 0;  // 0: adaptive
@@ -488,13 +491,15 @@ struct Engine {
   char* st_dn_live() { return st_dn_reals() + align_up(sizeof(Real) * reals.size()); }
 
   // Binds the engine to a persistent region of `count` records at `base`.
-  // walls: the records' grids may hold other phases' cells (the sweep variants for them).
+  // walls: the records' grids may hold other phases' cells (the sweep variants for them);
+  // auto_grow_block: the sweep workgroup size when the tuning leaves it to the call.
   void bind(void* base, const PersistLayout& L, size_t count, hipStream_t stream,
-            bool walls = false) {
+            bool walls = false, uint32_t auto_grow_block = 0) {
     ws = base;
     P = L;
     s = stream;
     tune = current_tuning();
+    if (tune.grow_block_auto && auto_grow_block) tune.grow_block = auto_grow_block;
     reals.assign(count, Real{});
     args = BatchArgs{};
     args.reals = at<Real>(base, L.reals);
