@@ -460,6 +460,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy kernel over BYTES bytes three times "
                          "(the reference kernel for scaling HBM byte counters)")
+    ap.add_argument("--step-api-only", action="store_true",
+                    help="only run the voxel-list step API against qsgs_generate on the 400^3 "
+                         "porosity-0.20 realization (for profiling k_grow and k_prune)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -470,7 +473,8 @@ def main():
 
     # the CPU leg first, before anything touches the GPU (its workers are forks)
     cpu = None
-    if not args.no_cpu_baseline and not args.copy_calibration and not args.alu_calibration:
+    if not (args.no_cpu_baseline or args.copy_calibration or args.alu_calibration
+            or args.step_api_only):
         cpu = cpu_baseline(workloads.config3(), edge=args.cpu_edge)
 
     import torch
@@ -487,6 +491,9 @@ def main():
         print(json.dumps({"alu_lane_ops_per_s_T_by_waves_per_simd": rates,
                           "peak_T": ALU_PEAK_TOPS,
                           "best_frac_of_peak": max(rates.values()) / ALU_PEAK_TOPS}))
+        return
+    if args.step_api_only:
+        print(json.dumps(voxel_list_step_api(q, torch, workloads.config3()[1])))
         return
     if args.copy_calibration:
         # an elementwise kernel that reads and writes BYTES bytes (a DMA copy would
